@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs: gas level tables, laser fields, initial states.
+
+This module holds no arithmetic of the ionization method itself (no rates, no
+chain solution, no window logic).  It only draws inputs, and both the HIP path
+and the CPU oracle consume what it returns.
+
+The paper's own workload (krypton in a 9.2 um CO2 laser pulse, Sec. 3 and
+Sec. 4) needs measured ionization potentials and the electron structure of its
+Fig. 1, which are not reproduced here.  Synthetic level tables with the same
+structure stand in for them: Z ionization potentials drawn log-uniformly in a
+range and sorted ascending (no rejection of near-equal values, so near-equal
+rates occur), with orbital numbers assigned outermost shell first.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+C_LIGHT = 2.99792458e8  # m/s
+
+#: projection code meaning "average the rate over m = -l..l"
+M_AVERAGE = -1
+
+# Shell sequences, outermost first: (l, number of electrons).
+_SHELLS = {
+    7: [(1, 5), (0, 2)],
+    18: [(1, 6), (0, 2), (1, 6), (0, 2), (0, 2)],
+    36: [(1, 6), (0, 2), (2, 10), (1, 6), (0, 2), (1, 6), (0, 2), (0, 2)],
+    54: [(1, 6), (0, 2), (2, 10), (1, 6), (0, 2), (2, 10), (1, 6), (0, 2), (1, 6), (0, 2),
+         (0, 2)],
+}
+_U_RANGE = {1: (13.6, 13.6), 7: (10.0, 700.0), 18: (15.0, 4500.0), 36: (14.0, 18000.0),
+            54: (12.0, 41000.0)}
+_M_AVG = {36}
+
+
+@dataclass
+class GasTable:
+    """U[k] (eV) ionizes charge k -> k+1 with orbital number l[k] and projection
+    code m[k] (|m| >= 0, or M_AVERAGE)."""
+    name: str
+    U: np.ndarray
+    l: np.ndarray
+    m: np.ndarray
+
+    @property
+    def Z(self) -> int:
+        return int(self.U.shape[0])
+
+
+def synthetic_gas(Z: int) -> GasTable:
+    """Level table of the synthetic gas with Z levels (Z in 1, 7, 18, 36, 54)."""
+    if Z == 1:
+        return GasTable("H-like", np.array([13.6]), np.zeros(1, np.int8), np.zeros(1, np.int8))
+    lo, hi = _U_RANGE[Z]
+    rng = np.random.default_rng(100 + Z)
+    U = np.sort(np.exp(rng.uniform(math.log(lo), math.log(hi), size=Z)))
+    l = np.concatenate([np.full(n, ll, np.int8) for ll, n in _SHELLS[Z]])
+    assert l.shape == (Z,)
+    m = np.full(Z, M_AVERAGE if Z in _M_AVG else 0, np.int8)
+    return GasTable(f"synthetic-Z{Z}", U, l, m)
+
+
+def loguniform_field(n: int, lo: float, hi: float, seed: int) -> np.ndarray:
+    """n field values log-uniform in [lo, hi] GV/m (float64)."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(math.log(lo), math.log(hi), size=n))
+
+
+@dataclass
+class LaserMesh:
+    """Gaussian laser pulse on a uniform mesh, cell centres, z fastest.
+    E(x,z,t) = E0 exp(-(r^2/w0^2 + (z - c t)^2/(c tau)^2)) cos(k0 z - w0 t)."""
+    shape: tuple          # (nx, nz) or (nx, ny, nz)
+    dx_um: float
+    dz_um: float
+    E0: float = 3000.0    # GV/m
+    lam_um: float = 0.8
+    w0_um: float = 20.0
+    tau_fs: float = 30.0
+    steps: int = 2000
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(self.shape))
+
+    @property
+    def dt(self) -> float:
+        """0.05 laser periods, in s."""
+        return 0.05 * self.lam_um * 1e-6 / C_LIGHT
+
+    def axes_um(self):
+        nz = self.shape[-1]
+        z = (np.arange(nz) + 0.5) * self.dz_um
+        trans = []
+        for n in self.shape[:-1]:
+            trans.append((np.arange(n) + 0.5 - n / 2) * self.dx_um)
+        return trans, z
+
+    def field_at(self, step: int, idx, dtype=np.float64) -> np.ndarray:
+        """E at the flat cell indices idx at t = step * dt (float64 arithmetic,
+        same formula and operation order as field())."""
+        idx = np.asarray(idx, dtype=np.int64)
+        trans, z = self.axes_um()
+        coords = np.unravel_index(idx, self.shape)
+        t = step * self.dt
+        ct_um = C_LIGHT * t * 1e6
+        k0 = 2 * math.pi / self.lam_um
+        om_t = 2 * math.pi * C_LIGHT * t / (self.lam_um * 1e-6)
+        r2 = np.zeros(idx.shape)
+        for i, a in enumerate(trans):
+            r2 = r2 + a[coords[i]] ** 2
+        ctau = C_LIGHT * self.tau_fs * 1e-15 * 1e6
+        zz = z[coords[-1]]
+        env_z = np.exp(-((zz - ct_um) / ctau) ** 2) * np.cos(k0 * zz - om_t)
+        return (self.E0 * np.exp(-r2 / self.w0_um ** 2) * env_z).astype(dtype)
+
+    def field(self, step: int, dtype=np.float64) -> np.ndarray:
+        """Flat E over all cells at t = step * dt (float64 arithmetic)."""
+        trans, z = self.axes_um()
+        t = step * self.dt
+        ct_um = C_LIGHT * t * 1e6
+        k0 = 2 * math.pi / self.lam_um
+        om_t = 2 * math.pi * C_LIGHT * t / (self.lam_um * 1e-6)
+        r2 = np.zeros([len(a) for a in trans])
+        for i, a in enumerate(trans):
+            shp = [1] * len(trans)
+            shp[i] = a.size
+            r2 = r2 + (a.reshape(shp)) ** 2
+        ctau = C_LIGHT * self.tau_fs * 1e-15 * 1e6
+        env_z = np.exp(-((z - ct_um) / ctau) ** 2) * np.cos(k0 * z - om_t)
+        E = self.E0 * np.exp(-r2 / self.w0_um ** 2)[..., None] * env_z
+        return E.reshape(-1).astype(dtype)
+
+
+def mesh_2d() -> LaserMesh:
+    """1024 x 1024 2D mesh, 0.08 um cells, E0 = 3000 GV/m, 2000 steps."""
+    return LaserMesh((1024, 1024), 0.08, 0.08, E0=3000.0, steps=2000)
+
+
+def mesh_3d() -> LaserMesh:
+    """256 x 256 x 512 3D mesh, 0.32/0.32/0.08 um cells, E0 = 5000 GV/m, 500 steps."""
+    return LaserMesh((256, 256, 512), 0.32, 0.08, E0=5000.0, steps=500)
+
+
+def neutral_state(ncells: int, rows: int, dtype=np.float64):
+    """All population in the neutral level: pops[rows][n] with row 0 = 1, lo = 0."""
+    pops = np.zeros((rows, ncells), dtype=dtype)
+    pops[0] = 1.0
+    return pops, np.zeros(ncells, np.uint8)
+
+
+def random_window_state(ncells: int, Z: int, w: int, seed: int, dtype=np.float64,
+                        eps: float = 1e-8):
+    """Random normalized window states with varied lowest level lo in [0, Z]:
+    compact pops[(w+1)][n].  Slots beyond Z are zero.  Some slots are set
+    exactly to zero or below eps so that shifts occur."""
+    rng = np.random.default_rng(seed)
+    lo = rng.integers(0, Z + 1, size=ncells).astype(np.uint8)
+    raw = rng.exponential(size=(w + 1, ncells))
+    kill = rng.random((w + 1, ncells))
+    raw[kill < 0.2] = 0.0
+    raw[(kill >= 0.2) & (kill < 0.3)] *= eps * 0.1
+    slot_level = lo[None, :].astype(np.int64) + np.arange(w + 1)[:, None]
+    raw[slot_level > Z] = 0.0
+    s = raw.sum(axis=0)
+    empty = s == 0
+    raw[0, empty] = 1.0
+    s[empty] = 1.0
+    return (raw / s).astype(dtype), lo
