@@ -26,6 +26,8 @@
  *
  * Readings of the paper that this file takes (silent or garbled passages):
  *   - E_L = |E|; E_L == 0 gives W = 0 (limit of the exp factor of Eq. (1)).
+ *   - A rate whose exp factor exp(-2 E_a (Q/n*)^3 / (3 E_L)) is below the
+ *     smallest normal double is taken as zero (such rates are < 1e-200/s).
  *   - Level k (charge k -> k+1) uses Q = k + 1 and the k-th listed ionization
  *     potential U[k]; n* = Q sqrt(U_H / U[k]) (Sec. 2, text after Eq. (1)).
  *   - "e" in (2e/n*)^(2n*) is Euler's number.
@@ -34,6 +36,7 @@
  *   - The residual population at a window shift is folded upward, which
  *     conserves the total exactly.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -68,8 +71,10 @@ double orc_rate_lm(double U, int Q, int l, int am, double E, const double *const
     const double f_q2 = (double)Q * Q / (2.0 * ns * ns);
     const double f_stirling = pow(2.0 * M_E / ns, 2.0 * ns);
     const double f_tunnel = exp(-2.0 * E_a / (3.0 * EL) * pow((double)Q / ns, 3.0));
-    /* exp factor underflowed: the product is zero to within subnormals */
-    if (f_tunnel == 0.0) return 0.0;
+    /* Tunnelling factor below the normal range: the rate is below ~1e-200/s
+     * (W dt < 1e-215 for fs steps) and is taken as zero; this also keeps the
+     * product from inheriting the lost precision of a subnormal factor. */
+    if (f_tunnel < DBL_MIN) return 0.0;
     const double f_lm = (2.0 * l + 1.0) * orc_fact(l + am) /
                         (2.0 * M_PI * ns * pow(2.0, am) * orc_fact(am) * orc_fact(l - am));
     const double f_pow = pow(2.0 * E_a * Q3 / (EL * n3), 2.0 * ns - am - 1.0);
