@@ -1,0 +1,223 @@
+"""Python binding of libadkion (ctypes over the C ABI in include/adkion.h).
+
+Argument marshalling only: every step of the ionization path runs in the HIP
+kernels of libadkion.so.  Device arrays are torch tensors on a ROCm device
+(torch is used for device memory and streams).  If the library is not built
+the first call raises; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadkion.so")
+
+ADK_OK, ADK_EINVAL, ADK_ERANGE, ADK_EDEVICE, ADK_ENOMEM = 0, -1, -2, -3, -4
+ADK_F64, ADK_MIXED = 0, 1
+ADK_LAYOUT_COMPACT, ADK_LAYOUT_FULL = 0, 1
+ADK_MAX_Z, ADK_MAX_W, ADK_M_AVERAGE = 64, 8, -1
+
+#: every function the header declares (checked by the CPU test suite)
+EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "adk_gas_destroy",
+           "adk_gas_levels", "adk_rates", "adk_chain_advance", "ionize_step")
+
+
+class AdkError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_text(status)} ({status})")
+
+
+class _Consts(ctypes.Structure):
+    _fields_ = [("omega_a", ctypes.c_double), ("E_a", ctypes.c_double), ("U_H", ctypes.c_double)]
+
+
+class _GasDesc(ctypes.Structure):
+    _fields_ = [("Z", ctypes.c_int32), ("U_eV", ctypes.POINTER(ctypes.c_double)),
+                ("l", ctypes.POINTER(ctypes.c_int8)), ("m", ctypes.POINTER(ctypes.c_int8))]
+
+
+class _Window(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("eps", ctypes.c_double), ("layout", ctypes.c_int),
+                ("prec", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libadkion.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2202_10647_amd.build` "
+                           "(no fallback path exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.adk_version.restype = ctypes.c_char_p
+    L.adk_version.argtypes = []
+    L.adk_strerror.restype = ctypes.c_char_p
+    L.adk_strerror.argtypes = [ctypes.c_int]
+    L.adk_gas_coeffs.restype = ctypes.c_int
+    L.adk_gas_coeffs.argtypes = [ctypes.POINTER(_GasDesc), ctypes.POINTER(_Consts), ctypes.POINTER(dbl)]
+    L.adk_gas_create.restype = ctypes.c_int
+    L.adk_gas_create.argtypes = [ctypes.POINTER(_GasDesc), ctypes.POINTER(_Consts), ctypes.POINTER(vp)]
+    L.adk_gas_destroy.restype = ctypes.c_int
+    L.adk_gas_destroy.argtypes = [vp]
+    L.adk_gas_levels.restype = ctypes.c_int
+    L.adk_gas_levels.argtypes = [vp]
+    L.adk_rates.restype = ctypes.c_int
+    L.adk_rates.argtypes = [vp, vp, i64, i32, i32, vp, ctypes.c_int, vp]
+    L.adk_chain_advance.restype = ctypes.c_int
+    L.adk_chain_advance.argtypes = [i32, vp, i64, dbl, vp, ctypes.c_int, vp]
+    L.ionize_step.restype = ctypes.c_int
+    L.ionize_step.argtypes = [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp]
+    _lib = L
+    return L
+
+
+def status_text(status: int) -> str:
+    try:
+        return lib().adk_strerror(int(status)).decode()
+    except RuntimeError:
+        return "library not built"
+
+
+def version() -> str:
+    return lib().adk_version().decode()
+
+
+def _check(st: int, what: str):
+    if st != ADK_OK:
+        raise AdkError(st, what)
+
+
+def _desc(U, l, m):
+    U = np.ascontiguousarray(np.asarray(U, dtype=np.float64))
+    l = np.ascontiguousarray(np.asarray(l, dtype=np.int8))
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.int8))
+    d = _GasDesc(int(U.size), U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                 l.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                 m.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    return d, (U, l, m)
+
+
+def _consts(consts):
+    if consts is None:
+        return None
+    return ctypes.pointer(_Consts(*[float(c) for c in consts]))
+
+
+def gas_coeffs(U, l, m, consts=None) -> np.ndarray:
+    """Host-only log-domain coefficient table [Z][8] (A, alpha, B, c1, c2, c3, 0, 0)."""
+    d, keep = _desc(U, l, m)
+    out = np.zeros((max(d.Z, 1), 8), dtype=np.float64)
+    st = lib().adk_gas_coeffs(ctypes.byref(d), _consts(consts),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(st, "adk_gas_coeffs")
+    return out[: d.Z]
+
+
+class Gas:
+    """A gas level table uploaded to the current device (owned by the library)."""
+
+    def __init__(self, U, l, m, consts=None):
+        d, keep = _desc(U, l, m)
+        h = ctypes.c_void_p()
+        st = lib().adk_gas_create(ctypes.byref(d), _consts(consts), ctypes.byref(h))
+        _check(st, "adk_gas_create")
+        self._h = h
+        self.Z = int(d.Z)
+
+    @classmethod
+    def from_table(cls, table, consts=None):
+        return cls(table.U, table.l, table.m, consts)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().adk_gas_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _prec_of(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return ADK_F64
+    if t.dtype == torch.float32:
+        return ADK_MIXED
+    raise TypeError(f"unsupported dtype {t.dtype}: float64 (ADK_F64) or float32 (ADK_MIXED)")
+
+
+def _dev(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def rates(gas: Gas, E, k0: int = 0, nk: Optional[int] = None, out=None, stream=None):
+    """W[nk][n] (1/s) of levels k0..k0+nk-1 at fields E[n] (float64 or float32)."""
+    import torch
+    if nk is None:
+        nk = gas.Z - k0
+    n = E.numel()
+    if out is None:
+        out = torch.empty((nk, n), dtype=E.dtype, device=E.device)
+    st = lib().adk_rates(gas.handle, _dev(E, "E"), n, k0, nk, _dev(out, "W_out"), _prec_of(E),
+                         _stream(stream))
+    _check(st, "adk_rates")
+    return out
+
+
+def chain_advance(W, dt: float, pops, stream=None):
+    """In place: pops[(w+1)][n] <- expm(dt A(W)) pops with rates W[w][n] (1/s)."""
+    w = W.shape[0]
+    n = pops.shape[1] if pops.dim() == 2 else 0
+    if pops.dtype != W.dtype or pops.shape[0] != w + 1 or W.shape[1] != n:
+        raise ValueError("W must be [w][n] and pops [(w+1)][n] of the same dtype")
+    st = lib().adk_chain_advance(w, _dev(W, "W"), n, float(dt), _dev(pops, "pops"), _prec_of(pops),
+                                 _stream(stream))
+    _check(st, "adk_chain_advance")
+    return pops
+
+
+def ionize_step(gas: Gas, E, dt: float, pops, lo, w: int, eps: float = 1e-8, layout: str = "compact",
+                stream=None):
+    """One ionization step, in place on pops and lo (see include/adkion.h).
+
+    float64 tensors select ADK_F64, float32 tensors ADK_MIXED."""
+    import torch
+    lay = {"compact": ADK_LAYOUT_COMPACT, "full": ADK_LAYOUT_FULL}[layout]
+    n = E.numel()
+    rows = (w + 1) if lay == ADK_LAYOUT_COMPACT else (gas.Z + 1)
+    if pops.dtype != E.dtype or tuple(pops.shape) != (rows, n):
+        raise ValueError(f"pops must be [{rows}][{n}] of dtype {E.dtype}, got {tuple(pops.shape)} {pops.dtype}")
+    if lo.dtype != torch.uint8 or lo.numel() != n:
+        raise ValueError("lo must be uint8[ncells]")
+    win = _Window(int(w), float(eps), lay, _prec_of(E))
+    st = lib().ionize_step(gas.handle, _dev(E, "E"), n, float(dt), _dev(pops, "pops"), _dev(lo, "lo"),
+                           ctypes.byref(win), _stream(stream))
+    _check(st, "ionize_step")
+    return pops, lo

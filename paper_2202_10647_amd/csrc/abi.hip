@@ -1,0 +1,162 @@
+// C-ABI entry points of libadkion: host validation (before any device call),
+// gas objects, and dispatch to the per-(precision, window) kernel
+// instantiations compiled from inst.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "kernels.hpp"
+
+namespace adk {
+
+// ---------------------------------------------------------------------------
+static int g_num_cu = 0;
+
+int grid_for(int64_t n)
+{
+    if (g_num_cu <= 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            g_num_cu = prop.multiProcessorCount;
+        if (g_num_cu <= 0) g_num_cu = 256;
+    }
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    const int64_t cap = (int64_t)g_num_cu * 16;
+    return (int)(blocks < cap ? blocks : cap);
+}
+
+static const StepFn kStepF64[ADK_MAX_W + 1] = {nullptr, adk_step_f64_1, adk_step_f64_2, adk_step_f64_3,
+                                               adk_step_f64_4, adk_step_f64_5, adk_step_f64_6,
+                                               adk_step_f64_7, adk_step_f64_8};
+static const StepFn kStepMixed[ADK_MAX_W + 1] = {nullptr, adk_step_mixed_1, adk_step_mixed_2, adk_step_mixed_3,
+                                                 adk_step_mixed_4, adk_step_mixed_5, adk_step_mixed_6,
+                                                 adk_step_mixed_7, adk_step_mixed_8};
+static const AdvanceFn kAdvF64[ADK_MAX_W + 1] = {nullptr, adk_advance_f64_1, adk_advance_f64_2,
+                                                 adk_advance_f64_3, adk_advance_f64_4, adk_advance_f64_5,
+                                                 adk_advance_f64_6, adk_advance_f64_7, adk_advance_f64_8};
+static const AdvanceFn kAdvMixed[ADK_MAX_W + 1] = {nullptr, adk_advance_mixed_1, adk_advance_mixed_2,
+                                                   adk_advance_mixed_3, adk_advance_mixed_4,
+                                                   adk_advance_mixed_5, adk_advance_mixed_6,
+                                                   adk_advance_mixed_7, adk_advance_mixed_8};
+
+static int status_of(hipError_t e)
+{
+    if (e == hipSuccess) return ADK_OK;
+    if (e == hipErrorOutOfMemory) return ADK_ENOMEM;
+    return ADK_EDEVICE;
+}
+
+static bool valid_prec(int p) { return p == ADK_F64 || p == ADK_MIXED; }
+
+}  // namespace adk
+
+using namespace adk;
+
+extern "C" {
+
+const char *adk_version(void) { return "adkion 0.1.0 (gfx950)"; }
+
+const char *adk_strerror(int status)
+{
+    switch (status) {
+    case ADK_OK: return "ok";
+    case ADK_EINVAL: return "invalid argument";
+    case ADK_ERANGE: return "value out of supported range";
+    case ADK_EDEVICE: return "HIP device error";
+    case ADK_ENOMEM: return "device allocation failed";
+    default: return "unknown status";
+    }
+}
+
+int adk_gas_create(const adk_gas_desc *desc, const adk_constants *consts, adk_gas **out)
+{
+    if (!out) return ADK_EINVAL;
+    *out = nullptr;
+    const int st = validate_desc(desc, consts);
+    if (st != ADK_OK) return st;
+    adk_gas *g = new (std::nothrow) adk_gas;
+    if (!g) return ADK_ENOMEM;
+    std::memset(g, 0, sizeof(*g));
+    g->Z = desc->Z;
+    g->consts = resolve_constants(consts);
+    build_coeffs(*desc, g->consts, g->h_coef);
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return ADK_EDEVICE;
+    }
+    const size_t bytes = sizeof(double) * 8 * (size_t)g->Z;
+    hipError_t e = hipMalloc((void **)&g->d_coef, bytes);
+    if (e != hipSuccess) {
+        delete g;
+        return status_of(e);
+    }
+    e = hipMemcpy(g->d_coef, g->h_coef, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(g->d_coef);
+        delete g;
+        return status_of(e);
+    }
+    *out = g;
+    return ADK_OK;
+}
+
+int adk_gas_destroy(adk_gas *gas)
+{
+    if (!gas) return ADK_OK;
+    const hipError_t e = gas->d_coef ? hipFree(gas->d_coef) : hipSuccess;
+    delete gas;
+    return status_of(e);
+}
+
+int adk_gas_levels(const adk_gas *gas) { return gas ? gas->Z : ADK_EINVAL; }
+
+int adk_rates(const adk_gas *gas, const void *E, int64_t n, int32_t k0, int32_t nk, void *W_out, adk_prec prec,
+              hipStream_t stream)
+{
+    if (!gas || n < 0 || !valid_prec(prec)) return ADK_EINVAL;
+    if (n > 0 && (!E || !W_out)) return ADK_EINVAL;
+    if (k0 < 0 || nk < 1 || (int64_t)k0 + nk > gas->Z) return ADK_ERANGE;
+    if (n == 0) return ADK_OK;
+    const double inv_Ea = 1.0 / gas->consts.E_a;
+    if (prec == ADK_F64)
+        hipLaunchKernelGGL((rates_kernel<PolicyF64>), dim3(grid_for(n)), dim3(kBlock), 0, stream, gas->d_coef,
+                           gas->Z, k0, nk, inv_Ea, (const double *)E, (double *)W_out, n);
+    else
+        hipLaunchKernelGGL((rates_kernel<PolicyMixed>), dim3(grid_for(n)), dim3(kBlock), 0, stream, gas->d_coef,
+                           gas->Z, k0, nk, inv_Ea, (const float *)E, (float *)W_out, n);
+    return status_of(hipGetLastError());
+}
+
+int adk_chain_advance(int32_t w, const void *W, int64_t ncells, double dt, void *pops, adk_prec prec,
+                      hipStream_t stream)
+{
+    if (ncells < 0 || !valid_prec(prec)) return ADK_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
+    if (w < 1 || w > ADK_MAX_W) return ADK_ERANGE;
+    if (ncells > 0 && (!W || !pops)) return ADK_EINVAL;
+    if (ncells == 0) return ADK_OK;
+    const hipError_t e = (prec == ADK_F64 ? kAdvF64 : kAdvMixed)[w](W, ncells, dt, pops, stream);
+    return status_of(e);
+}
+
+int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops, uint8_t *lo,
+                const adk_window *win, hipStream_t stream)
+{
+    if (!gas || !win || ncells < 0) return ADK_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
+    if (!(win->eps >= 0.0) || !std::isfinite(win->eps)) return ADK_EINVAL;
+    if (!valid_prec(win->prec)) return ADK_EINVAL;
+    if (win->layout != ADK_LAYOUT_COMPACT && win->layout != ADK_LAYOUT_FULL) return ADK_EINVAL;
+    if (win->w < 1 || win->w > ADK_MAX_W || win->w > gas->Z) return ADK_ERANGE;
+    if (ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
+    if (ncells == 0) return ADK_OK;
+    const hipError_t e = (win->prec == ADK_F64 ? kStepF64 : kStepMixed)[win->w](gas, E, ncells, dt, pops, lo,
+                                                                               win, stream);
+    return status_of(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function the
+header declares, validates arguments on the host before any device call,
+and its host-built coefficient table reproduces the oracle's Eq. (1)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2202_10647_amd import adkion, workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "adkion.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(adkion.LIB_PATH):
+        from paper_2202_10647_amd import build
+        build.build()
+    return adkion.lib()
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*([a-z_]+)\s*\(", src, flags=re.M))
+
+
+def test_exports_every_declared_function(L):
+    declared = header_functions()
+    assert declared == set(adkion.EXPORTS), declared
+    out = subprocess.run(["nm", "-D", "--defined-only", adkion.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = declared - exported
+    assert not missing, missing
+    for name in declared:
+        assert hasattr(L, name)
+
+
+def test_version_and_strerror(L):
+    assert "adkion" in adkion.version()
+    assert adkion.status_text(adkion.ADK_EINVAL) == "invalid argument"
+    assert adkion.status_text(12345) == "unknown status"
+
+
+def gas_desc(Z=7):
+    g = wl.synthetic_gas(Z)
+    return g.U, g.l, g.m
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(U=[-1.0]), adkion.ADK_EINVAL),
+    (dict(U=[float("nan")]), adkion.ADK_EINVAL),
+    (dict(l=[4]), adkion.ADK_EINVAL),
+    (dict(l=[-1]), adkion.ADK_EINVAL),
+    (dict(l=[1], m=[2]), adkion.ADK_EINVAL),
+    (dict(l=[1], m=[-2]), adkion.ADK_EINVAL),
+])
+def test_gas_validation(L, bad, status):
+    U, l, m = [13.6], [0], [0]
+    U = bad.get("U", U)
+    l = bad.get("l", l)
+    m = bad.get("m", m)
+    with pytest.raises(adkion.AdkError) as e:
+        adkion.gas_coeffs(U, l, m)
+    assert e.value.status == status
+
+
+def test_gas_z_range(L):
+    with pytest.raises(adkion.AdkError) as e:
+        adkion.gas_coeffs(np.full(65, 20.0), np.zeros(65), np.zeros(65))
+    assert e.value.status == adkion.ADK_ERANGE
+    d = adkion._GasDesc(0, None, None, None)
+    assert L.adk_gas_coeffs(ctypes.byref(d), None, None) == adkion.ADK_ERANGE
+    assert L.adk_gas_coeffs(None, None, None) == adkion.ADK_EINVAL
+    with pytest.raises(adkion.AdkError):
+        adkion.gas_coeffs([13.6], [0], [0], consts=(-1.0, 510.0, 13.6))
+
+
+@pytest.mark.parametrize("Z", [1, 7, 18, 36, 54])
+def test_coefficients_reproduce_eq1(L, orc, Z):
+    """ln W = A + alpha L - B R + ln(1 + sum c_j u^j) from the host table
+    against the oracle's literal product form."""
+    g = wl.synthetic_gas(Z)
+    coef = adkion.gas_coeffs(g.U, g.l, g.m)
+    spec = orc.GasSpec(g.U, g.l, g.m)
+    E = np.geomspace(5.0, 20000.0, 37)
+    W = orc.rates(spec, E)
+    u = E / orc.E_A
+    for k in range(Z):
+        A, al, B, c1, c2, c3 = coef[k, :6]
+        lnW = A + al * np.log(u) - B / u + np.log1p(c1 * u + c2 * u ** 2 + c3 * u ** 3)
+        ok = W[k] > 1e-250
+        if not ok.any():
+            continue
+        assert np.max(np.abs(lnW[ok] - np.log(W[k, ok]))) < 1e-12 * max(1.0, np.max(np.abs(lnW[ok])))
+
+
+def test_default_constants_are_paper_values(L):
+    U, l, m = gas_desc(7)
+    a = adkion.gas_coeffs(U, l, m)
+    b = adkion.gas_coeffs(U, l, m, consts=(4.13e16, 510.0, 27.21 / 2))
+    assert np.array_equal(a, b)
+
+
+def test_chain_advance_validation_before_device(L):
+    """Every rejected argument returns before any HIP call (no GPU here)."""
+    f = L.adk_chain_advance
+    p = ctypes.c_void_p(16)
+    assert f(0, p, 10, 1e-16, p, 0, None) == adkion.ADK_ERANGE
+    assert f(9, p, 10, 1e-16, p, 0, None) == adkion.ADK_ERANGE
+    assert f(3, p, -1, 1e-16, p, 0, None) == adkion.ADK_EINVAL
+    assert f(3, p, 10, 0.0, p, 0, None) == adkion.ADK_EINVAL
+    assert f(3, p, 10, float("inf"), p, 0, None) == adkion.ADK_EINVAL
+    assert f(3, None, 10, 1e-16, p, 0, None) == adkion.ADK_EINVAL
+    assert f(3, p, 10, 1e-16, p, 7, None) == adkion.ADK_EINVAL
+    # zero cells is a no-op that touches no device
+    assert f(3, None, 0, 1e-16, None, 0, None) == adkion.ADK_OK
+
+
+def test_step_and_rates_reject_null_gas(L):
+    win = adkion._Window(3, 1e-8, 0, 0)
+    p = ctypes.c_void_p(16)
+    assert L.ionize_step(None, p, 10, 1e-16, p, p, ctypes.byref(win), None) == adkion.ADK_EINVAL
+    assert L.ionize_step(p, p, 10, 1e-16, p, p, None, None) == adkion.ADK_EINVAL
+    assert L.adk_rates(None, p, 10, 0, 1, p, 0, None) == adkion.ADK_EINVAL
+    assert L.adk_gas_levels(None) == adkion.ADK_EINVAL
+    assert L.adk_gas_destroy(None) == adkion.ADK_OK
+
+
+def test_gas_create_out_pointer_required(L):
+    U, l, m = gas_desc(7)
+    d, keep = adkion._desc(U, l, m)
+    assert L.adk_gas_create(ctypes.byref(d), None, None) == adkion.ADK_EINVAL
+    h = ctypes.c_void_p(1234)
+    bad, keep2 = adkion._desc([-5.0], [0], [0])
+    assert L.adk_gas_create(ctypes.byref(bad), None, ctypes.byref(h)) == adkion.ADK_EINVAL
+    assert h.value is None

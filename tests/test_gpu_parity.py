@@ -1,0 +1,354 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (per call, from identical input bits):
+  ADK_F64   max |dN_k| <= 1e-12, window index bit-exact
+  ADK_MIXED max |dN_k| <= 1e-6,  window index bit-exact (the shift test is
+            evaluated in double on both sides from the same float inputs)
+"""
+import numpy as np
+import pytest
+
+from paper_2202_10647_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "mixed": 1e-6}
+DT = 1.334e-16
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ak(torch_dev):
+    from paper_2202_10647_amd import adkion
+    adkion.lib()
+    return adkion
+
+
+_GAS_CACHE = {}
+
+
+def gas_pair(ak, orc, Z):
+    if Z not in _GAS_CACHE:
+        g = wl.synthetic_gas(Z)
+        _GAS_CACHE[Z] = (ak.Gas.from_table(g), orc.GasSpec(g.U, g.l, g.m))
+    return _GAS_CACHE[Z]
+
+
+def npdt(prec):
+    return np.float64 if prec == "f64" else np.float32
+
+
+def run_step(torch, ak, gas, E, pops, lo, w, eps, layout, dt=DT):
+    Et = torch.from_numpy(np.ascontiguousarray(E)).cuda()
+    Pt = torch.from_numpy(np.ascontiguousarray(pops)).cuda()
+    Lt = torch.from_numpy(np.ascontiguousarray(lo)).cuda()
+    ak.ionize_step(gas, Et, dt, Pt, Lt, w=w, eps=eps, layout=layout)
+    torch.cuda.synchronize()
+    return Pt.cpu().numpy(), Lt.cpu().numpy()
+
+
+def compare(gpu, ref, prec, what):
+    g = gpu.astype(np.float64)
+    finite = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(g), finite), f"{what}: non-finite pattern differs"
+    err = np.max(np.abs(g[finite] - ref[finite])) if finite.any() else 0.0
+    assert err <= TOL[prec], f"{what}: max |dN| = {err:.3e} > {TOL[prec]:.0e}"
+    return err
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("Z", [1, 7, 18, 36, 54])
+def test_rates(torch_dev, ak, orc, prec, Z):
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, Z)
+    E = np.concatenate([wl.loguniform_field(3000, 1.0, 20000.0, 21), [0.0, -300.0, 1e-30, 5e-4]])
+    E = E.astype(npdt(prec))
+    Et = torch.from_numpy(E).cuda()
+    W = ak.rates(gas, Et).cpu().numpy().astype(np.float64)
+    ref = orc.rates(spec, E.astype(np.float64))
+    assert np.all(W[:, -4] == 0.0)
+    # the oracle sets rates below ~1e-200/s to zero; the GPU's log-domain
+    # value there must be negligible too
+    assert np.all(W[ref == 0.0] * DT < 1e-150)
+    floor = 1e-250 if prec == "f64" else 1e-30
+    ok = ref > floor
+    rel = np.abs(W[ok] - ref[ok]) / ref[ok]
+    if prec == "f64":
+        assert rel.max() < 1e-12
+    else:
+        # float result of a double exponent: a few float ulps
+        assert rel.max() < 4e-7
+    assert np.all(W[(ref > 0) & ~ok] < 10 * floor)
+
+
+def adversarial_rates(rng, w, n):
+    """Rates per step x = W dt: random magnitudes, clusters, exact ties,
+    zeros, crossings and huge values."""
+    x = np.empty((w, n))
+    kinds = rng.integers(0, 7, n)
+    for c in range(n):
+        k = kinds[c]
+        if k == 0:
+            v = np.exp(rng.uniform(np.log(1e-8), np.log(1e3), w))
+        elif k == 1:
+            c0 = np.exp(rng.uniform(np.log(1e-3), np.log(30)))
+            v = np.abs(c0 * (1 + 10.0 ** rng.uniform(-12, -1, w) * rng.standard_normal(w)))
+        elif k == 2:
+            v = np.full(w, np.exp(rng.uniform(np.log(1e-3), np.log(30))))
+        elif k == 3:
+            v = np.exp(rng.uniform(np.log(1e-3), np.log(5), w))
+            v[rng.random(w) < 0.4] = 0.0
+        elif k == 4:
+            v = rng.uniform(0, 3, w)
+        elif k == 5:
+            v = np.exp(rng.uniform(np.log(1e-2), np.log(1e10), w))
+        else:
+            v = rng.uniform(0, 10, w)
+            v[-1] = v[0] * (1 + 1e-9)
+        x[:, c] = v
+    return x
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("w", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_chain_advance_adversarial(torch_dev, ak, orc, prec, w):
+    torch = torch_dev
+    rng = np.random.default_rng(1000 + w)
+    n = 4099
+    W = (adversarial_rates(rng, w, n) / DT).astype(npdt(prec))
+    pops = rng.random((w + 1, n))
+    pops /= pops.sum(axis=0)
+    pops = pops.astype(npdt(prec))
+    Wt = torch.from_numpy(W).cuda()
+    Pt = torch.from_numpy(pops).cuda()
+    ak.chain_advance(Wt, DT, Pt)
+    out = Pt.cpu().numpy()
+    # the oracle sees the same rate per step: dt * float(W), widened
+    ref = orc.chain_advance(W.astype(np.float64), DT, pops.astype(np.float64))
+    compare(out, ref, prec, f"chain_advance w={w} {prec}")
+    assert out.astype(np.float64).min() >= -TOL[prec]
+
+
+def test_config1_full_chain_f64(torch_dev, ak, orc):
+    """4096 cells, 7-level chain, E log-uniform [10, 2000] GV/m, dt = 0.1 fs,
+    neutral start, full chain (w = Z = 7), one step."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, 7)
+    n = 4096
+    E = wl.loguniform_field(n, 10.0, 2000.0, seed=1)
+    pops, lo = wl.neutral_state(n, 8)
+    out, lo2 = run_step(torch, ak, gas, E, pops, lo, w=7, eps=0.0, layout="compact", dt=1e-16)
+    ref, rlo = orc.ionize_step(spec, E, 1e-16, pops, lo, 7, 0.0)
+    assert np.array_equal(lo2, rlo)
+    compare(out, ref, "f64", "config 1")
+    # closed-form pin on the GPU result: neutral fraction is exp(-W0 dt)
+    W0 = orc.rates(spec, E, k0=0, nk=1)[0]
+    assert np.max(np.abs(out[0] - np.exp(-W0 * 1e-16))) < 1e-13
+    assert np.max(np.abs(out.sum(axis=0) - 1)) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("layout", ["compact", "full"])
+@pytest.mark.parametrize("Z,w", [(7, 3), (18, 3), (18, 4), (36, 3), (54, 6), (7, 1), (18, 2), (36, 5)])
+def test_random_window_states(torch_dev, ak, orc, prec, layout, Z, w):
+    """Random states with every window position, shifts, exact zeros and
+    ragged cell counts; E spans 0, negative and [1, 2e4] GV/m."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, Z)
+    n = 3 * 256 + 77
+    comp, lo = wl.random_window_state(n, Z, w, seed=Z * 10 + w)
+    E = wl.loguniform_field(n, 1.0, 20000.0, seed=Z + w)
+    E[::17] *= -1
+    E[::29] = 0.0
+    if layout == "compact":
+        pops = comp
+    else:
+        pops = np.zeros((Z + 1, n))
+        for c in range(n):
+            for s in range(w + 1):
+                if lo[c] + s <= Z:
+                    pops[lo[c] + s, c] = comp[s, c]
+    pops = pops.astype(npdt(prec))
+    E = E.astype(npdt(prec))
+    out, lo2 = run_step(torch, ak, gas, E, pops, lo, w=w, eps=1e-8, layout=layout)
+    ref, rlo = orc.ionize_step(spec, E.astype(np.float64), DT, pops.astype(np.float64), lo, w, 1e-8,
+                               layout=0 if layout == "compact" else 1)
+    assert np.array_equal(lo2, rlo)
+    compare(out, ref, prec, f"Z={Z} w={w} {layout} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_mesh2d_trajectory(torch_dev, ak, orc, prec):
+    """A strip of the 2D pulse mesh (18 levels, w = 4) stepped 800 times on
+    the GPU and, independently, by the oracle from the same neutral start and
+    the same field bits.  F64 must stay within the per-call tolerance over
+    the whole trajectory; the float path is bounded by its accumulated
+    storage rounding (reported drift, window indices agree)."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, 18)
+    mesh = wl.mesh_2d()
+    rows = np.arange(448, 576, 8)
+    idx = (rows[:, None] * 1024 + np.arange(0, 1024, 16)[None, :]).ravel()
+    n = idx.size
+    w = 4
+    pops, lo = wl.neutral_state(n, w + 1, dtype=npdt(prec))
+    Pt = torch.from_numpy(pops).cuda()
+    Lt = torch.from_numpy(lo).cuda()
+    rp, rl = pops.astype(np.float64), lo.copy()
+    worst = 0.0
+    for step in range(0, 1600, 2):
+        E = mesh.field_at(step, idx).astype(npdt(prec))
+        ak.ionize_step(gas, torch.from_numpy(E).cuda(), 2 * mesh.dt, Pt, Lt, w=w, eps=1e-8)
+        rp, rl = orc.ionize_step(spec, E.astype(np.float64), 2 * mesh.dt, rp, rl, w, 1e-8)
+        if step % 100 == 0:
+            out, l2 = Pt.cpu().numpy().astype(np.float64), Lt.cpu().numpy()
+            same = l2 == rl
+            if prec == "f64":
+                assert same.all(), step
+            else:
+                assert same.mean() > 0.99, step
+            worst = max(worst, float(np.max(np.abs(out[:, same] - rp[:, same]))))
+    assert rl.max() >= 5
+    assert worst < (1e-12 if prec == "f64" else 1e-4), worst
+
+
+def test_mixed_tracks_f64_over_trajectory(torch_dev, ak, orc):
+    """Trajectory drift of the float path relative to the double path
+    (reported, loosely bounded: per-call errors accumulate over steps)."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, 18)
+    mesh = wl.mesh_2d()
+    idx = (np.arange(480, 544)[:, None] * 1024 + np.arange(0, 1024, 8)[None, :]).ravel()
+    st = {}
+    for dt_ in (torch.float64, torch.float32):
+        p, l = wl.neutral_state(idx.size, 5)
+        st[dt_] = [torch.from_numpy(p).to(dt_).cuda(), torch.from_numpy(l).cuda()]
+    for step in range(0, 2000, 4):
+        E = mesh.field_at(step, idx)
+        for dt_ in st:
+            ak.ionize_step(gas, torch.from_numpy(E).to(dt_).cuda(), 4 * mesh.dt, *st[dt_], w=4, eps=1e-8)
+    p64, l64 = [t.cpu().numpy() for t in st[torch.float64]]
+    p32, l32 = [t.cpu().numpy() for t in st[torch.float32]]
+    same = l64 == l32
+    assert same.mean() > 0.99
+    drift = np.max(np.abs(p64[:, same] - p32[:, same].astype(np.float64)))
+    assert drift < 1e-4
+
+
+def test_edge_cases(torch_dev, ak, orc):
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, 7)
+    # zero cells: no-op
+    E = torch.zeros(0, dtype=torch.float64, device="cuda")
+    P = torch.zeros((4, 0), dtype=torch.float64, device="cuda")
+    L = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    ak.ionize_step(gas, E, DT, P, L, w=3)
+    for n in (1, 63, 64, 65, 255, 256, 257):
+        Eh = wl.loguniform_field(n, 100, 3000, n)
+        pops, lo = wl.neutral_state(n, 4)
+        lo[-1] = 200  # read as Z
+        pops[:, -1] = [1.0, 0, 0, 0]
+        out, lo2 = run_step(torch, ak, gas, Eh, pops, lo, w=3, eps=1e-8, layout="compact")
+        ref, rlo = orc.ionize_step(spec, Eh, DT, pops, lo, 3, 1e-8)
+        assert np.array_equal(lo2, rlo) and lo2[-1] == 7
+        compare(out, ref, "f64", f"n={n}")
+    # NaN field: that cell only
+    n = 300
+    Eh = wl.loguniform_field(n, 100, 3000, 3)
+    Eh[123] = np.nan
+    pops, lo = wl.neutral_state(n, 4)
+    out, lo2 = run_step(torch, ak, gas, Eh, pops, lo, w=3, eps=1e-8, layout="compact")
+    assert np.all(np.isnan(out[:, 123]))
+    mask = np.ones(n, bool)
+    mask[123] = False
+    assert np.all(np.isfinite(out[:, mask]))
+
+
+def test_argument_errors(torch_dev, ak, orc):
+    torch = torch_dev
+    gas, _ = gas_pair(ak, orc, 7)
+    E = torch.ones(10, dtype=torch.float64, device="cuda")
+    P = torch.zeros((9, 10), dtype=torch.float64, device="cuda")
+    L = torch.zeros(10, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ak.AdkError) as e:
+        ak.ionize_step(gas, E, DT, P, L, w=8)  # w > Z
+    assert e.value.status == ak.ADK_ERANGE
+    with pytest.raises(ak.AdkError) as e:
+        ak.ionize_step(gas, E, -1.0, P[:4].contiguous(), L, w=3)
+    assert e.value.status == ak.ADK_EINVAL
+    with pytest.raises(ak.AdkError) as e:
+        ak.ionize_step(gas, E, DT, P[:4].contiguous(), L, w=3, eps=-1.0)
+    assert e.value.status == ak.ADK_EINVAL
+    with pytest.raises(ak.AdkError) as e:
+        ak.rates(gas, E, k0=5, nk=3)
+    assert e.value.status == ak.ADK_ERANGE
+
+
+def test_determinism_and_layout_equivalence(torch_dev, ak, orc):
+    torch = torch_dev
+    gas, _ = gas_pair(ak, orc, 18)
+    n = 20000
+    comp, lo = wl.random_window_state(n, 18, 3, seed=9)
+    E = wl.loguniform_field(n, 10, 5000, 8)
+    a = run_step(torch, ak, gas, E, comp, lo, 3, 1e-8, "compact")
+    b = run_step(torch, ak, gas, E, comp, lo, 3, 1e-8, "compact")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    full = np.zeros((19, n))
+    for s in range(4):
+        ok = lo.astype(int) + s <= 18
+        full[lo[ok].astype(int) + s, np.nonzero(ok)[0]] = comp[s, ok]
+    f, fl = run_step(torch, ak, gas, E, full, lo, 3, 1e-8, "full")
+    assert np.array_equal(fl, a[1])
+    for s in range(4):
+        ok = fl.astype(int) + s <= 18
+        cols = np.nonzero(ok)[0]
+        assert np.array_equal(f[fl[ok].astype(int) + s, cols], a[0][s, ok])
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f64"])
+@pytest.mark.parametrize("state", ["neutral", "random"])
+def test_mesh3d_full_size_sampled(torch_dev, ak, orc, prec, state):
+    """33,554,432 cells, 36 levels (m averaged), w = 3, one call in the launch
+    configuration the benchmark times, with the pulse inside the mesh
+    (t = 250 dt).  Pre-states are seeded synthetic inputs; 65,536 random cells
+    plus three on-axis lines are recomputed by the oracle."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, 36)
+    mesh = wl.mesh_3d()
+    n = mesh.ncells
+    w = 3
+    dtp = npdt(prec)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    rng = np.random.default_rng(33)
+    nz = mesh.shape[-1]
+    hot = (128 * 256 + 128) * nz + np.arange(nz)
+    sample = np.unique(np.concatenate([rng.choice(n, 65536, replace=False), hot, hot + nz,
+                                       hot + 256 * nz]))
+    E = mesh.field(250, dtype=dtp)
+    if state == "neutral":
+        pops, lo = wl.neutral_state(n, w + 1, dtype=dtp)
+    else:
+        pops, lo = wl.random_window_state(n, 36, w, seed=77, dtype=dtp)
+    Et = torch.from_numpy(E).cuda()
+    Pt = torch.from_numpy(pops).cuda()
+    Lt = torch.from_numpy(lo).cuda()
+    ak.ionize_step(gas, Et, mesh.dt, Pt, Lt, w=w, eps=1e-8)
+    idx_t = torch.from_numpy(sample).cuda()
+    out = Pt[:, idx_t].cpu().numpy()
+    l2 = Lt[idx_t].cpu().numpy()
+    ref, rlo = orc.ionize_step(spec, E[sample].astype(np.float64), mesh.dt,
+                               pops[:, sample].astype(np.float64), lo[sample], w, 1e-8)
+    assert np.array_equal(l2, rlo)
+    compare(out, ref, prec, f"3D {state} {prec}")
+    if state == "neutral":
+        # a neutral start ionizes through the window in the pulse centre
+        assert out[w].max() > 0.5
+    del Pt, Lt, Et, idx_t
+    torch.cuda.empty_cache()
