@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Throughput of the multi-level ADK ionization step on one MI355X.
+
+Metric: cell-level updates per second of ionize_step, one unit being one
+population of a cell's active window advanced by one step (sum over cells
+of top - lo + 1), for the mixed-precision path, next to the plain FP64 path
+on the same GPU and the CPU oracle on the host.
+
+Headline workload: the 2D laser-pulse mesh (1024 x 1024 cells, 18-level
+synthetic chain, window of 4 populations, w = 3, 2000 steps of 0.05 laser
+periods).  The timed region is K consecutive steps of that run (default: the
+whole run), with the field of every step already resident in device memory.
+A second, HBM-bound workload (the 256 x 256 x 512 3D mesh, 36 levels,
+m-averaged) is measured as well and reported under "mesh3d".
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "cell·level updates/s of ionize_step vs plain FP64 at max |ΔN_k| ≤ 1e-6"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_cell(w, prec):
+    """Algorithmic HBM bytes per cell per step, compact layout: E read, window
+    index read + write, w+1 populations read + written."""
+    s = 4 if prec == "mixed" else 8
+    return s + 1 + 1 + 2 * (w + 1) * s
+
+
+def window_units(lo, w, Z):
+    import torch
+    top = torch.clamp(lo.to(torch.int64) + w, max=Z)
+    return int((top - lo.to(torch.int64) + 1).sum().item())
+
+
+def run_steps(ak, gas, fields, dt, pops, lo, w, eps, t0=0, nsteps=None, per_launch=False, count_units=False,
+              Z=None):
+    """Advance nsteps steps with fields[t0 + i].  Returns (elapsed_ms between
+    events on the launch stream, per-launch average ms or None, units)."""
+    import torch
+    nsteps = fields.shape[0] - t0 if nsteps is None else nsteps
+    stream = torch.cuda.current_stream()
+    units = 0
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(nsteps)] if per_launch else None
+    start.record(stream)
+    for i in range(nsteps):
+        if per_launch:
+            evs[i][0].record(stream)
+        ak.ionize_step(gas, fields[t0 + i], dt, pops, lo, w=w, eps=eps)
+        if per_launch:
+            evs[i][1].record(stream)
+        if count_units:
+            units += window_units(lo, w, Z)
+    end.record(stream)
+    torch.cuda.synchronize()
+    total = start.elapsed_time(end)
+    avg = float(np.mean([a.elapsed_time(b) for a, b in evs])) if per_launch else None
+    return total, avg, units
+
+
+def measure_path(ak, gas, mesh, fields, prec, w, eps, Z, warmup, label):
+    """Warm up, time the run, time each launch, count window units."""
+    import torch
+    tdt = torch.float32 if prec == "mixed" else torch.float64
+    n = mesh.ncells
+    K = fields.shape[0]
+
+    def fresh():
+        p = torch.zeros((w + 1, n), dtype=tdt, device="cuda")
+        p[0] = 1.0
+        return p, torch.zeros(n, dtype=torch.uint8, device="cuda")
+
+    p, lo = fresh()
+    run_steps(ak, gas, fields, mesh.dt, p, lo, w, eps, nsteps=min(warmup, K))
+    p, lo = fresh()
+    total_ms, _, _ = run_steps(ak, gas, fields, mesh.dt, p, lo, w, eps)
+    # same run again with an event pair around every launch (kernel duration)
+    p, lo = fresh()
+    _, avg_ms, _ = run_steps(ak, gas, fields, mesh.dt, p, lo, w, eps, per_launch=True)
+    # untimed replay counting the window populations advanced per step
+    p, lo = fresh()
+    _, _, units = run_steps(ak, gas, fields, mesh.dt, p, lo, w, eps, count_units=True, Z=Z)
+    final_lo = int(lo.max().item())
+    ms_per_step = total_ms / K
+    value = units / (total_ms * 1e-3)
+    gbps = bytes_per_cell(w, prec) * n / (avg_ms * 1e-3) / 1e9
+    log(f"[{label}] {prec}: {ms_per_step * 1e3:.2f} us/step, kernel {avg_ms * 1e3:.2f} us, "
+        f"{value:.3e} cell-level/s, {gbps:.0f} GB/s algorithmic, max lo {final_lo}")
+    return dict(value=value, ms_per_step=ms_per_step, kernel_ms=avg_ms, units=units, achieved_gbps=gbps,
+                max_lo=final_lo)
+
+
+def parity_check(ak, orc, gas, spec, mesh, w, eps, step, seed):
+    """One call from a seeded synthetic state at full mesh size; sampled cells
+    recomputed by the oracle from the same input bits."""
+    import torch
+    from paper_2202_10647_amd import workloads as wl
+    n = mesh.ncells
+    rng = np.random.default_rng(seed)
+    sample = np.unique(np.concatenate([rng.choice(n, min(n, 65536), replace=False),
+                                       np.arange(n // 2, n // 2 + mesh.shape[-1])]))
+    E64 = mesh.field(step)
+    comp, lo = wl.random_window_state(n, spec.Z, w, seed=seed)
+    out = {}
+    for prec, npdt, tdt in (("mixed", np.float32, torch.float32), ("f64", np.float64, torch.float64)):
+        E = E64.astype(npdt)
+        P = comp.astype(npdt)
+        Pt, Lt = torch.from_numpy(P).cuda(), torch.from_numpy(lo.copy()).cuda()
+        ak.ionize_step(gas, torch.from_numpy(E).cuda(), mesh.dt, Pt, Lt, w=w, eps=eps)
+        idx = torch.from_numpy(sample).cuda()
+        g = Pt[:, idx].cpu().numpy().astype(np.float64)
+        gl = Lt[idx].cpu().numpy()
+        ref, rlo = orc.ionize_step(spec, E[sample].astype(np.float64), mesh.dt, P[:, sample].astype(np.float64),
+                                   lo[sample], w, eps)
+        out[prec] = dict(max_abs_err=float(np.max(np.abs(g - ref))), lo_mismatch=int(np.sum(gl != rlo)),
+                         cells=int(sample.size))
+        log(f"[parity] {prec}: max |dN| = {out[prec]['max_abs_err']:.2e} over {sample.size} cells, "
+            f"lo mismatches {out[prec]['lo_mismatch']}")
+    return out
+
+
+def cpu_baseline(orc, spec, mesh, w, eps, step, seed, target_s):
+    """The oracle as it stands, on the host cores: one ionize_step over a
+    bounded sample of the mesh cells (sized for about target_s seconds)."""
+    from paper_2202_10647_amd import workloads as wl
+    n = mesh.ncells
+    E = mesh.field(step)
+    comp, lo = wl.random_window_state(n, spec.Z, w, seed=seed)
+    probe = 8192
+    t = time.perf_counter()
+    orc.ionize_step(spec, E[:probe], mesh.dt, comp[:, :probe], lo[:probe], w, eps)
+    rate = probe / max(time.perf_counter() - t, 1e-6)
+    m = int(min(n, max(probe, rate * target_s)))
+    t = time.perf_counter()
+    _, lo2 = orc.ionize_step(spec, E[:m], mesh.dt, comp[:, :m], lo[:m], w, eps)
+    el = time.perf_counter() - t
+    units = int(np.sum(np.minimum(lo2.astype(np.int64) + w, spec.Z) - lo2.astype(np.int64) + 1))
+    log(f"[cpu] oracle: {m} cells in {el:.2f} s on {orc.max_threads()} threads")
+    return dict(value=units / el, unit="cell·level updates/s", cores=orc.max_threads(), kind="oracle",
+                sample=f"one ionize_step (w={w}, {spec.Z} levels, FP64 rates, binary128 expm) over the first "
+                       f"{m} cells of the {mesh.shape[0]}x{mesh.shape[1]} mesh at t={step} dt from a seeded "
+                       f"random window state; OpenMP over cells; {el:.1f} s")
+
+
+def mesh3d_measure(ak, gas36, w, eps, steps, warmup):
+    """HBM-bound workload: 33.5M cells, 36 levels, m averaged, mixed and FP64."""
+    import torch
+    from paper_2202_10647_amd import workloads as wl
+    mesh = wl.mesh_3d()
+    n = mesh.ncells
+    t_first = 200
+    res = {}
+    for prec, tdt in (("mixed", torch.float32), ("f64", torch.float64)):
+        fields = torch.empty((steps, n), dtype=tdt, device="cuda")
+        for i in range(steps):
+            fields[i] = mesh.field_torch(t_first + i, "cuda", tdt)
+        p = torch.zeros((w + 1, n), dtype=tdt, device="cuda")
+        p[0] = 1.0
+        lo = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        for i in range(min(warmup, t_first)):  # run the pulse in (untimed)
+            ak.ionize_step(gas36, mesh.field_torch(i, "cuda", tdt), mesh.dt, p, lo, w=w, eps=eps)
+        total, avg, _ = run_steps(ak, gas36, fields, mesh.dt, p, lo, w, eps, per_launch=True)
+        # the window index only grows, so the final index bounds every step's
+        # window from below (exact while lo <= Z - w, which holds here)
+        units = window_units(lo, w, 36) * steps
+        value = units / (total * 1e-3)
+        gbps = bytes_per_cell(w, prec) * n / (avg * 1e-3) / 1e9
+        res[prec] = dict(value=value, ms_per_step=total / steps, kernel_ms=avg, achieved_gbps=gbps,
+                         frac_hbm=gbps / HBM_PEAK_GBPS)
+        log(f"[mesh3d] {prec}: {total / steps * 1e3:.1f} us/step, kernel {avg * 1e3:.1f} us, {value:.3e} "
+            f"cell-level/s, {gbps:.0f} GB/s ({gbps / HBM_PEAK_GBPS:.2f} of HBM peak)")
+        del fields, p, lo
+        torch.cuda.empty_cache()
+    res["speedup_mixed_vs_f64"] = res["mixed"]["value"] / res["f64"]["value"]
+    res["workload"] = "laser3d_256x256x512_Z36mavg_w3"
+    res["timed_steps"] = f"{steps} steps from t={t_first} dt"
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--window", type=int, default=3)
+    ap.add_argument("--eps", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-mesh3d", action="store_true")
+    ap.add_argument("--mesh3d-steps", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the ionization step has no "
+              "cross-cell coupling and this build measures one GPU's share; see DESIGN.md for sharding.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle
+    from paper_2202_10647_amd import adkion, workloads as wl
+
+    if not os.path.exists(adkion.LIB_PATH):
+        from paper_2202_10647_amd import build
+        build.build()
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    torch.cuda.set_device(0)
+
+    w, eps = args.window, args.eps
+    mesh = wl.mesh_2d()
+    K = min(args.steps, mesh.steps)
+    g18 = wl.synthetic_gas(18)
+    gas = adkion.Gas.from_table(g18)
+    spec = oracle.GasSpec(g18.U, g18.l, g18.m)
+    n = mesh.ncells
+
+    log(f"[setup] {n} cells, Z=18, w={w}, {K} timed steps, fields resident in HBM")
+    f64 = torch.empty((K, n), dtype=torch.float64, device="cuda")
+    for t in range(K):
+        f64[t] = mesh.field_torch(t, "cuda", torch.float64)
+    f32 = f64.to(torch.float32)
+
+    res = {}
+    res["mixed"] = measure_path(adkion, gas, mesh, f32, "mixed", w, eps, 18, args.warmup, "mesh2d")
+    res["f64"] = measure_path(adkion, gas, mesh, f64, "f64", w, eps, 18, args.warmup, "mesh2d")
+    del f64, f32
+    torch.cuda.empty_cache()
+
+    parity = None if args.no_parity else parity_check(adkion, oracle, gas, spec, mesh, w, eps, 1000, 2024)
+    mesh3d = None
+    if not args.no_mesh3d:
+        g36 = wl.synthetic_gas(36)
+        gas36 = adkion.Gas.from_table(g36)
+        mesh3d = mesh3d_measure(adkion, gas36, w, eps, args.mesh3d_steps, 200)
+        gas36.close()
+    cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, spec, mesh, w, eps, 1000, 7,
+                                                         args.cpu_seconds)
+
+    m = res["mixed"]
+    line = {
+        "metric": METRIC,
+        "value": m["value"],
+        "unit": "cell·level updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"laser2d_1024x1024_Z18_w{w}", "cells": n, "levels": 18, "window_w": w,
+                   "eps": eps, "layout": "compact", "precision": "mixed", "dt_s": mesh.dt,
+                   "timed_steps": f"steps 0..{K - 1} of the {mesh.steps}-step run", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": m["achieved_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": m["achieved_gbps"] / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": f"step_compact_kernel<PolicyMixed,{w}>",
+                     "bytes_per_cell": bytes_per_cell(w, "mixed"), "kernel_avg_us": m["kernel_ms"] * 1e3},
+        "fp64": {"value": res["f64"]["value"], "ms_per_step": res["f64"]["ms_per_step"],
+                 "kernel_avg_us": res["f64"]["kernel_ms"] * 1e3, "achieved_gbps": res["f64"]["achieved_gbps"]},
+        "speedup_vs_fp64": m["value"] / res["f64"]["value"],
+        "parity": parity,
+        "mesh3d": mesh3d,
+        "cpu_baseline": cpu,
+    }
+    gas.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -135,6 +135,29 @@ class LaserMesh:
         return E.reshape(-1).astype(dtype)
 
 
+    def field_torch(self, step: int, device, dtype):
+        """field() evaluated with torch on a device (same formula, float64
+        arithmetic, cast to dtype); used to keep many steps of E resident in
+        device memory without a host round trip."""
+        import torch
+        trans, z = self.axes_um()
+        t = step * self.dt
+        ct_um = C_LIGHT * t * 1e6
+        k0 = 2 * math.pi / self.lam_um
+        om_t = 2 * math.pi * C_LIGHT * t / (self.lam_um * 1e-6)
+        ctau = C_LIGHT * self.tau_fs * 1e-15 * 1e6
+        zt = torch.from_numpy(z).to(device)
+        env_z = torch.exp(-((zt - ct_um) / ctau) ** 2) * torch.cos(k0 * zt - om_t)
+        r2 = None
+        for i, a in enumerate(trans):
+            shp = [1] * len(trans)
+            shp[i] = a.size
+            term = torch.from_numpy(a).to(device).reshape(shp) ** 2
+            r2 = term if r2 is None else r2 + term
+        E = self.E0 * torch.exp(-r2 / self.w0_um ** 2)[..., None] * env_z
+        return E.reshape(-1).to(dtype)
+
+
 def mesh_2d() -> LaserMesh:
     """1024 x 1024 2D mesh, 0.08 um cells, E0 = 3000 GV/m, 2000 steps."""
     return LaserMesh((1024, 1024), 0.08, 0.08, E0=3000.0, steps=2000)
