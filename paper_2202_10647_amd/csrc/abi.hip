@@ -15,18 +15,79 @@ namespace adk {
 // ---------------------------------------------------------------------------
 static int g_num_cu = 0;
 
-int grid_for(int64_t n)
+int num_cus()
 {
     if (g_num_cu <= 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            g_num_cu = prop.multiProcessorCount;
-        if (g_num_cu <= 0) g_num_cu = 256;
+        int dev = 0, cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            g_num_cu = cu;
+        else
+            g_num_cu = 256;
     }
+    return g_num_cu;
+}
+
+int grid_for(int64_t n)
+{
     const int64_t blocks = (n + kBlock - 1) / kBlock;
-    const int64_t cap = (int64_t)g_num_cu * 16;
+    const int64_t cap = (int64_t)num_cus() * 8;
     return (int)(blocks < cap ? blocks : cap);
+}
+
+StepArgs step_args(const adk_gas *g, double dt, double eps)
+{
+    StepArgs a;
+    a.tab = g->d_coef;
+    a.Z = g->Z;
+    a.has_poly = g->has_poly;
+    a.ln_dt = std::log(dt);
+    a.eps = eps;
+    adk_gas *mg = const_cast<adk_gas *>(g);
+    std::lock_guard<std::mutex> lock(mg->cut_mu);
+    if (mg->cut_dt != dt) {
+        mg->cut_E = field_cutoff(*g, dt);
+        mg->cut_dt = dt;
+    }
+    a.E_cut = mg->cut_E;
+    return a;
+}
+
+// Reduction table of fast_log2: bin j of the mantissa m in [1/2, 1) (top six
+// fraction bits) has centre m_j = (1 + (j + 1/2)/64)/2; c_j is 1/m_j rounded
+// to a float (so that m c_j is exact for float inputs) and -log2 c_j is
+// evaluated in long double.
+static void log2_table(double *t)
+{
+    for (int j = 0; j < kLogTable; ++j) {
+        const double mj = 0.5 * (1.0 + (j + 0.5) / kLogTable);
+        const double c = (double)(float)(1.0 / mj);
+        t[2 * j] = c;
+        t[2 * j + 1] = (double)(-std::log2((long double)c));
+    }
+}
+
+// Rows of the LDS rate table (see kernels.hpp): for level k,
+// a = A log2(e) - alpha log2(E_a) (ln dt log2(e) is added at staging),
+// alpha, b = B log2(e) E_a, c_j / E_a^j; rows Z.. have a = -1e300 (rate 0).
+static void fold_rows(const adk_gas &g, double *rows)
+{
+    const double log2e = 1.4426950408889634, Ea = g.consts.E_a, l2Ea = std::log2(Ea);
+    for (int k = 0; k < kCoefRows; ++k) {
+        double *r = rows + kCoefStride * k;
+        for (int f = 0; f < kCoefStride; ++f) r[f] = 0.0;
+        if (k < g.Z) {
+            const double *c = g.h_coef + 8 * k;
+            r[0] = c[0] * log2e - c[1] * l2Ea;
+            r[1] = c[1];
+            r[2] = c[2] * log2e * Ea;
+            r[3] = c[3] / Ea;
+            r[4] = c[4] / (Ea * Ea);
+            r[5] = c[5] / (Ea * Ea * Ea);
+        } else {
+            r[0] = -1e300;
+        }
+    }
 }
 
 static const StepFn kStepF64[ADK_MAX_W + 1] = {nullptr, adk_step_f64_1, adk_step_f64_2, adk_step_f64_3,
@@ -78,23 +139,29 @@ int adk_gas_create(const adk_gas_desc *desc, const adk_constants *consts, adk_ga
     *out = nullptr;
     const int st = validate_desc(desc, consts);
     if (st != ADK_OK) return st;
-    adk_gas *g = new (std::nothrow) adk_gas;
+    adk_gas *g = new (std::nothrow) adk_gas();
     if (!g) return ADK_ENOMEM;
-    std::memset(g, 0, sizeof(*g));
     g->Z = desc->Z;
     g->consts = resolve_constants(consts);
     build_coeffs(*desc, g->consts, g->h_coef);
+    for (int k = 0; k < g->Z; ++k)
+        if (g->h_coef[8 * k + 3] != 0.0 || g->h_coef[8 * k + 4] != 0.0 || g->h_coef[8 * k + 5] != 0.0)
+            g->has_poly = 1;
     if (hipGetDevice(&g->device) != hipSuccess) {
         delete g;
         return ADK_EDEVICE;
     }
-    const size_t bytes = sizeof(double) * 8 * (size_t)g->Z;
+    // device buffer: folded rows, then the log2 reduction table
+    double staging[kDevTableLen];
+    fold_rows(*g, staging);
+    log2_table(staging + kCoefRows * kCoefStride);
+    const size_t bytes = sizeof(double) * kDevTableLen;
     hipError_t e = hipMalloc((void **)&g->d_coef, bytes);
     if (e != hipSuccess) {
         delete g;
         return status_of(e);
     }
-    e = hipMemcpy(g->d_coef, g->h_coef, bytes, hipMemcpyHostToDevice);
+    e = hipMemcpy(g->d_coef, staging, bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(g->d_coef);
         delete g;
@@ -121,13 +188,13 @@ int adk_rates(const adk_gas *gas, const void *E, int64_t n, int32_t k0, int32_t 
     if (n > 0 && (!E || !W_out)) return ADK_EINVAL;
     if (k0 < 0 || nk < 1 || (int64_t)k0 + nk > gas->Z) return ADK_ERANGE;
     if (n == 0) return ADK_OK;
-    const double inv_Ea = 1.0 / gas->consts.E_a;
+    const StepArgs a = step_args(gas, 1.0, 0.0);
     if (prec == ADK_F64)
-        hipLaunchKernelGGL((rates_kernel<PolicyF64>), dim3(grid_for(n)), dim3(kBlock), 0, stream, gas->d_coef,
-                           gas->Z, k0, nk, inv_Ea, (const double *)E, (double *)W_out, n);
+        hipLaunchKernelGGL((rates_kernel<PolicyF64>), dim3(grid_for(n)), dim3(kBlock), 0, stream, a, k0, nk,
+                           (const double *)E, (double *)W_out, n);
     else
-        hipLaunchKernelGGL((rates_kernel<PolicyMixed>), dim3(grid_for(n)), dim3(kBlock), 0, stream, gas->d_coef,
-                           gas->Z, k0, nk, inv_Ea, (const float *)E, (float *)W_out, n);
+        hipLaunchKernelGGL((rates_kernel<PolicyMixed>), dim3(grid_for(n)), dim3(kBlock), 0, stream, a, k0, nk,
+                           (const float *)E, (float *)W_out, n);
     return status_of(hipGetLastError());
 }
 

@@ -1,32 +1,38 @@
 // Device-side exact solution of the windowed ionization chain over one step.
 //
 // The window holds populations N_0..N_W (levels lo..lo+W), rates x_k = W_k dt
-// for k < W and an absorbing top (x_W = 0).  With rates frozen over the step
-// (Sec. 3, constant-rate assumption) the update is N' = T N, T = exp(dt A)
-// for the lower-bidiagonal A of Eq. (3).  The eigen expansion of Eqs. (4)-(5)
-// (and its explicit 4-level form, Eqs. (6)-(9)) is, entry by entry, the
-// Bateman solution
-//     T[j][i] = (x_i x_{i+1} ... x_{j-1}) * g(x_i, ..., x_j),   j >= i,
+// for k < W and an absorbing top.  With rates frozen over the step (Sec. 3,
+// constant-rate assumption) the update is N' = T N, T = exp(dt A) for the
+// lower-bidiagonal A of Eq. (3).  The eigen expansion of Eqs. (4)-(5) (and
+// its explicit 4-level form, Eqs. (6)-(9)) is, entry by entry, the Bateman
+// solution
+//     T[j][i] = (x_i x_{i+1} ... x_{j-1}) * g(x_i, ..., x_j),   i <= j < W,
 // where g(S) = (-1)^n f[S] is the signed divided difference of f(x) = e^{-x}
-// over the n+1 points of S.  g is symmetric in its points and positive, so it
-// is evaluated on the points of each chain range sorted ascending with the
-// Newton recurrence
-//     g[a..b] = (g[a..b-1] - g[a+1..b]) / (s_b - s_a),
-// which loses accuracy only when s_b - s_a is small.  Those entries are taken
-// from the Taylor series of the divided difference about the smallest point
-// (McCurdy, Ng and Parlett 1984):
-//     g[a..b] = e^{-s_a} sum_m (-1)^m h_m(s_{a+1}-s_a, ..., s_b-s_a) / (n+m)!
-// with h_m the complete homogeneous symmetric polynomials.  This is the
-// divided-difference form of the paper's 1/(W_i - W_j) coefficients: it has
-// no division by a rate difference, so equal, zero and crossing rates need no
-// special case.
+// over the n+1 points of S.  The absorbing row follows from conservation
+// (columns of A sum to zero): T[W][i] = (1 - e^{-x_i}) - sum_{i<j<W} T[j][i],
+// with 1 - e^{-x_i} evaluated without cancellation.
 //
-// Scaling: synthetic gases reach x ~ 1e10 per step, where the products of
-// rates and the divided differences over- and underflow.  The table stores
-// ghat[a..b] = g[a..b] * prod_{k=a+1..b} m_k with m_k = max(1, s_k), whose
-// recurrence is ghat[a..b] = (ghat[a..b-1] m_b - ghat[a+1..b] m_{a+1}) /
-// (s_b - s_a), and the rate product becomes prod (x_k / m_k) times a ratio of
-// m's <= 1, so no intermediate leaves the range of the storage type.
+// Evaluation of g, which is symmetric in its points and positive:
+//   * two points a <= b: g = (e^{-a} - e^{-b}) / (b - a) when b - a is not
+//     small, else e^{-a} phi(b - a) with the series
+//     phi(d) = (1 - e^{-d})/d = sum_k (-d)^k / (k+1)!;
+//   * three or more points: the points of the range are sorted and the Newton
+//     recurrence g[a..b] = (g[a..b-1] - g[a+1..b]) / (s_b - s_a) is used
+//     where s_b - s_a is not small; clustered entries come from the Taylor
+//     series of the divided difference about the smallest point (McCurdy, Ng
+//     and Parlett 1984),
+//         g[a..b] = e^{-s_a} sum_m (-1)^m h_m(s_{a+1}-s_a, ..., s_b-s_a)/(n+m)!,
+//     h_m the complete homogeneous symmetric polynomials, summed in double
+//     until the terms are negligible for every lane of the wavefront.
+// No formula divides by a small rate difference, so equal, zero and
+// crossing rates need no special case.
+//
+// Scaling (ranges of 3+ points): synthetic gases reach x ~ 1e10 per step,
+// where products of rates and divided differences leave the float range.
+// The sorted table stores ghat[a..b] = g[a..b] prod_{k=a+1..b} m_k with
+// m_k = max(1, s_k); its recurrence is ghat[a..b] = (ghat[a..b-1] m_b -
+// ghat[a+1..b] m_{a+1}) / (s_b - s_a), and the rate product enters as
+// prod (x_k / m_k) <= 1 times a ratio of m's <= 1.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -45,12 +51,12 @@ __device__ __forceinline__ void static_for(F &&f)
 }
 
 struct InvFactTable {
-    double v[48];
+    double v[64];
     constexpr InvFactTable() : v()
     {
         double f = 1.0;
         v[0] = 1.0;
-        for (int k = 1; k < 48; ++k) {
+        for (int k = 1; k < 64; ++k) {
             f *= (double)k;
             v[k] = 1.0 / f;
         }
@@ -58,31 +64,54 @@ struct InvFactTable {
 };
 inline constexpr InvFactTable kInvFact{};
 
+// (-1)^m / (n+m)! indexed [n][m] for the Taylor branch (m is wave-uniform,
+// so the loads are scalar).
+struct TaylorCoefTable {
+    double v[10][40];
+    constexpr TaylorCoefTable() : v()
+    {
+        InvFactTable f{};
+        for (int n = 0; n < 10; ++n)
+            for (int m = 0; m < 40; ++m) v[n][m] = (m & 1) ? -f.v[n + m] : f.v[n + m];
+    }
+};
+__constant__ inline constexpr TaylorCoefTable kTaylorCoef{};
+
 // Precision policies.  `real` is the storage / main arithmetic type; the
-// Taylor branch always runs in double.
+// Taylor branch of 3+ clustered points always runs in double.
 struct PolicyF64 {
     using real = double;
-    static constexpr double kDeltaSmallW = 0.5, kDeltaLargeW = 1.0;
-    static constexpr int kMSmallW = 16, kMLargeW = 20;
+    static constexpr double kDeltaPhi = 0.1;       // 2-point: series below, difference above
+    static constexpr int kPhiDegree = 10;          // 0.1^11/12! < 1e-19
+    static constexpr double kDelta3 = 0.5;         // Taylor below this spread (ranges of <= 4 points;
+                                                   // longer ranges: TableDelta)
+    static constexpr double kTaylorRelTol = 1e-17;
+    static constexpr double kSkipProduct = 1e-18;  // rate products below this: entry is 0
     __device__ static __forceinline__ double expneg(double x) { return exp(-x); }
-    __device__ static __forceinline__ double quot(double a, double b) { return a / b; }
+    // a / b from the hardware reciprocal estimate refined by Newton steps
+    // (no IEEE division sequence; ~1 ulp)
+    __device__ static __forceinline__ double quot(double a, double b)
+    {
+        double r = __builtin_amdgcn_rcp(b);
+        r = fma(r, fma(-b, r, 1.0), r);
+        r = fma(r, fma(-b, r, 1.0), r);
+        const double q = a * r;
+        return fma(fma(-b, q, a), r, q);
+    }
 };
 
 struct PolicyMixed {
     using real = float;
-    static constexpr double kDeltaSmallW = 1.0, kDeltaLargeW = 2.0;
-    static constexpr int kMSmallW = 13, kMLargeW = 17;
+    static constexpr double kDeltaPhi = 0.5;
+    static constexpr int kPhiDegree = 8;           // 0.5^9/10! < 1e-9
+    static constexpr double kDelta3 = 1.0;
+    static constexpr double kTaylorRelTol = 1e-9;
+    static constexpr double kSkipProduct = 1e-12;
     __device__ static __forceinline__ float expneg(float x) { return __expf(-x); }
     __device__ static __forceinline__ float quot(float a, float b)
     {
         return a * __builtin_amdgcn_rcpf(b);
     }
-};
-
-template <class P, int W>
-struct DDParams {
-    static constexpr double delta = (W <= 4) ? P::kDeltaSmallW : P::kDeltaLargeW;
-    static constexpr int M = (W <= 4) ? P::kMSmallW : P::kMLargeW;
 };
 
 template <class R>
@@ -91,14 +120,36 @@ __device__ __forceinline__ R scale_of(R s)
     return s > R(1) ? s : R(1);
 }
 
-// Chain point K of the window: rate x_K for K < W, the absorbing top (0) at K = W.
-template <int W, int K, class R>
-__device__ __forceinline__ R point(const R (&x)[W])
+// phi(d) = sum_{k=0}^{K} (-d)^k / (k+1)!  (Horner)
+template <int K, class R>
+__device__ __forceinline__ R phi_series(R d)
 {
-    if constexpr (K < W)
-        return x[K];
-    else
-        return R(0);
+    R acc = R((K & 1) ? -kInvFact.v[K + 1] : kInvFact.v[K + 1]);
+    static_for<0, K>([&](auto kk) {
+        constexpr int k = K - 1 - decltype(kk)::value;
+        acc = fma(acc, d, R((k & 1) ? -kInvFact.v[k + 1] : kInvFact.v[k + 1]));
+    });
+    return acc;
+}
+
+// g of two sorted points a <= b with exps ea, eb.
+template <class P>
+__device__ __forceinline__ typename P::real g2_sorted(typename P::real a, typename P::real b,
+                                                      typename P::real ea, typename P::real eb)
+{
+    using R = typename P::real;
+    const R d = b - a;
+    const R diff = P::quot(ea - eb, d);
+    const R ser = ea * phi_series<P::kPhiDegree>(d);
+    return d >= R(P::kDeltaPhi) ? diff : ser;
+}
+
+// 1 - e^{-x} without cancellation (e = e^{-x}).
+template <class P>
+__device__ __forceinline__ typename P::real one_minus_exp(typename P::real x, typename P::real e)
+{
+    using R = typename P::real;
+    return x >= R(P::kDeltaPhi) ? R(1) - e : x * phi_series<P::kPhiDegree>(x);
 }
 
 // Compare-exchange of sorted position (A, B) carrying the exp values.
@@ -131,7 +182,6 @@ __device__ __forceinline__ void sort_points(R (&s)[L], R (&e)[L])
         cswap<1, 3>(s, e);
         cswap<1, 2>(s, e);
     } else {
-        // odd-even transposition network: L rounds
         static_for<0, L>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
             static_for<0, L / 2 + 1>([&](auto qq) {
@@ -142,50 +192,73 @@ __device__ __forceinline__ void sort_points(R (&s)[L], R (&e)[L])
     }
 }
 
-// Taylor branch for the sorted points s[A..B] (A < B), in double:
-// g[A..B] * prod_{k=A+1..B} m_k.
-template <int A, int B, int M, class R, int L>
+// Taylor branch for sorted points s[A..B] (B > A), in double, summed
+// until the terms are below the tolerance relative to the sum in every
+// active lane: returns ghat[A..B] = g[A..B] * prod_{k=A+1..B} m_k.
+template <class P, int A, int B, class R, int L>
 __device__ __forceinline__ double taylor_scaled(const R (&s)[L], R ea)
 {
-    constexpr int n = B - A;
+    constexpr int n = B - A;  // number of variables s_k - s_A, k = A+1..B
     const double base = (double)s[A];
-    double h[M + 1];
-    h[0] = 1.0;
-    static_for<1, M + 1>([&](auto mm) { h[decltype(mm)::value] = 0.0; });
+    double y[n], h[n];
     double msc = 1.0;
-    static_for<A + 1, B + 1>([&](auto vv) {
+    static_for<0, n>([&](auto vv) {
         constexpr int v = decltype(vv)::value;
-        const double y = (double)s[v] - base;
-        msc *= (double)scale_of(s[v]);
-        static_for<1, M + 1>([&](auto mm) {
-            constexpr int m = decltype(mm)::value;
-            h[m] = fma(y, h[m - 1], h[m]);
+        y[v] = (double)s[A + 1 + v] - base;
+        h[v] = 1.0;
+        msc *= (double)scale_of(s[A + 1 + v]);
+    });
+    double acc = kInvFact.v[n];
+    for (int m = 1; m < 39; ++m) {
+        // h^(1)_m = y_1 h^(1)_{m-1};  h^(k)_m = y_k h^(k)_{m-1} + h^(k-1)_m
+        h[0] *= y[0];
+        static_for<1, n>([&](auto vv) {
+            constexpr int v = decltype(vv)::value;
+            h[v] = fma(y[v], h[v], h[v - 1]);
         });
-    });
-    double tot = 0.0;
-    static_for<0, M + 1>([&](auto mm) {
-        constexpr int m = M - decltype(mm)::value;
-        constexpr double c = (m & 1) ? -kInvFact.v[n + m] : kInvFact.v[n + m];
-        tot = fma(c, h[m], tot);
-    });
-    return (double)ea * tot * msc;
+        const double term = kTaylorCoef.v[n][m] * h[n - 1];
+        acc += term;
+        if (__all(!(fabs(term) > P::kTaylorRelTol * acc))) break;
+    }
+    return (double)ea * acc * msc;
 }
 
-// Full scaled table over L sorted points: tab[a][b] = ghat[a..b] for a <= b.
-template <class P, int W, int L>
-__device__ __forceinline__ void dd_table(const typename P::real (&s)[L], const typename P::real (&e)[L],
-                                         typename P::real (&tab)[L][L])
+// Newton/Taylor switch for a table over L points.  Rounding errors of the
+// Newton recurrence grow by a factor ~ (entries' points)/spread per level, so
+// longer ranges switch to the series at larger spreads.
+template <class P, int L>
+struct TableDelta {
+    static constexpr double v = P::kDelta3 * (L <= 4 ? 1.0 : (L <= 6 ? 2.0 : 3.0));
+};
+
+// Scaled sorted table over L >= 3 points: returns ghat[0..L-1].
+template <class P, int L>
+__device__ __forceinline__ typename P::real dd_top(const typename P::real (&s)[L],
+                                                   const typename P::real (&e)[L])
 {
     using R = typename P::real;
-    constexpr R delta = (R)DDParams<P, W>::delta;
-    constexpr int M = DDParams<P, W>::M;
+    constexpr R delta = R(TableDelta<P, L>::v);
+    R tab[L][L];
     R msc[L];
     static_for<0, L>([&](auto aa) {
         constexpr int a = decltype(aa)::value;
-        tab[a][a] = e[a];
         msc[a] = scale_of(s[a]);
     });
-    static_for<1, L>([&](auto ll) {
+    static_for<0, L - 1>([&](auto aa) {
+        constexpr int a = decltype(aa)::value;
+        if constexpr (L <= 4) {
+            tab[a][a + 1] = g2_sorted<P>(s[a], s[a + 1], e[a], e[a + 1]) * msc[a + 1];
+        } else {
+            const R d = s[a + 1] - s[a];
+            R t;
+            if (d >= delta)
+                t = P::quot(e[a] - e[a + 1], d) * msc[a + 1];
+            else
+                t = (R)taylor_scaled<P, a, a + 1>(s, e[a]);
+            tab[a][a + 1] = t;
+        }
+    });
+    static_for<2, L>([&](auto ll) {
         constexpr int len = decltype(ll)::value;
         static_for<0, L - len>([&](auto aa) {
             constexpr int a = decltype(aa)::value;
@@ -195,110 +268,213 @@ __device__ __forceinline__ void dd_table(const typename P::real (&s)[L], const t
             if (spread >= delta) {
                 t = P::quot(tab[a][b - 1] * msc[b] - tab[a + 1][b] * msc[a + 1], spread);
             } else {
-                t = (R)taylor_scaled<a, b, M>(s, e[a]);
+                t = (R)taylor_scaled<P, a, b>(s, e[a]);
             }
             tab[a][b] = t;
         });
     });
+    return tab[0][L - 1];
 }
 
-// Accumulate out[j] += T[j][i] N[i] for all i <= j of the window.
-// x[0..W-1] rates, ex[0..W] = exp(-x) with ex[W] = 1.
-// General path: every chain range is sorted on its own.
-template <class P, int W>
-__device__ __forceinline__ void chain_apply_general(const typename P::real (&x)[W],
-                                                    const typename P::real (&ex)[W + 1],
-                                                    const double (&N)[W + 1], double (&out)[W + 1])
+// T[J][I] for the chain range [I..J] of rate points (J - I >= 2), 0 when the
+// rate product is negligible in every lane of the wavefront.
+template <class P, int W, int I, int J>
+__device__ __forceinline__ double range_entry(const typename P::real (&x)[W], const typename P::real (&ex)[W])
 {
     using R = typename P::real;
-    static_for<0, W + 1>([&](auto jj) {
-        constexpr int j = decltype(jj)::value;
-        out[j] = (double)ex[j] * N[j];
+    constexpr int L = J - I + 1;
+    double prod = 1.0;
+    R rho = R(1);  // prod x_k / max(1, x_k) = prod min(x_k, 1)
+    static_for<I, J>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        prod *= (double)x[k];
+        rho *= x[k] < R(1) ? x[k] : R(1);
     });
-    static_for<0, W>([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        R rho = R(1);  // prod_{k=i}^{j-1} x_k / m_k
-        static_for<i + 1, W + 1>([&](auto jj) {
-            constexpr int j = decltype(jj)::value;
-            constexpr int L = j - i + 1;
-            rho *= x[j - 1] / scale_of(x[j - 1]);
-            R s[L], e[L];
-            static_for<0, L>([&](auto kk) {
-                constexpr int k = decltype(kk)::value;
-                s[k] = point<W, i + k>(x);
-                e[k] = ex[i + k];
-            });
-            sort_points<L>(s, e);
-            R tab[L][L];
-            dd_table<P, W, L>(s, e, tab);
-            const R mj = scale_of(point<W, j>(x));
-            const double Tji = (double)rho * (double)tab[0][L - 1] * ((double)scale_of(s[0]) / (double)mj);
-            out[j] = fma(Tji, N[i], out[j]);
-        });
-    });
-}
-
-// Monotone path: valid when x_0 >= x_1 >= ... >= x_{W-1} >= 0, so every chain
-// range is already sorted (descending) and one table over the reversed points
-// serves all ranges: chain range [i..j] is sorted range [W-j .. W-i].
-template <class P, int W>
-__device__ __forceinline__ void chain_apply_monotone(const typename P::real (&x)[W],
-                                                     const typename P::real (&ex)[W + 1],
-                                                     const double (&N)[W + 1], double (&out)[W + 1])
-{
-    using R = typename P::real;
-    constexpr int L = W + 1;
+    if (!__any(prod >= P::kSkipProduct)) return 0.0;
     R s[L], e[L];
     static_for<0, L>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
-        constexpr int c = W - k;  // chain index of sorted position k
-        s[k] = point<W, c>(x);
-        e[k] = ex[c];
+        s[k] = x[I + k];
+        e[k] = ex[I + k];
     });
-    R tab[L][L];
-    dd_table<P, W, L>(s, e, tab);
-    static_for<0, W + 1>([&](auto jj) {
-        constexpr int j = decltype(jj)::value;
-        out[j] = (double)ex[j] * N[j];
-    });
-    static_for<0, W>([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        R rho = R(1);
-        static_for<i + 1, W + 1>([&](auto jj) {
-            constexpr int j = decltype(jj)::value;
-            rho *= x[j - 1] / scale_of(x[j - 1]);
-            const double Tji = (double)rho * (double)tab[W - j][W - i];
-            out[j] = fma(Tji, N[i], out[j]);
-        });
-    });
+    sort_points<L>(s, e);
+    const R top = dd_top<P, L>(s, e);
+    const R ratio = P::quot(scale_of(s[0]), scale_of(x[J]));
+    return (double)rho * (double)top * (double)ratio;
 }
 
-// N' = T N for one cell.  Wave-uniform dispatch: identity when no lane of the
-// wave has a nonzero rate, the single-table path when every lane's rates are
-// non-increasing along the window, the general path otherwise.
+// g of two points in any order.
+template <class P>
+__device__ __forceinline__ typename P::real g_pair(typename P::real a, typename P::real b, typename P::real ea,
+                                                   typename P::real eb)
+{
+    using R = typename P::real;
+    const bool sw = a > b;
+    const R lo = sw ? b : a, hi = sw ? a : b;
+    const R elo = sw ? eb : ea, ehi = sw ? ea : eb;
+    return g2_sorted<P>(lo, hi, elo, ehi);
+}
+
+// Taylor series of g over three points mn <= md <= mx (double, adaptive).
+template <class P, class R>
+__device__ __forceinline__ double taylor3(R mn, R md, R mx, R emn)
+{
+    const double y1 = (double)md - (double)mn, y2 = (double)mx - (double)mn;
+    double h1 = 1.0, h2 = 1.0, acc = 0.5;
+    for (int m = 1; m < 39; ++m) {
+        h1 *= y1;
+        h2 = fma(y2, h2, h1);
+        const double term = kTaylorCoef.v[2][m] * h2;
+        acc += term;
+        if (__all(!(fabs(term) > P::kTaylorRelTol * acc))) break;
+    }
+    return (double)emn * acc;
+}
+
+// Windows of up to three rates: the only range of three points is [0..2],
+// whose divided difference reuses the pair values of the neighbouring
+// entries.  With rates capped at 1e12 no product leaves the float range.
+template <class P, int W>
+__device__ __forceinline__ void chain_apply_small(const typename P::real (&x)[W], const double (&N)[W + 1],
+                                                  double (&out)[W + 1])
+{
+    using R = typename P::real;
+    R ex[W];
+    double om[W];
+    static_for<0, W>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        ex[k] = P::expneg(x[k]);
+        om[k] = (double)one_minus_exp<P>(x[k], ex[k]);
+    });
+    if constexpr (W == 1) {
+        out[0] = (double)ex[0] * N[0];
+        out[1] = fma(om[0], N[0], N[1]);
+    } else if constexpr (W == 2) {
+        const double T10 = (double)(x[0] * g_pair<P>(x[0], x[1], ex[0], ex[1]));
+        out[0] = (double)ex[0] * N[0];
+        out[1] = fma(T10, N[0], (double)ex[1] * N[1]);
+        double t0 = om[0] - T10;
+        t0 = t0 < 0.0 ? 0.0 : t0;
+        out[2] = fma(t0, N[0], fma(om[1], N[1], N[2]));
+    } else {
+        const R x0 = x[0], x1 = x[1], x2 = x[2];
+        const R e0 = ex[0], e1 = ex[1], e2 = ex[2];
+        const R g01 = g_pair<P>(x0, x1, e0, e1);
+        const R g12 = g_pair<P>(x1, x2, e1, e2);
+        const double T10 = (double)(x0 * g01), T21 = (double)(x1 * g12);
+        double T20 = 0.0;
+        const double prod = (double)x0 * (double)x1;
+        if (__any(prod >= P::kSkipProduct)) {
+            // g[S] = (g[S \ max] - g[S \ min]) / (max - min)
+            const bool x1_mid = (x0 <= x1 && x1 <= x2) || (x0 >= x1 && x1 >= x2);
+            R g02 = R(0);
+            if (__any(!x1_mid)) g02 = g_pair<P>(x0, x2, e0, e2);
+            const int imax = (x0 >= x1 && x0 >= x2) ? 0 : (x1 >= x2 ? 1 : 2);
+            const int imin = (x0 <= x1 && x0 <= x2) ? 0 : (x1 <= x2 ? 1 : 2);
+            // pair without point m: m = 0 -> (1,2), 1 -> (0,2), 2 -> (0,1)
+            const R g_lo = imax == 0 ? g12 : (imax == 1 ? g02 : g01);
+            const R g_hi = imin == 0 ? g12 : (imin == 1 ? g02 : g01);
+            const R mn = x0 < x1 ? (x0 < x2 ? x0 : x2) : (x1 < x2 ? x1 : x2);
+            const R mx = x0 > x1 ? (x0 > x2 ? x0 : x2) : (x1 > x2 ? x1 : x2);
+            const R spread = mx - mn;
+            R g3;
+            if (spread >= R(P::kDelta3)) {
+                g3 = P::quot(g_lo - g_hi, spread);
+            } else {
+                const R a01 = x0 < x1 ? x0 : x1, b01 = x0 < x1 ? x1 : x0;
+                const R md = b01 < x2 ? b01 : (a01 > x2 ? a01 : x2);
+                const R emn = imin == 0 ? e0 : (imin == 1 ? e1 : e2);
+                g3 = (R)taylor3<P>(mn, md, mx, emn);
+            }
+            T20 = prod * (double)g3;
+        }
+        out[0] = (double)e0 * N[0];
+        out[1] = fma(T10, N[0], (double)e1 * N[1]);
+        out[2] = fma(T20, N[0], fma(T21, N[1], (double)e2 * N[2]));
+        double t0 = om[0] - T10 - T20, t1 = om[1] - T21;
+        t0 = t0 < 0.0 ? 0.0 : t0;
+        t1 = t1 < 0.0 ? 0.0 : t1;
+        out[3] = fma(t0, N[0], fma(t1, N[1], fma(om[2], N[2], N[3])));
+    }
+}
+
+template <class P, int W>
+__device__ __forceinline__ void chain_apply_general(const typename P::real (&x)[W], const double (&N)[W + 1],
+                                                    double (&out)[W + 1]);
+
+// N' = T N for one cell.  Identity when no lane of the wavefront has a
+// nonzero rate.
 template <class P, int W>
 __device__ __forceinline__ void chain_apply(const typename P::real (&x)[W], const double (&N)[W + 1],
                                             double (&out)[W + 1])
 {
     using R = typename P::real;
-    bool active = false, mono = true;
-    static_for<0, W>([&](auto kk) {
-        constexpr int k = decltype(kk)::value;
-        active |= !(x[k] == R(0));
-        if constexpr (k + 1 < W) mono &= (x[k] >= x[k + 1]);
-    });
+    bool active = false;
+    static_for<0, W>([&](auto kk) { active |= !(x[decltype(kk)::value] == R(0)); });
     if (!__any(active)) {
         static_for<0, W + 1>([&](auto jj) { out[decltype(jj)::value] = N[decltype(jj)::value]; });
         return;
     }
-    R ex[W + 1];
-    static_for<0, W>([&](auto kk) { ex[decltype(kk)::value] = P::expneg(x[decltype(kk)::value]); });
-    ex[W] = R(1);
-    if (__all(mono)) {
-        chain_apply_monotone<P, W>(x, ex, N, out);
+    if constexpr (W <= 3) {
+        chain_apply_small<P, W>(x, N, out);
     } else {
-        chain_apply_general<P, W>(x, ex, N, out);
+        chain_apply_general<P, W>(x, N, out);
     }
+}
+
+// Windows of four or more rates: every range of three or more points is
+// sorted and tabulated on its own.
+template <class P, int W>
+__device__ __forceinline__ void chain_apply_general(const typename P::real (&x)[W], const double (&N)[W + 1],
+                                                    double (&out)[W + 1])
+{
+    using R = typename P::real;
+    R ex[W];
+    double om[W];
+    static_for<0, W>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        ex[k] = P::expneg(x[k]);
+        om[k] = (double)one_minus_exp<P>(x[k], ex[k]);
+    });
+    // T[j][i] for i <= j < W
+    double T[W][W];
+    static_for<0, W>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        T[i][i] = (double)ex[i];
+        if constexpr (i + 1 < W) {
+            const R a = x[i], b = x[i + 1];
+            const bool sw = a > b;
+            const R lo = sw ? b : a, hi = sw ? a : b;
+            const R elo = sw ? ex[i + 1] : ex[i], ehi = sw ? ex[i] : ex[i + 1];
+            T[i + 1][i] = (double)(x[i] * g2_sorted<P>(lo, hi, elo, ehi));
+        }
+    });
+    static_for<2, W>([&](auto dd) {
+        constexpr int d = decltype(dd)::value;
+        static_for<0, W - d>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            T[i + d][i] = range_entry<P, W, i, i + d>(x, ex);
+        });
+    });
+    static_for<0, W>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        double acc = T[j][j] * N[j];
+        static_for<0, j>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            acc = fma(T[j][i], N[i], acc);
+        });
+        out[j] = acc;
+    });
+    // absorbing top: column sums of T are one
+    double top = N[W];
+    static_for<0, W>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        double t = om[i];
+        static_for<i + 1, W>([&](auto jj) { t -= T[decltype(jj)::value][i]; });
+        t = t < 0.0 ? 0.0 : t;  // rounding only; NaN passes through
+        top = fma(t, N[i], top);
+    });
+    out[W] = top;
 }
 
 }  // namespace adk

@@ -94,6 +94,42 @@ void build_coeffs(const adk_gas_desc &d, const adk_constants &c, double *coef)
     }
 }
 
+// Field below which the rate of every level is below 1e-30 per step.  Per
+// level the base-2 exponent t(u) = a2 + alpha log2 u - b2/u (u = E/E_a)
+// increases up to u* = b2 ln2 / (-alpha) (all u when alpha >= 0), and the
+// m-average factor increases with u, so ln(W dt) is increasing on (0, u*]:
+// bisection on ln u gives the crossing of ln(1e-30), or u* when the level
+// stays below it.  The minimum over the levels (less a margin) is returned.
+double field_cutoff(const adk_gas &g, double dt)
+{
+    const double target = std::log(1e-30);
+    const double ln2 = std::log(2.0), log2e = 1.0 / ln2;
+    double cut = INFINITY;
+    for (int k = 0; k < g.Z; ++k) {
+        const double *r = g.h_coef + 8 * k;
+        const double a2 = (r[0] + std::log(dt)) * log2e, al = r[1], b2 = r[2] * log2e;
+        auto lnx = [&](double lu) {
+            const double u = std::exp(lu);
+            const double poly = 1.0 + u * (r[3] + u * (r[4] + u * r[5]));
+            return (a2 + al * lu * log2e - b2 / u) * ln2 + std::log(poly);
+        };
+        const double lu_star = al < 0.0 ? std::log(b2 * ln2 / -al) : std::log(1e8);
+        double lo = std::log(1e-30), hi = lu_star;
+        if (!(lnx(hi) > target)) {
+            cut = std::fmin(cut, std::exp(hi));
+            continue;
+        }
+        if (lnx(lo) > target) return 0.0;  // no usable cutoff
+        for (int it = 0; it < 200 && hi - lo > 1e-12; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            (lnx(mid) > target ? hi : lo) = mid;
+        }
+        cut = std::fmin(cut, std::exp(lo));
+    }
+    if (!std::isfinite(cut)) cut = 1e8;
+    return cut * g.consts.E_a * (1.0 - 1e-9);
+}
+
 }  // namespace adk
 
 extern "C" int adk_gas_coeffs(const adk_gas_desc *desc, const adk_constants *consts, double *coef_out)

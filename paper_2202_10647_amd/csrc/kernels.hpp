@@ -21,33 +21,89 @@
 namespace adk {
 
 constexpr int kBlock = 256;
-constexpr int kCoefStride = 6;           // LDS: A + ln dt, alpha, B, c1, c2, c3
 constexpr double kLog2e = 1.4426950408889634;
-constexpr double kXMax = 1e30;           // cap of W dt (keeps inf out of the solver)
+// LDS row per level (base-2 exponent of W dt, field terms folded in):
+//   t = a + alpha log2|E| - b / |E|,   W dt = 2^t (1 + c1 |E| + c2 |E|^2 + c3 |E|^3)
+// a = (A + ln dt) log2(e) - alpha log2(E_a), b = B log2(e) E_a, c_j = c_j,orig / E_a^j.
+// Rows Z..Z+kPadRows-1 hold a = -1e300 (rate 0), so windows reaching past
+// level Z-1 need no per-level test.
+constexpr int kCoefStride = 6;
+constexpr int kPadRows = 8;
+constexpr int kCoefRows = ADK_MAX_Z + kPadRows;
+// log2 reduction table: 64 pairs (c_j, -log2 c_j), see fast_log2.
+constexpr int kLogTable = 64;
+// Cap of W dt.  Replacing a rate x_i > cap by the cap changes T by less than
+// 0.37 / cap (the level empties either way; only x_{i+1}/x_i enters).
+template <class R>
+inline constexpr R kXMax = R(1e15);
+template <>
+inline constexpr float kXMax<float> = 1e12f;
 
-// Per-cell field terms of Eq. (1), in double: L = ln(E/E_a), R = E_a/E, u = E/E_a.
-struct Field {
-    double L, R, u;
-    bool zero;
+// Launch arguments shared by the step kernels.
+struct StepArgs {
+    const double *tab;   // device table of the gas (kDevTableLen doubles)
+    int Z;
+    int has_poly;        // some level averages over m (c_j != 0)
+    double ln_dt;
+    double eps;
+    double E_cut;        // below this |E| every rate of the gas is < 1e-30 per step
 };
 
-__device__ __forceinline__ Field field_terms(double E, double inv_Ea)
+// log2 of a positive finite double v: v = m 2^k with m in [1/2, 1); the top
+// six fraction bits of m select c_j ~ 1/m from the table, r = m c_j - 1 is
+// formed with one rounding (|r| < 0.0078) and log2(1 + r) is a short series,
+// so log2 v = k + (-log2 c_j) + r q(r).  D terms: D = 7 gives ~1e-19 (FP64
+// path), D = 4 gives ~5e-12 (float path, where only ~1e-10 is needed).
+template <int D>
+__device__ __forceinline__ double fast_log2(double v, const double *slog)
 {
+    int k;
+    const double m = frexp(v, &k);
+    const unsigned hi = (unsigned)(__double_as_longlong(m) >> 32);
+    const int j = (hi >> 14) & (kLogTable - 1);
+    const double c = slog[2 * j], nlc = slog[2 * j + 1];
+    const double r = fma(m, c, -1.0);
+    double q = ((D & 1) ? -kLog2e : kLog2e) / (D + 1);
+    static_for<0, D>([&](auto ii) {
+        constexpr int i = D - 1 - decltype(ii)::value;
+        q = fma(q, r, ((i & 1) ? -kLog2e : kLog2e) / (i + 1));
+    });
+    return fma(r, q, (double)k + nlc);
+}
+
+// 1/v from the hardware estimate and two Newton steps.
+__device__ __forceinline__ double fast_rcp(double v)
+{
+    double r = __builtin_amdgcn_rcp(v);
+    r = fma(r, fma(-v, r, 1.0), r);
+    return fma(r, fma(-v, r, 1.0), r);
+}
+
+// Per-cell field terms of Eq. (1) in double: lg = log2|E|, inv = 1/|E|.
+struct Field {
+    double lg, inv, E;
+};
+
+template <int D>
+__device__ __forceinline__ Field field_terms(double EL, const double *slog)
+{
+    // |E| = 0 (and non-finite |E|, whose cell is overwritten with NaN at the
+    // end) is replaced by a tiny field: every rate underflows to exactly 0.
     Field f;
-    const double EL = fabs(E);
-    f.u = EL * inv_Ea;
-    f.L = log(f.u);
-    f.R = 1.0 / f.u;
-    f.zero = (EL == 0.0);
+    f.E = EL > 1e-280 ? (EL <= 1e300 ? EL : 1.0) : 1e-280;
+    f.lg = fast_log2<D>(f.E, slog);
+    f.inv = fast_rcp(f.E);
     return f;
 }
 
-// Exponent of W_k dt (or of W_k when the LDS table holds A without ln dt) and
-// the m-average polynomial, from the LDS row of level k.
-__device__ __forceinline__ double rate_exponent(const double *row, const Field &f, double &poly)
+__device__ __forceinline__ double rate_exponent2(const double *row, const Field &f)
 {
-    poly = fma(fma(fma(row[5], f.u, row[4]), f.u, row[3]), f.u, 1.0);
-    return fma(-row[2], f.R, fma(row[1], f.L, row[0]));
+    return fma(-row[2], f.inv, fma(row[1], f.lg, row[0]));
+}
+
+__device__ __forceinline__ double mavg_poly(const double *row, const Field &f)
+{
+    return fma(fma(fma(row[5], f.E, row[4]), f.E, row[3]), f.E, 1.0);
 }
 
 template <class P>
@@ -55,86 +111,115 @@ struct RateEval;
 
 template <>
 struct RateEval<PolicyF64> {
-    __device__ static __forceinline__ double x_of(const double *row, const Field &f)
+    static constexpr int kLogTerms = 7;
+    __device__ static __forceinline__ double x_of(const double *row, const Field &f, bool has_poly)
     {
-        double poly;
-        const double y = rate_exponent(row, f, poly);
-        double x = exp(y) * poly;
-        x = f.zero ? 0.0 : x;
-        return x < kXMax ? x : (x == x ? kXMax : x);
+        double x = exp2(rate_exponent2(row, f));
+        if (has_poly) x *= mavg_poly(row, f);
+        return fmin(x, kXMax<double>);
     }
 };
 
 template <>
 struct RateEval<PolicyMixed> {
-    __device__ static __forceinline__ float x_of(const double *row, const Field &f)
+    static constexpr int kLogTerms = 4;
+    __device__ static __forceinline__ float x_of(const double *row, const Field &f, bool has_poly)
     {
-        double poly;
-        const double y = rate_exponent(row, f, poly);
         // 2^t with t split exactly in double: the integer part goes to the
-        // exponent, only |f| <= 1/2 passes through the float exp2, so the
-        // relative error stays ~1e-7 whatever the size of the exponent.
-        double t = y * kLog2e;
-        t = t < 120.0 ? t : (t == t ? 120.0 : t);
-        t = t > -160.0 ? t : (t == t ? -160.0 : t);
+        // exponent and only |fr| <= 1/2 passes through the float exp2, so the
+        // relative error stays a few float ulps whatever the size of t.
+        const double t = fmax(fmin(rate_exponent2(row, f), 45.0), -160.0);
         const double ti = rint(t);
-        const float fr = (float)(t - ti);
-        float x = ldexpf(exp2f(fr), (int)ti) * (float)poly;
-        x = f.zero ? 0.0f : x;
-        return x < (float)kXMax ? x : (x == x ? (float)kXMax : x);
+        float x = ldexpf(exp2f((float)(t - ti)), (int)ti);
+        if (has_poly) x *= (float)mavg_poly(row, f);
+        return fminf(x, kXMax<float>);
     }
 };
 
-__device__ __forceinline__ void stage_coefficients(double *sc, const double *__restrict__ coef, int Z,
-                                                   double ln_dt)
+// Stage the prefolded coefficient rows (ln dt added to column 0) and the
+// log2 table into LDS.  Device layout of a gas: kCoefRows x kCoefStride
+// folded rows (see gas_table.cpp: fold_rows), then the 64 x 2 log2 table.
+constexpr int kDevTableLen = kCoefRows * kCoefStride + 2 * kLogTable;
+
+__device__ __forceinline__ void stage_coefficients(double *sc, const double *__restrict__ tab, double ln_dt)
 {
-    for (int t = threadIdx.x; t < Z * kCoefStride; t += blockDim.x) {
-        const int k = t / kCoefStride, f = t - k * kCoefStride;
-        double v = coef[k * 8 + f];
-        if (f == 0) v += ln_dt;
-        sc[t] = v;
+    const double add = ln_dt * kLog2e;
+    for (int t = threadIdx.x; t < kDevTableLen; t += blockDim.x) {
+        const double v = tab[t];
+        sc[t] = (t < kCoefRows * kCoefStride && t % kCoefStride == 0) ? v + add : v;
     }
     __syncthreads();
 }
 
-// Rates of the W window levels p..p+W-1 (0 past level Z-1).
+// Rates of the W window levels p..p+W-1 (0 past level Z-1: padded rows).
 template <class P, int W>
-__device__ __forceinline__ void window_rates(const double *sc, int Z, int p, const Field &f,
+__device__ __forceinline__ void window_rates(const double *sc, int p, const Field &f, bool has_poly,
                                              typename P::real (&x)[W])
 {
-    using R = typename P::real;
     static_for<0, W>([&](auto ss) {
         constexpr int s = decltype(ss)::value;
-        const int k = p + s;
-        const int kk = k < Z ? k : Z - 1;
-        const R v = RateEval<P>::x_of(sc + kk * kCoefStride, f);
-        x[s] = k < Z ? v : R(0);
+        x[s] = RateEval<P>::x_of(sc + (p + s) * kCoefStride, f, has_poly);
     });
 }
 
 // ---------------------------------------------------------------------------
 // ionize_step, compact layout: pops[(W+1)][n], slot s = level lo + s.
+// Grid-stride loop, software pipelined: the loads of a lane's next cell are
+// issued before the current cell is computed, so their latency overlaps the
+// arithmetic.
+template <class R, int W>
+struct CellLoad {
+    R E;
+    R N[W + 1];
+    uint8_t lo;
+};
+
+template <class R, int W>
+__device__ __forceinline__ void load_cell(CellLoad<R, W> &d, const R *__restrict__ E, const R *__restrict__ pops,
+                                          const uint8_t *__restrict__ lo, int64_t n, int64_t c)
+{
+    d.E = E[c];
+    static_for<0, W + 1>([&](auto ss) {
+        constexpr int s = decltype(ss)::value;
+        d.N[s] = pops[(int64_t)s * n + c];
+    });
+    d.lo = lo[c];
+}
+
 template <class P, int W>
-__global__ __launch_bounds__(kBlock) void step_compact_kernel(
-    const double *__restrict__ coef, int Z, double ln_dt, double inv_Ea, double eps,
-    const typename P::real *__restrict__ E, typename P::real *__restrict__ pops,
-    uint8_t *__restrict__ lo, int64_t n)
+__global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const typename P::real *__restrict__ E,
+                                                              typename P::real *__restrict__ pops,
+                                                              uint8_t *__restrict__ lo, int64_t n)
 {
     using R = typename P::real;
-    __shared__ double sc[ADK_MAX_Z * kCoefStride];
-    stage_coefficients(sc, coef, Z, ln_dt);
+    __shared__ double sc[kDevTableLen];
+    const double *slog = sc + kCoefRows * kCoefStride;
+    stage_coefficients(sc, a.tab, a.ln_dt);
+    const int Z = a.Z;
+    const bool has_poly = a.has_poly != 0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < n; c += stride) {
-        const double Ec = (double)E[c];
-        int p = lo[c];
+    int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    CellLoad<R, W> nxt;
+    if (c < n) load_cell(nxt, E, pops, lo, n, c);
+    for (; c < n; c += stride) {
+        const CellLoad<R, W> cur = nxt;
+        if (c + stride < n) load_cell(nxt, E, pops, lo, n, c + stride);
+        const double EL = fabs((double)cur.E);
+        int p = cur.lo;
         p = p < Z ? p : Z;
+        // whole wavefront below the field cutoff and no shift due: T = I
+        if (__all(EL < a.E_cut && (double)cur.N[0] >= a.eps)) {
+            static_for<0, W + 1>([&](auto ss) {
+                constexpr int s = decltype(ss)::value;
+                pops[(int64_t)s * n + c] = cur.N[s];
+            });
+            lo[c] = (uint8_t)p;
+            continue;
+        }
         double N[W + 1];
-        static_for<0, W + 1>([&](auto ss) {
-            constexpr int s = decltype(ss)::value;
-            N[s] = (double)pops[(int64_t)s * n + c];
-        });
+        static_for<0, W + 1>([&](auto ss) { N[decltype(ss)::value] = (double)cur.N[decltype(ss)::value]; });
         // window shift at the start of the step; residual folded upward
-        while (p < Z && N[0] < eps) {
+        while (p < Z && N[0] < a.eps) {
             N[0] += N[1];
             static_for<1, W>([&](auto ss) {
                 constexpr int s = decltype(ss)::value;
@@ -143,14 +228,18 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(
             N[W] = 0.0;
             ++p;
         }
-        const Field f = field_terms(Ec, inv_Ea);
+        const Field f = field_terms<RateEval<P>::kLogTerms>(EL, slog);
         R x[W];
-        window_rates<P, W>(sc, Z, p, f, x);
+        window_rates<P, W>(sc, p, f, has_poly, x);
         double out[W + 1];
         chain_apply<P, W>(x, N, out);
+        const bool finite = EL <= 1.7976931348623157e308;
         static_for<0, W + 1>([&](auto ss) {
             constexpr int s = decltype(ss)::value;
-            pops[(int64_t)s * n + c] = (R)out[s];
+            // slots past level Z hold no population (rounding of the top row);
+            // a non-finite field makes the whole window NaN
+            const R v = finite ? (R)out[s] : R(NAN);
+            pops[(int64_t)s * n + c] = (p + s <= Z) ? v : R(0);
         });
         lo[c] = (uint8_t)p;
     }
@@ -158,23 +247,25 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(
 
 // ionize_step, full layout: pops[(Z+1)][n], row k = level k.
 template <class P, int W>
-__global__ __launch_bounds__(kBlock) void step_full_kernel(
-    const double *__restrict__ coef, int Z, double ln_dt, double inv_Ea, double eps,
-    const typename P::real *__restrict__ E, typename P::real *__restrict__ pops,
-    uint8_t *__restrict__ lo, int64_t n)
+__global__ __launch_bounds__(kBlock) void step_full_kernel(StepArgs a, const typename P::real *__restrict__ E,
+                                                           typename P::real *__restrict__ pops,
+                                                           uint8_t *__restrict__ lo, int64_t n)
 {
     using R = typename P::real;
-    __shared__ double sc[ADK_MAX_Z * kCoefStride];
-    stage_coefficients(sc, coef, Z, ln_dt);
+    __shared__ double sc[kDevTableLen];
+    const double *slog = sc + kCoefRows * kCoefStride;
+    stage_coefficients(sc, a.tab, a.ln_dt);
+    const int Z = a.Z;
+    const bool has_poly = a.has_poly != 0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < n; c += stride) {
-        const double Ec = (double)E[c];
+        const double EL = fabs((double)E[c]);
         int p = lo[c];
         p = p < Z ? p : Z;
         const int p0 = p;
         double N[W + 1];
         N[0] = (double)pops[(int64_t)p * n + c];
-        while (p < Z && N[0] < eps) {
+        while (p < Z && N[0] < a.eps) {
             N[0] += (double)pops[(int64_t)(p + 1) * n + c];
             ++p;
         }
@@ -182,15 +273,20 @@ __global__ __launch_bounds__(kBlock) void step_full_kernel(
             constexpr int s = decltype(ss)::value;
             N[s] = (p + s <= Z) ? (double)pops[(int64_t)(p + s) * n + c] : 0.0;
         });
-        const Field f = field_terms(Ec, inv_Ea);
-        R x[W];
-        window_rates<P, W>(sc, Z, p, f, x);
         double out[W + 1];
-        chain_apply<P, W>(x, N, out);
+        if (__all(EL < a.E_cut)) {
+            static_for<0, W + 1>([&](auto ss) { out[decltype(ss)::value] = N[decltype(ss)::value]; });
+        } else {
+            const Field f = field_terms<RateEval<P>::kLogTerms>(EL, slog);
+            R x[W];
+            window_rates<P, W>(sc, p, f, has_poly, x);
+            chain_apply<P, W>(x, N, out);
+        }
+        const bool finite = EL <= 1.7976931348623157e308;
         for (int k = p0; k < p; ++k) pops[(int64_t)k * n + c] = R(0);
         static_for<0, W + 1>([&](auto ss) {
             constexpr int s = decltype(ss)::value;
-            if (p + s <= Z) pops[(int64_t)(p + s) * n + c] = (R)out[s];
+            if (p + s <= Z) pops[(int64_t)(p + s) * n + c] = finite ? (R)out[s] : R(NAN);
         });
         lo[c] = (uint8_t)p;
     }
@@ -210,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void chain_advance_kernel(const typename P:
         static_for<0, W>([&](auto ss) {
             constexpr int s = decltype(ss)::value;
             double v = (double)Wr[(int64_t)s * n + c] * dt;
-            v = v < kXMax ? v : (v == v ? kXMax : v);
+            v = v < (double)kXMax<R> ? v : (v == v ? (double)kXMax<R> : v);
             x[s] = (R)v;
         });
         static_for<0, W + 1>([&](auto ss) {
@@ -226,37 +322,66 @@ __global__ __launch_bounds__(kBlock) void chain_advance_kernel(const typename P:
     }
 }
 
-// Rates W_out[j][i] = W_{k0+j}(E[i]) in 1/s (table staged with ln dt = 0).
+// Rates W_out[j][i] = W_{k0+j}(E[i]) in 1/s (table staged with ln dt = 0,
+// evaluated in double and rounded to the output type).
 template <class P>
-__global__ __launch_bounds__(kBlock) void rates_kernel(const double *__restrict__ coef, int Z, int k0, int nk,
-                                                       double inv_Ea, const typename P::real *__restrict__ E,
+__global__ __launch_bounds__(kBlock) void rates_kernel(StepArgs a, int k0, int nk,
+                                                       const typename P::real *__restrict__ E,
                                                        typename P::real *__restrict__ Wout, int64_t n)
 {
-    __shared__ double sc[ADK_MAX_Z * kCoefStride];
-    stage_coefficients(sc, coef, Z, 0.0);
+    __shared__ double sc[kDevTableLen];
+    const double *slog = sc + kCoefRows * kCoefStride;
+    stage_coefficients(sc, a.tab, 0.0);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        const Field f = field_terms((double)E[i], inv_Ea);
-        for (int j = 0; j < nk; ++j) Wout[(int64_t)j * n + i] = RateEval<P>::x_of(sc + (k0 + j) * kCoefStride, f);
+        const double EL = fabs((double)E[i]);
+        const Field f = field_terms<7>(EL, slog);
+        const bool finite = EL <= 1.7976931348623157e308;
+        for (int j = 0; j < nk; ++j) {
+            const double *row = sc + (k0 + j) * kCoefStride;
+            double x = exp2(rate_exponent2(row, f));
+            if (a.has_poly) x *= mavg_poly(row, f);
+            Wout[(int64_t)j * n + i] = (typename P::real)(finite ? x : NAN);
+        }
     }
 }
 
 // Launch helpers (one instantiation per precision and window width).
+int num_cus();
 int grid_for(int64_t n);
+StepArgs step_args(const adk_gas *g, double dt, double eps);
+
+// Grid of a grid-stride kernel: every workgroup resident at once (occupancy
+// from the compiled resource usage), no more groups than cells need.
+template <class K>
+int resident_grid(K kernel, int64_t n)
+{
+    static int per_cu = 0;
+    if (per_cu <= 0) {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, kBlock, 0) != hipSuccess || b <= 0) b = 4;
+        per_cu = b;
+    }
+    const int64_t need = (n + kBlock - 1) / kBlock;
+    const int64_t cap = (int64_t)num_cus() * per_cu;
+    return (int)(need < cap ? need : cap);
+}
 
 template <class P, int W>
 hipError_t launch_step(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,
                        const adk_window *win, hipStream_t st)
 {
     using R = typename P::real;
-    const int grid = grid_for(n);
-    const double ln_dt = std::log(dt), inv_Ea = 1.0 / g->consts.E_a;
-    if (win->layout == ADK_LAYOUT_COMPACT)
-        hipLaunchKernelGGL((step_compact_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, g->d_coef, g->Z, ln_dt,
-                           inv_Ea, win->eps, (const R *)E, (R *)pops, lo, n);
-    else
-        hipLaunchKernelGGL((step_full_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, g->d_coef, g->Z, ln_dt,
-                           inv_Ea, win->eps, (const R *)E, (R *)pops, lo, n);
+    const StepArgs a = step_args(g, dt, win->eps);
+    if (win->layout == ADK_LAYOUT_COMPACT) {
+        const int grid = resident_grid(step_compact_kernel<P, W>, n);
+        hipLaunchKernelGGL((step_compact_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E,
+                           (R *)pops, lo, n);
+    } else {
+        const int grid = resident_grid(step_full_kernel<P, W>, n);
+        hipLaunchKernelGGL((step_full_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E,
+                           (R *)pops, lo, n);
+    }
     return hipGetLastError();
 }
 

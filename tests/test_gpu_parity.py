@@ -352,3 +352,41 @@ def test_mesh3d_full_size_sampled(torch_dev, ak, orc, prec, state):
         assert out[w].max() > 0.5
     del Pt, Lt, Et, idx_t
     torch.cuda.empty_cache()
+
+
+def test_graph_replay_matches_eager(torch_dev, ak, orc):
+    """Thirty steps captured in one HIP graph and replayed three times, with
+    eager work and synchronisations between replays: every replay equals the
+    eager run bit for bit."""
+    torch = torch_dev
+    gas, _ = gas_pair(ak, orc, 18)
+    mesh = wl.mesh_2d()
+    idx = (np.arange(480, 544)[:, None] * 1024 + np.arange(0, 1024, 4)[None, :]).ravel()
+    n, w, K = idx.size, 3, 30
+    for tdt in (torch.float32, torch.float64):
+        fields = torch.stack([torch.from_numpy(mesh.field_at(600 + 3 * t, idx)).to(tdt) for t in range(K)]).cuda()
+        comp, lo0 = wl.random_window_state(n, 18, w, seed=12)
+        P0 = torch.from_numpy(comp).to(tdt).cuda()
+        L0 = torch.from_numpy(lo0).cuda()
+        P, L = P0.clone(), L0.clone()
+        for t in range(K):
+            ak.ionize_step(gas, fields[t], 3 * mesh.dt, P, L, w=w)
+        torch.cuda.synchronize()
+        want_p, want_l = P.clone(), L.clone()
+        P.copy_(P0)
+        L.copy_(L0)
+        ak.ionize_step(gas, fields[0], 3 * mesh.dt, P, L, w=w)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for t in range(K):
+                ak.ionize_step(gas, fields[t], 3 * mesh.dt, P, L, w=w)
+        for rep in range(3):
+            P.copy_(P0)
+            L.copy_(L0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(P, want_p) and torch.equal(L, want_l), f"replay {rep} ({tdt})"
+            _ = (P.sum() + 1).item()  # eager work between replays
+        del g
