@@ -225,6 +225,115 @@ def mesh3d_measure(ak, gas36, w, eps, steps, warmup):
     return res
 
 
+def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
+    """Mixed gases with uneven windows (1-level host gas, 1 % dopants of 7, 18,
+    36 and 54 levels, w in 1..6): one persistent plan launch per step.  Each
+    step's field is generated on the device by the hash harness; the timed
+    graph holds [field, step] x steps and the field-only graph is timed
+    separately and subtracted."""
+    import torch
+    from paper_2202_10647_amd import workloads as wl
+    tables = [wl.synthetic_gas(z) for z in (1,) + wl.DOPANT_Z]
+    gases = [ak.Gas.from_table(t) for t in tables]
+    cell_gas, cell_w = wl.batched_cells(ncells, seed=4)
+    dt = 1.334e-16
+    res = {"workload": f"batched_{ncells}_cells_1pct_dopants_Z7_18_36_54_w1to6", "steps": steps}
+    for prec, tdt in (("mixed", torch.float32), ("f64", torch.float64)):
+        t0 = time.perf_counter()
+        plan = ak.Plan(gases, cell_gas, cell_w, prec=prec, eps=1e-8, cells_per_lane=0)
+        create_s = time.perf_counter() - t0
+        info = plan.info
+        rows = info["rows"]
+        E = torch.empty(ncells, dtype=tdt, device="cuda")
+        P = torch.zeros((rows, ncells), dtype=tdt, device="cuda")
+        L = torch.zeros(ncells, dtype=torch.uint8, device="cuda")
+
+        def reset():
+            P.zero_()
+            P[0] = 1.0
+            L.zero_()
+            torch.cuda.synchronize()
+
+        reset()
+        ak.field_hash(E, 4, 0)
+        plan.step(E, dt, P, L)  # host caches before capture
+        torch.cuda.synchronize()
+        g_all, g_field = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_all):
+            for s in range(steps):
+                ak.field_hash(E, 4, s)
+                plan.step(E, dt, P, L)
+        with torch.cuda.graph(g_field):
+            for s in range(steps):
+                ak.field_hash(E, 4, s)
+        stream = torch.cuda.current_stream()
+        times = {}
+        for name, g in (("all", g_all), ("field", g_field)):
+            reset()
+            g.replay()  # warm
+            reset()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            g.replay()
+            b.record(stream)
+            torch.cuda.synchronize()
+            times[name] = a.elapsed_time(b)
+        step_ms = (times["all"] - times["field"]) / steps
+        top = np.minimum(L.cpu().numpy().astype(np.int64) + cell_w, np.array([t.Z for t in tables])[cell_gas])
+        units_last = int((top - L.cpu().numpy().astype(np.int64) + 1).sum())
+        es = 4 if prec == "mixed" else 8
+        bytes_step = int(ncells * (es + 2 + 4) + 2 * es * int((cell_w.astype(np.int64) + 1).sum()))
+        res[prec] = dict(ms_per_step=step_ms, field_ms_per_step=times["field"] / steps,
+                         value=units_last / (step_ms * 1e-3), achieved_gbps=bytes_step / (step_ms * 1e-3) / 1e9,
+                         algorithmic_bytes_per_step=bytes_step, plan_create_s=create_s,
+                         cells_per_lane=info["cells_per_lane"], grid=info["grid"], tiles=info["ntiles"],
+                         buckets=info["nbuckets"], tuned_us=info["tuned_us"])
+        log(f"[batched] {prec}: {step_ms * 1e3:.1f} us/step (+{times['field'] / steps * 1e3:.1f} us field), "
+            f"{res[prec]['value']:.3e} cell-level/s (final windows), {res[prec]['achieved_gbps']:.0f} GB/s, "
+            f"cells/lane {info['cells_per_lane']}, {info['ntiles']} tiles, {info['nbuckets']} groups")
+        # parity of one launch from a seeded synthetic state and host-generated
+        # field (the same bits go to the oracle), on sampled cells
+        rng = np.random.default_rng(5)
+        dop = np.nonzero(cell_gas > 0)[0]
+        samp = np.unique(np.concatenate([rng.choice(ncells, parity_cells // 2, replace=False),
+                                         rng.choice(dop, min(dop.size, parity_cells // 2), replace=False)]))
+        npdt = np.float32 if prec == "mixed" else np.float64
+        zs = [t.Z for t in tables]
+        pops0, lo0 = wl.plan_window_state(cell_gas, cell_w, zs, rows, seed=31, dtype=npdt)
+        E0 = wl.hash_field(ncells, 99, 7, dtype=npdt)
+        P.copy_(torch.from_numpy(pops0))
+        L.copy_(torch.from_numpy(lo0))
+        E.copy_(torch.from_numpy(E0))
+        plan.step(E, dt, P, L)
+        torch.cuda.synchronize()
+        idx = torch.from_numpy(samp).cuda()
+        out, l2 = P[:, idx].cpu().numpy().astype(np.float64), L[idx].cpu().numpy()
+        pre_p, pre_l, e_s = pops0[:, samp], lo0[samp], E0[samp]
+        del pops0
+        err, mism = 0.0, 0
+        for gi, t in enumerate(tables):
+            spec = orc.GasSpec(t.U, t.l, t.m)
+            for w in range(1, 7):
+                sel = np.nonzero((cell_gas[samp] == gi) & (cell_w[samp] == w))[0]
+                if sel.size == 0:
+                    continue
+                ref, rlo = orc.ionize_step(spec, e_s[sel].astype(np.float64), dt,
+                                           pre_p[: w + 1, sel].astype(np.float64), pre_l[sel], w, 1e-8)
+                err = max(err, float(np.max(np.abs(out[: w + 1, sel] - ref))))
+                mism += int(np.sum(l2[sel] != rlo))
+        res[prec]["parity_max_abs_err"] = err
+        res[prec]["parity_lo_mismatch"] = mism
+        log(f"[batched] {prec} parity on {samp.size} sampled cells (seeded state, host field): "
+            f"max |dN| {err:.2e}, lo mismatches {mism}")
+        del g_all, g_field, P, L, E
+        plan.close()
+        torch.cuda.empty_cache()
+    res["speedup_mixed_vs_f64"] = res["f64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    for g in gases:
+        g.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -237,6 +346,9 @@ def main():
     ap.add_argument("--no-mesh3d", action="store_true")
     ap.add_argument("--mesh3d-steps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--batched-cells", type=int, default=1 << 24)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the ionization step has no "
@@ -281,6 +393,7 @@ def main():
         gas36 = adkion.Gas.from_table(g36)
         mesh3d = mesh3d_measure(adkion, gas36, w, eps, args.mesh3d_steps, 200)
         gas36.close()
+    batched = None if args.no_batched else batched_measure(adkion, oracle, args.batched_steps, args.batched_cells)
     cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, spec, mesh, w, eps, 1000, 7,
                                                          args.cpu_seconds)
 
@@ -314,6 +427,7 @@ def main():
         "speedup_vs_fp64": m["value"] / res["f64"]["value"],
         "parity": parity,
         "mesh3d": mesh3d,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     gas.close()

@@ -149,6 +149,67 @@ int adk_chain_advance(int32_t w, const void *W, int64_t ncells, double dt, void 
 int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops,
                 uint8_t *lo, const adk_window *win, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched step over cells of several gases with uneven window widths.
+ * Cells are independent (Sec. 3), so one launch can serve a mesh whose cells
+ * carry different gases (for example a dopant in a host gas) and different
+ * window widths w (Sec. 3, reduced system of 3 or 4 levels, chosen per cell).
+ */
+#define ADK_PLAN_MAX_GAS 8
+#define ADK_PLAN_MAX_W 6
+
+typedef struct adk_plan adk_plan; /* opaque: grouping of the cells, tiles, tuning */
+
+typedef struct {
+    int32_t ngas;            /* gases of the plan                                   */
+    int32_t nbuckets;        /* non-empty (gas, w) groups                           */
+    int32_t ntiles;          /* tiles of cells_per_lane * 256 cells of one group    */
+    int32_t cells_per_lane;  /* 1, 2 or 4 (autotuned, cached, or fixed by caller)   */
+    int32_t grid;            /* workgroups of the persistent launch                 */
+    int32_t rows;            /* population rows of the plan layout: max w + 1       */
+    int32_t from_cache;      /* 1 when cells_per_lane came from ADK_TUNE_CACHE      */
+    double tuned_us;         /* best trial launch time of the autotuner (0 if none) */
+} adk_plan_info;
+
+/* Create a plan over ncells cells: cell c uses gases[cell_gas[c]] with window
+ * width cell_w[c] (1 <= w <= min(Z, ADK_PLAN_MAX_W)).  gases (host array of
+ * ngas handles, which must outlive the plan), cell_gas and cell_w are host
+ * arrays read during the call.  Populations use the compact layout with
+ * info.rows rows: pops[rows][ncells], slot s of cell c = level lo[c] + s for
+ * s <= cell_w[c] (other rows are not touched).  cells_per_lane = 0 runs the
+ * autotuner (timed trials on scratch device buffers of the plan's size;
+ * result cached in the file named by ADK_TUNE_CACHE when set), 1, 2 or 4 fixes
+ * it.  Synchronous; allocates device memory.  Errors: ADK_EINVAL (null
+ * pointers, bad prec, eps < 0 or non-finite, cells_per_lane not in
+ * {0,1,2,4}), ADK_ERANGE (ngas outside [1, ADK_PLAN_MAX_GAS], a cell's gas
+ * index or width out of range, ncells >= 2^31 - 256), ADK_EDEVICE/ADK_ENOMEM. */
+int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *cell_gas, const uint8_t *cell_w,
+                    int64_t ncells, adk_prec prec, double eps, int32_t cells_per_lane, adk_plan **out);
+
+/* One ionization step of every cell of the plan (same semantics per cell as
+ * ionize_step with the cell's gas and width): one persistent launch on stream.
+ * E[ncells], pops[rows][ncells], lo[ncells] are device arrays of the plan's
+ * precision.  Allocates nothing and never synchronises, so it may be captured
+ * into a hipGraph; consecutive launches of one plan must be ordered (one
+ * stream).  Errors: ADK_EINVAL (null plan or arrays, dt <= 0 or non-finite). */
+int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t *lo, hipStream_t stream);
+
+/* Host query of the plan's grouping and tuning.  ADK_EINVAL for NULL. */
+int adk_plan_get_info(const adk_plan *plan, adk_plan_info *info);
+
+/* Free a plan (NULL accepted); no enqueued step may still use it. */
+int adk_plan_destroy(adk_plan *plan);
+
+/* Synthetic field generator for tests and benchmarks (an input generator,
+ * not part of the method): E[i] = exp(ln E_lo + u (ln E_hi - ln E_lo)) with
+ * u = (z >> 11) 2^-53, z the SplitMix64 finaliser of
+ * seed + 0x9E3779B97F4A7C15 * (step * n + i + 1) (Steele, Lea & Flood 2014),
+ * so every (seed, step, cell) has its own log-uniform value.  Device array E
+ * of the precision's type.  Errors: ADK_EINVAL (n < 0, step < 0, E_lo <= 0,
+ * E_hi < E_lo, null E with n > 0, bad prec). */
+int adk_field_hash(void *E, int64_t n, uint64_t seed, int64_t step, double E_lo, double E_hi, adk_prec prec,
+                   hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,9 @@ ADK_MAX_Z, ADK_MAX_W, ADK_M_AVERAGE = 64, 8, -1
 
 #: every function the header declares (checked by the CPU test suite)
 EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "adk_gas_destroy",
-           "adk_gas_levels", "adk_rates", "adk_chain_advance", "ionize_step")
+           "adk_gas_levels", "adk_rates", "adk_chain_advance", "ionize_step", "adk_plan_create",
+           "adk_plan_step", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash")
+ADK_PLAN_MAX_GAS, ADK_PLAN_MAX_W = 8, 6
 
 
 class AdkError(RuntimeError):
@@ -39,6 +41,12 @@ class _Consts(ctypes.Structure):
 class _GasDesc(ctypes.Structure):
     _fields_ = [("Z", ctypes.c_int32), ("U_eV", ctypes.POINTER(ctypes.c_double)),
                 ("l", ctypes.POINTER(ctypes.c_int8)), ("m", ctypes.POINTER(ctypes.c_int8))]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("ngas", ctypes.c_int32), ("nbuckets", ctypes.c_int32), ("ntiles", ctypes.c_int32),
+                ("cells_per_lane", ctypes.c_int32), ("grid", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("from_cache", ctypes.c_int32), ("tuned_us", ctypes.c_double)]
 
 
 class _Window(ctypes.Structure):
@@ -77,6 +85,17 @@ def lib():
     L.adk_chain_advance.argtypes = [i32, vp, i64, dbl, vp, ctypes.c_int, vp]
     L.ionize_step.restype = ctypes.c_int
     L.ionize_step.argtypes = [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp]
+    L.adk_plan_create.restype = ctypes.c_int
+    L.adk_plan_create.argtypes = [ctypes.POINTER(vp), i32, vp, vp, i64, ctypes.c_int, dbl, i32,
+                                  ctypes.POINTER(vp)]
+    L.adk_plan_step.restype = ctypes.c_int
+    L.adk_plan_step.argtypes = [vp, vp, dbl, vp, vp, vp]
+    L.adk_plan_get_info.restype = ctypes.c_int
+    L.adk_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
+    L.adk_plan_destroy.restype = ctypes.c_int
+    L.adk_plan_destroy.argtypes = [vp]
+    L.adk_field_hash.restype = ctypes.c_int
+    L.adk_field_hash.argtypes = [vp, i64, ctypes.c_uint64, i64, dbl, dbl, ctypes.c_int, vp]
     _lib = L
     return L
 
@@ -221,3 +240,64 @@ def ionize_step(gas: Gas, E, dt: float, pops, lo, w: int, eps: float = 1e-8, lay
                            ctypes.byref(win), _stream(stream))
     _check(st, "ionize_step")
     return pops, lo
+
+
+class Plan:
+    """Batched step over cells of several gases (see adk_plan_create).
+
+    gases: list of Gas; cell_gas, cell_w: per-cell gas index and window width
+    (host arrays); prec: "mixed" (float) or "f64"; cells_per_lane: 0 = autotune.
+    Populations use pops[info.rows][ncells] (compact slots per cell)."""
+
+    def __init__(self, gases, cell_gas, cell_w, prec="mixed", eps=1e-8, cells_per_lane=0):
+        cg = np.ascontiguousarray(np.asarray(cell_gas, dtype=np.uint8))
+        cw = np.ascontiguousarray(np.asarray(cell_w, dtype=np.uint8))
+        if cg.shape != cw.shape or cg.ndim != 1:
+            raise ValueError("cell_gas and cell_w must be 1-D arrays of one length")
+        arr = (ctypes.c_void_p * max(1, len(gases)))(*[g.handle.value for g in gases])
+        h = ctypes.c_void_p()
+        self._prec = {"mixed": ADK_MIXED, "f64": ADK_F64}[prec]
+        st = lib().adk_plan_create(arr, len(gases), cg.ctypes.data_as(ctypes.c_void_p),
+                                   cw.ctypes.data_as(ctypes.c_void_p), int(cg.size), self._prec, float(eps),
+                                   int(cells_per_lane), ctypes.byref(h))
+        _check(st, "adk_plan_create")
+        self._h = h
+        self._gases = list(gases)  # keep the gas tables alive
+        self.ncells = int(cg.size)
+        self.info = self.get_info()
+
+    def get_info(self) -> dict:
+        inf = _PlanInfo()
+        _check(lib().adk_plan_get_info(self._h, ctypes.byref(inf)), "adk_plan_get_info")
+        return {k: getattr(inf, k) for k, _ in _PlanInfo._fields_}
+
+    def step(self, E, dt: float, pops, lo, stream=None):
+        import torch
+        want = torch.float32 if self._prec == ADK_MIXED else torch.float64
+        if E.dtype != want or pops.dtype != want or E.numel() != self.ncells:
+            raise ValueError("E/pops dtype or size does not match the plan")
+        if tuple(pops.shape) != (self.info["rows"], self.ncells) or lo.dtype != torch.uint8:
+            raise ValueError(f"pops must be [{self.info['rows']}][{self.ncells}], lo uint8[{self.ncells}]")
+        st = lib().adk_plan_step(self._h, _dev(E, "E"), float(dt), _dev(pops, "pops"), _dev(lo, "lo"),
+                                 _stream(stream))
+        _check(st, "adk_plan_step")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().adk_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def field_hash(E, seed: int, step: int, E_lo: float = 10.0, E_hi: float = 5000.0, stream=None):
+    """Fill the device tensor E with the seeded log-uniform synthetic field of
+    (seed, step) (input generator; workloads.hash_field is its host twin)."""
+    st = lib().adk_field_hash(_dev(E, "E"), E.numel(), int(seed) & 0xFFFFFFFFFFFFFFFF, int(step), float(E_lo),
+                              float(E_hi), _prec_of(E), _stream(stream))
+    _check(st, "adk_field_hash")
+    return E

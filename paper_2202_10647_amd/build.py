@@ -32,6 +32,13 @@ def _jobs(objdir):
                   "-o", obj], obj))
     obj = os.path.join(objdir, "abi.o")
     jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "abi.hip"), "-o", obj], obj))
+    obj = os.path.join(objdir, "plan.o")
+    jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "plan.hip"), "-o", obj], obj))
+    for prec in PRECS:
+        for cpl in (1, 2, 4):
+            obj = os.path.join(objdir, f"plan_{prec}_{cpl}.o")
+            jobs.append((["hipcc", *HIP_FLAGS, f"-DADK_PLAN_PREC={prec}", f"-DADK_PLAN_CPL={cpl}", "-c",
+                          os.path.join(CSRC, "plan_inst.hip"), "-o", obj], obj))
     for prec in PRECS:
         for w in WIDTHS:
             obj = os.path.join(objdir, f"inst_{prec}_{w}.o")
@@ -46,7 +53,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(objdir, exist_ok=True)
     work = _jobs(objdir)
     # largest instantiations first so the pool stays busy
-    work.sort(key=lambda j: -int(j[1].rsplit("_", 1)[-1][:-2]) if "inst_" in j[1] else 0)
+    work.sort(key=lambda j: (0 if "plan_" in j[1] else 1, -int(j[1].rsplit("_", 1)[-1][:-2]) if "inst_" in j[1] else 0))
     njobs = jobs or max(1, min(16, os.cpu_count() or 1))
     with ThreadPoolExecutor(njobs) as ex:
         list(ex.map(lambda j: _run(j[0], verbose), work))

@@ -186,6 +186,56 @@ __device__ __forceinline__ void load_cell(CellLoad<R, W> &d, const R *__restrict
     d.lo = lo[c];
 }
 
+// One cell of a compact-layout step from its loaded data: window shift,
+// rates, exact chain update, store.  Called by all active lanes of a
+// wavefront together (the fast path and the solver use wavefront votes).
+template <class P, int W>
+__device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &cur, const double *sc,
+                                          const double *slog, int Z, bool has_poly, double eps, double E_cut,
+                                          typename P::real *__restrict__ pops, uint8_t *__restrict__ lo, int64_t n,
+                                          int64_t c)
+{
+    using R = typename P::real;
+    const double EL = fabs((double)cur.E);
+    int p = cur.lo;
+    p = p < Z ? p : Z;
+    // whole wavefront below the field cutoff and no shift due: T = I
+    if (__all(EL < E_cut && (double)cur.N[0] >= eps)) {
+        static_for<0, W + 1>([&](auto ss) {
+            constexpr int s = decltype(ss)::value;
+            pops[(int64_t)s * n + c] = cur.N[s];
+        });
+        lo[c] = (uint8_t)p;
+        return;
+    }
+    double N[W + 1];
+    static_for<0, W + 1>([&](auto ss) { N[decltype(ss)::value] = (double)cur.N[decltype(ss)::value]; });
+    // window shift at the start of the step; residual folded upward
+    while (p < Z && N[0] < eps) {
+        N[0] += N[1];
+        static_for<1, W>([&](auto ss) {
+            constexpr int s = decltype(ss)::value;
+            N[s] = N[s + 1];
+        });
+        N[W] = 0.0;
+        ++p;
+    }
+    const Field f = field_terms<RateEval<P>::kLogTerms>(EL, slog);
+    R x[W];
+    window_rates<P, W>(sc, p, f, has_poly, x);
+    double out[W + 1];
+    chain_apply<P, W>(x, N, out);
+    const bool finite = EL <= 1.7976931348623157e308;
+    static_for<0, W + 1>([&](auto ss) {
+        constexpr int s = decltype(ss)::value;
+        // slots past level Z hold no population (rounding of the top row);
+        // a non-finite field makes the whole window NaN
+        const R v = finite ? (R)out[s] : R(NAN);
+        pops[(int64_t)s * n + c] = (p + s <= Z) ? v : R(0);
+    });
+    lo[c] = (uint8_t)p;
+}
+
 template <class P, int W>
 __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const typename P::real *__restrict__ E,
                                                               typename P::real *__restrict__ pops,
@@ -195,8 +245,6 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const 
     __shared__ double sc[kDevTableLen];
     const double *slog = sc + kCoefRows * kCoefStride;
     stage_coefficients(sc, a.tab, a.ln_dt);
-    const int Z = a.Z;
-    const bool has_poly = a.has_poly != 0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     CellLoad<R, W> nxt;
@@ -204,44 +252,7 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const 
     for (; c < n; c += stride) {
         const CellLoad<R, W> cur = nxt;
         if (c + stride < n) load_cell(nxt, E, pops, lo, n, c + stride);
-        const double EL = fabs((double)cur.E);
-        int p = cur.lo;
-        p = p < Z ? p : Z;
-        // whole wavefront below the field cutoff and no shift due: T = I
-        if (__all(EL < a.E_cut && (double)cur.N[0] >= a.eps)) {
-            static_for<0, W + 1>([&](auto ss) {
-                constexpr int s = decltype(ss)::value;
-                pops[(int64_t)s * n + c] = cur.N[s];
-            });
-            lo[c] = (uint8_t)p;
-            continue;
-        }
-        double N[W + 1];
-        static_for<0, W + 1>([&](auto ss) { N[decltype(ss)::value] = (double)cur.N[decltype(ss)::value]; });
-        // window shift at the start of the step; residual folded upward
-        while (p < Z && N[0] < a.eps) {
-            N[0] += N[1];
-            static_for<1, W>([&](auto ss) {
-                constexpr int s = decltype(ss)::value;
-                N[s] = N[s + 1];
-            });
-            N[W] = 0.0;
-            ++p;
-        }
-        const Field f = field_terms<RateEval<P>::kLogTerms>(EL, slog);
-        R x[W];
-        window_rates<P, W>(sc, p, f, has_poly, x);
-        double out[W + 1];
-        chain_apply<P, W>(x, N, out);
-        const bool finite = EL <= 1.7976931348623157e308;
-        static_for<0, W + 1>([&](auto ss) {
-            constexpr int s = decltype(ss)::value;
-            // slots past level Z hold no population (rounding of the top row);
-            // a non-finite field makes the whole window NaN
-            const R v = finite ? (R)out[s] : R(NAN);
-            pops[(int64_t)s * n + c] = (p + s <= Z) ? v : R(0);
-        });
-        lo[c] = (uint8_t)p;
+        step_cell<P, W>(cur, sc, slog, a.Z, a.has_poly != 0, a.eps, a.E_cut, pops, lo, n, c);
     }
 }
 
@@ -416,3 +427,149 @@ using AdvanceFn = hipError_t (*)(const void *, int64_t, double, void *, hipStrea
     ADK_DECLARE_INST(PREC, 8)
 ADK_DECLARE_PREC(f64)
 ADK_DECLARE_PREC(mixed)
+
+// ---------------------------------------------------------------------------
+// Batched step over cells of several gases and window widths (plan).
+// Cells are grouped by (gas, w) on the host; a tile is up to CPL*kBlock cells
+// of one group, listed through a permutation of the cell index.  One
+// persistent launch: every resident workgroup takes tiles from an atomic
+// counter until the list is exhausted; the last workgroup to finish resets
+// the counters, so consecutive launches (and graph replays) need no memset.
+namespace adk {
+
+constexpr int kPlanMaxGas = 8;
+constexpr int kPlanMaxW = 6;
+
+struct PlanGasArgs {
+    const double *tab;
+    int Z;
+    int has_poly;
+    double E_cut;
+};
+
+struct PlanArgs {
+    PlanGasArgs gas[kPlanMaxGas];
+    double ln_dt;
+    double eps;
+    int ntiles;
+};
+
+struct PlanTile {
+    int32_t gas, w, start, count;
+};
+
+template <class P, int W, int CPL>
+__device__ __forceinline__ void plan_tile(const PlanTile &tile, const PlanGasArgs &g, double eps, const double *sc,
+                                          const typename P::real *__restrict__ E,
+                                          typename P::real *__restrict__ pops, uint8_t *__restrict__ lo, int64_t n,
+                                          const int32_t *__restrict__ perm)
+{
+    using R = typename P::real;
+    const double *slog = sc + kCoefRows * kCoefStride;
+    const int end = tile.start + tile.count;
+    int idx = tile.start + (int)threadIdx.x;
+    CellLoad<R, W> nxt;
+    int64_t cn = 0;
+    if (idx < end) {
+        cn = perm[idx];
+        load_cell(nxt, E, pops, lo, n, cn);
+    }
+    static_for<0, CPL>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        if (idx < end) {
+            const CellLoad<R, W> cur = nxt;
+            const int64_t c = cn;
+            if constexpr (k + 1 < CPL) {
+                if (idx + kBlock < end) {
+                    cn = perm[idx + kBlock];
+                    load_cell(nxt, E, pops, lo, n, cn);
+                }
+            }
+            step_cell<P, W>(cur, sc, slog, g.Z, g.has_poly != 0, eps, g.E_cut, pops, lo, n, c);
+        }
+        idx += kBlock;
+    });
+}
+
+template <class P, int CPL>
+__global__ __launch_bounds__(kBlock) void plan_kernel(PlanArgs a, const typename P::real *__restrict__ E,
+                                                      typename P::real *__restrict__ pops,
+                                                      uint8_t *__restrict__ lo, int64_t n,
+                                                      const int32_t *__restrict__ perm,
+                                                      const PlanTile *__restrict__ tiles, unsigned *ctr)
+{
+    __shared__ double sc[kDevTableLen];
+    __shared__ int s_tile;
+    int staged = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&ctr[0], 1u);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (t >= a.ntiles) break;
+        const PlanTile tile = tiles[t];
+        // uniform selection (a dynamic index into the argument block would
+        // put it in scratch memory)
+        PlanGasArgs g = a.gas[0];
+        static_for<1, kPlanMaxGas>([&](auto kk) {
+            if (tile.gas == decltype(kk)::value) g = a.gas[decltype(kk)::value];
+        });
+        if (tile.gas != staged) {
+            stage_coefficients(sc, g.tab, a.ln_dt);
+            staged = tile.gas;
+        }
+        switch (tile.w) {
+        case 1: plan_tile<P, 1, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
+        case 2: plan_tile<P, 2, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
+        case 3: plan_tile<P, 3, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
+        case 4: plan_tile<P, 4, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
+        case 5: plan_tile<P, 5, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
+        default: plan_tile<P, 6, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&ctr[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&ctr[0], 0u);
+            atomicExch(&ctr[1], 0u);
+        }
+    }
+}
+
+template <class P, int CPL>
+hipError_t launch_plan(const PlanArgs &a, int grid, const void *E, void *pops, uint8_t *lo, int64_t n,
+                       const int32_t *perm, const PlanTile *tiles, unsigned *ctr, hipStream_t st)
+{
+    using R = typename P::real;
+    hipLaunchKernelGGL((plan_kernel<P, CPL>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E, (R *)pops, lo, n,
+                       perm, tiles, ctr);
+    return hipGetLastError();
+}
+
+template <class P, int CPL>
+int plan_occupancy()
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, plan_kernel<P, CPL>, kBlock, 0) != hipSuccess || b <= 0)
+        b = 2;
+    return b;
+}
+
+using PlanLaunchFn = hipError_t (*)(const PlanArgs &, int, const void *, void *, uint8_t *, int64_t,
+                                    const int32_t *, const PlanTile *, unsigned *, hipStream_t);
+using PlanOccFn = int (*)();
+
+}  // namespace adk
+
+#define ADK_DECLARE_PLAN(PREC, CPL)                                                                        \
+    hipError_t adk_plan_launch_##PREC##_##CPL(const adk::PlanArgs &, int, const void *, void *, uint8_t *, \
+                                              int64_t, const int32_t *, const adk::PlanTile *, unsigned *, \
+                                              hipStream_t);                                                \
+    int adk_plan_occupancy_##PREC##_##CPL();
+ADK_DECLARE_PLAN(f64, 1)
+ADK_DECLARE_PLAN(f64, 2)
+ADK_DECLARE_PLAN(f64, 4)
+ADK_DECLARE_PLAN(mixed, 1)
+ADK_DECLARE_PLAN(mixed, 2)
+ADK_DECLARE_PLAN(mixed, 4)

@@ -1,0 +1,427 @@
+// Batched plan over cells of several gases (host side), its autotuner, and
+// the synthetic-field harness kernel.
+//
+// A plan groups the cells by (gas, window width) with a stable counting sort
+// (cells of a group keep their mesh order, so runs of neighbouring cells stay
+// coalesced), orders the groups heaviest first (wider windows and longer
+// chains first, so the persistent launch starts the long tiles early), and
+// cuts them into tiles of cells_per_lane x 256 cells.  cells_per_lane is
+// chosen by timed trials on scratch buffers unless the caller fixes it; the
+// choice is cached per (device, problem) in the file named by the
+// ADK_TUNE_CACHE environment variable, when it is set.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+struct adk_plan {
+    int ngas = 0;
+    const adk_gas *gas[adk::kPlanMaxGas] = {};
+    adk_prec prec = ADK_F64;
+    double eps = 0.0;
+    int64_t ncells = 0;
+    int rows = 0;
+    int nbuckets = 0;
+    int ntiles = 0;
+    int cpl = 1;
+    int grid = 0;
+    double tuned_us = 0.0;
+    int from_cache = 0;
+    int32_t *d_perm = nullptr;
+    adk::PlanTile *d_tiles = nullptr;
+    unsigned *d_ctr = nullptr;
+};
+
+namespace adk {
+
+// ---------------------------------------------------------------------------
+// Synthetic field harness (input generator, not part of the method):
+// E[i] = exp(ln E_lo + u (ln E_hi - ln E_lo)) with u in [0, 1) from the
+// SplitMix64 finaliser (Steele, Lea and Flood 2014) of the counter
+// seed + 0x9E3779B97F4A7C15 (step n + i + 1).
+__host__ __device__ inline uint64_t splitmix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void field_hash_kernel(R *__restrict__ E, int64_t n, uint64_t seed,
+                                                            int64_t step, double llo, double lspan)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const uint64_t ctr = (uint64_t)step * (uint64_t)n + (uint64_t)i + 1ull;
+        const uint64_t z = splitmix64(seed + 0x9E3779B97F4A7C15ull * ctr);
+        const double u = (double)(z >> 11) * 0x1.0p-53;
+        E[i] = (R)exp(llo + u * lspan);
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void neutral_fill_kernel(R *__restrict__ pops, uint8_t *__restrict__ lo,
+                                                              int rows, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        pops[i] = R(1);
+        for (int r = 1; r < rows; ++r) pops[(int64_t)r * n + i] = R(0);
+        lo[i] = 0;
+    }
+}
+
+static const PlanLaunchFn kPlanLaunch[2][3] = {
+    {adk_plan_launch_f64_1, adk_plan_launch_f64_2, adk_plan_launch_f64_4},
+    {adk_plan_launch_mixed_1, adk_plan_launch_mixed_2, adk_plan_launch_mixed_4}};
+static const PlanOccFn kPlanOcc[2][3] = {{adk_plan_occupancy_f64_1, adk_plan_occupancy_f64_2, adk_plan_occupancy_f64_4},
+                                         {adk_plan_occupancy_mixed_1, adk_plan_occupancy_mixed_2,
+                                          adk_plan_occupancy_mixed_4}};
+
+static int cpl_slot(int cpl) { return cpl == 1 ? 0 : (cpl == 2 ? 1 : 2); }
+
+static int plan_status(hipError_t e)
+{
+    if (e == hipSuccess) return ADK_OK;
+    if (e == hipErrorOutOfMemory) return ADK_ENOMEM;
+    return ADK_EDEVICE;
+}
+
+struct Bucket {
+    int gas, w;
+    int64_t count;
+    int64_t offset;  // start in the permutation
+};
+
+// Tiles of cpl * kBlock cells over the buckets in permutation order.
+static std::vector<PlanTile> make_tiles(const std::vector<Bucket> &b, int cpl)
+{
+    std::vector<PlanTile> t;
+    const int64_t T = (int64_t)cpl * kBlock;
+    for (const Bucket &k : b)
+        for (int64_t s = 0; s < k.count; s += T) {
+            PlanTile x;
+            x.gas = k.gas;
+            x.w = k.w;
+            x.start = (int32_t)(k.offset + s);
+            x.count = (int32_t)std::min<int64_t>(T, k.count - s);
+            t.push_back(x);
+        }
+    return t;
+}
+
+static PlanArgs plan_args(const adk_plan *p, double dt, int ntiles)
+{
+    PlanArgs a;
+    std::memset(&a, 0, sizeof(a));
+    for (int g = 0; g < p->ngas; ++g) {
+        const StepArgs s = step_args(p->gas[g], dt, p->eps);
+        a.gas[g].tab = s.tab;
+        a.gas[g].Z = s.Z;
+        a.gas[g].has_poly = s.has_poly;
+        a.gas[g].E_cut = s.E_cut;
+    }
+    a.ln_dt = std::log(dt);
+    a.eps = p->eps;
+    a.ntiles = ntiles;
+    return a;
+}
+
+static int plan_grid(const adk_plan *p, int cpl, int ntiles)
+{
+    const int occ = kPlanOcc[p->prec == ADK_MIXED ? 1 : 0][cpl_slot(cpl)]();
+    const int g = num_cus() * occ;
+    return std::max(1, std::min(g, ntiles));
+}
+
+static std::string tune_key(const adk_plan *p, const std::vector<Bucket> &b)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    uint64_t h = 0x84222325cbf29ce4ull;
+    for (const Bucket &k : b) {
+        h = splitmix64(h ^ (uint64_t)(k.gas * 131 + k.w));
+        h = splitmix64(h ^ (uint64_t)k.count);
+        h = splitmix64(h ^ (uint64_t)p->gas[k.gas]->Z);
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s|n=%lld|prec=%d|b=%016llx", arch.c_str(), (long long)p->ncells,
+                  (int)p->prec, (unsigned long long)h);
+    for (char *c = buf; *c; ++c)
+        if (*c == ' ') *c = '_';
+    return buf;
+}
+
+static int cache_lookup(const std::string &key)
+{
+    const char *path = std::getenv("ADK_TUNE_CACHE");
+    if (!path) return 0;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return 0;
+    char k[512];
+    int v = 0, found = 0;
+    while (std::fscanf(f, "%511s %d", k, &v) == 2)
+        if (key == k && (v == 1 || v == 2 || v == 4)) found = v;  // last entry wins
+    std::fclose(f);
+    return found;
+}
+
+static void cache_store(const std::string &key, int cpl)
+{
+    const char *path = std::getenv("ADK_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", key.c_str(), cpl);
+    std::fclose(f);
+}
+
+// Timed trials of cells_per_lane in {1, 2, 4} on scratch buffers: neutral
+// state, fields log-uniform in [10, 5000] GV/m, dt = 0.1 fs.
+static int autotune(adk_plan *p, const std::vector<Bucket> &b, int *cpl_out, double *best_us)
+{
+    const int64_t n = p->ncells;
+    const size_t es = p->prec == ADK_MIXED ? 4 : 8;
+    void *E = nullptr, *pops = nullptr;
+    uint8_t *lo = nullptr;
+    PlanTile *tiles = nullptr;
+    unsigned *ctr = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = 1;
+    *best_us = 0.0;
+    hipError_t err = hipMalloc(&E, es * (size_t)n);
+    if (err == hipSuccess) err = hipMalloc(&pops, es * (size_t)n * (size_t)p->rows);
+    if (err == hipSuccess) err = hipMalloc((void **)&lo, (size_t)n);
+    if (err == hipSuccess) err = hipMalloc((void **)&ctr, 2 * sizeof(unsigned));
+    if (err == hipSuccess) err = hipMemset(ctr, 0, 2 * sizeof(unsigned));
+    const size_t max_tiles = (size_t)(n / kBlock + b.size() + 1);
+    if (err == hipSuccess) err = hipMalloc((void **)&tiles, sizeof(PlanTile) * max_tiles);
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    if (err == hipSuccess) {
+        const int g = grid_for(n);
+        if (p->prec == ADK_MIXED) {
+            hipLaunchKernelGGL(field_hash_kernel<float>, dim3(g), dim3(kBlock), 0, 0, (float *)E, n, 4ull, 0ll,
+                               std::log(10.0), std::log(500.0));
+            hipLaunchKernelGGL(neutral_fill_kernel<float>, dim3(g), dim3(kBlock), 0, 0, (float *)pops, lo, p->rows, n);
+        } else {
+            hipLaunchKernelGGL(field_hash_kernel<double>, dim3(g), dim3(kBlock), 0, 0, (double *)E, n, 4ull, 0ll,
+                               std::log(10.0), std::log(500.0));
+            hipLaunchKernelGGL(neutral_fill_kernel<double>, dim3(g), dim3(kBlock), 0, 0, (double *)pops, lo,
+                               p->rows, n);
+        }
+        err = hipGetLastError();
+    }
+    double best_t = 1e300;
+    const int cands[3] = {1, 2, 4};
+    for (int ci = 0; ci < 3 && err == hipSuccess; ++ci) {
+        const int cpl = cands[ci];
+        const std::vector<PlanTile> t = make_tiles(b, cpl);
+        err = hipMemcpy(tiles, t.data(), sizeof(PlanTile) * t.size(), hipMemcpyHostToDevice);
+        if (err != hipSuccess) break;
+        const PlanArgs a = plan_args(p, 1e-16, (int)t.size());
+        const int grid = plan_grid(p, cpl, (int)t.size());
+        const PlanLaunchFn fn = kPlanLaunch[p->prec == ADK_MIXED ? 1 : 0][ci];
+        double t_min = 1e300;
+        for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+            err = hipEventRecord(e0, 0);
+            if (err == hipSuccess) err = fn(a, grid, E, pops, lo, n, p->d_perm, tiles, ctr, 0);
+            if (err == hipSuccess) err = hipEventRecord(e1, 0);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) t_min = std::min(t_min, (double)ms);  // first launch is a warm-up
+        }
+        if (t_min < best_t) {
+            best_t = t_min;
+            best = cpl;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (E) (void)hipFree(E);
+    if (pops) (void)hipFree(pops);
+    if (lo) (void)hipFree(lo);
+    if (tiles) (void)hipFree(tiles);
+    if (ctr) (void)hipFree(ctr);
+    if (err != hipSuccess) return plan_status(err);
+    *best_us = best_t * 1e3;
+    *cpl_out = best;
+    return ADK_OK;
+}
+
+}  // namespace adk
+
+using namespace adk;
+
+extern "C" {
+
+int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *cell_gas, const uint8_t *cell_w,
+                    int64_t ncells, adk_prec prec, double eps, int32_t cells_per_lane, adk_plan **out)
+{
+    if (!out) return ADK_EINVAL;
+    *out = nullptr;
+    if (!gases || ngas < 1 || ngas > kPlanMaxGas) return ngas < 1 || !gases ? ADK_EINVAL : ADK_ERANGE;
+    if (ncells < 0 || ncells >= ((int64_t)1 << 31) - kBlock) return ADK_ERANGE;
+    if (ncells > 0 && (!cell_gas || !cell_w)) return ADK_EINVAL;
+    if (prec != ADK_F64 && prec != ADK_MIXED) return ADK_EINVAL;
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return ADK_EINVAL;
+    if (cells_per_lane != 0 && cells_per_lane != 1 && cells_per_lane != 2 && cells_per_lane != 4) return ADK_EINVAL;
+    for (int g = 0; g < ngas; ++g)
+        if (!gases[g]) return ADK_EINVAL;
+    int wmax = 0;
+    std::vector<int64_t> count((size_t)ngas * (kPlanMaxW + 1), 0);
+    for (int64_t c = 0; c < ncells; ++c) {
+        const int g = cell_gas[c], w = cell_w[c];
+        if (g >= ngas) return ADK_ERANGE;
+        if (w < 1 || w > kPlanMaxW || w > gases[g]->Z) return ADK_ERANGE;
+        ++count[(size_t)g * (kPlanMaxW + 1) + w];
+        wmax = std::max(wmax, w);
+    }
+    adk_plan *p = new (std::nothrow) adk_plan();
+    if (!p) return ADK_ENOMEM;
+    p->ngas = ngas;
+    for (int g = 0; g < ngas; ++g) p->gas[g] = gases[g];
+    p->prec = prec;
+    p->eps = eps;
+    p->ncells = ncells;
+    p->rows = wmax + 1;
+    // groups, heaviest first: wider windows, then longer chains
+    std::vector<Bucket> b;
+    for (int g = 0; g < ngas; ++g)
+        for (int w = 1; w <= kPlanMaxW; ++w) {
+            const int64_t k = count[(size_t)g * (kPlanMaxW + 1) + w];
+            if (k) b.push_back(Bucket{g, w, k, 0});
+        }
+    std::stable_sort(b.begin(), b.end(), [&](const Bucket &x, const Bucket &y) {
+        if (x.w != y.w) return x.w > y.w;
+        return gases[x.gas]->Z > gases[y.gas]->Z;
+    });
+    std::vector<int64_t> offset((size_t)ngas * (kPlanMaxW + 1), 0);
+    int64_t run = 0;
+    for (Bucket &k : b) {
+        k.offset = run;
+        offset[(size_t)k.gas * (kPlanMaxW + 1) + k.w] = run;
+        run += k.count;
+    }
+    p->nbuckets = (int)b.size();
+    std::vector<int32_t> perm((size_t)ncells);
+    for (int64_t c = 0; c < ncells; ++c) {
+        int64_t &o = offset[(size_t)cell_gas[c] * (kPlanMaxW + 1) + cell_w[c]];
+        perm[(size_t)o++] = (int32_t)c;
+    }
+    int st = ADK_OK;
+    hipError_t e = hipSuccess;
+    if (ncells > 0) {
+        e = hipMalloc((void **)&p->d_perm, sizeof(int32_t) * (size_t)ncells);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_perm, perm.data(), sizeof(int32_t) * (size_t)ncells, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_ctr, 2 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(p->d_ctr, 0, 2 * sizeof(unsigned));
+    if (e != hipSuccess) st = plan_status(e);
+    if (st == ADK_OK) {
+        int cpl = cells_per_lane;
+        if (cpl == 0 && ncells > 0) {
+            const std::string key = tune_key(p, b);
+            cpl = cache_lookup(key);
+            if (cpl) {
+                p->from_cache = 1;
+            } else {
+                st = autotune(p, b, &cpl, &p->tuned_us);
+                if (st == ADK_OK) cache_store(key, cpl);
+            }
+        }
+        if (cpl == 0) cpl = 1;
+        p->cpl = cpl;
+    }
+    if (st == ADK_OK) {
+        const std::vector<PlanTile> t = make_tiles(b, p->cpl);
+        p->ntiles = (int)t.size();
+        if (!t.empty()) {
+            e = hipMalloc((void **)&p->d_tiles, sizeof(PlanTile) * t.size());
+            if (e == hipSuccess)
+                e = hipMemcpy(p->d_tiles, t.data(), sizeof(PlanTile) * t.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) st = plan_status(e);
+        }
+        p->grid = plan_grid(p, p->cpl, std::max(p->ntiles, 1));
+    }
+    if (st != ADK_OK) {
+        adk_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return ADK_OK;
+}
+
+int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t *lo, hipStream_t stream)
+{
+    if (!plan) return ADK_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
+    if (plan->ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
+    if (plan->ntiles == 0) return ADK_OK;
+    const PlanArgs a = plan_args(plan, dt, plan->ntiles);
+    const PlanLaunchFn fn = kPlanLaunch[plan->prec == ADK_MIXED ? 1 : 0][cpl_slot(plan->cpl)];
+    return plan_status(fn(a, plan->grid, E, pops, lo, plan->ncells, plan->d_perm, plan->d_tiles, plan->d_ctr, stream));
+}
+
+int adk_plan_get_info(const adk_plan *plan, adk_plan_info *info)
+{
+    if (!plan || !info) return ADK_EINVAL;
+    info->ngas = plan->ngas;
+    info->nbuckets = plan->nbuckets;
+    info->ntiles = plan->ntiles;
+    info->cells_per_lane = plan->cpl;
+    info->grid = plan->grid;
+    info->rows = plan->rows;
+    info->from_cache = plan->from_cache;
+    info->tuned_us = plan->tuned_us;
+    return ADK_OK;
+}
+
+int adk_plan_destroy(adk_plan *plan)
+{
+    if (!plan) return ADK_OK;
+    hipError_t e = hipSuccess;
+    if (plan->d_perm) e = hipFree(plan->d_perm);
+    if (plan->d_tiles) {
+        const hipError_t e2 = hipFree(plan->d_tiles);
+        if (e == hipSuccess) e = e2;
+    }
+    if (plan->d_ctr) {
+        const hipError_t e2 = hipFree(plan->d_ctr);
+        if (e == hipSuccess) e = e2;
+    }
+    delete plan;
+    return plan_status(e);
+}
+
+int adk_field_hash(void *E, int64_t n, uint64_t seed, int64_t step, double E_lo, double E_hi, adk_prec prec,
+                   hipStream_t stream)
+{
+    if (n < 0 || step < 0 || (prec != ADK_F64 && prec != ADK_MIXED)) return ADK_EINVAL;
+    if (!(E_lo > 0.0) || !(E_hi >= E_lo) || !std::isfinite(E_hi)) return ADK_EINVAL;
+    if (n > 0 && !E) return ADK_EINVAL;
+    if (n == 0) return ADK_OK;
+    const double llo = std::log(E_lo), lspan = std::log(E_hi) - llo;
+    if (prec == ADK_MIXED)
+        hipLaunchKernelGGL(field_hash_kernel<float>, dim3(grid_for(n)), dim3(kBlock), 0, stream, (float *)E, n, seed,
+                           step, llo, lspan);
+    else
+        hipLaunchKernelGGL(field_hash_kernel<double>, dim3(grid_for(n)), dim3(kBlock), 0, stream, (double *)E, n,
+                           seed, step, llo, lspan);
+    return plan_status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -193,3 +193,61 @@ def random_window_state(ncells: int, Z: int, w: int, seed: int, dtype=np.float64
     raw[0, empty] = 1.0
     s[empty] = 1.0
     return (raw / s).astype(dtype), lo
+
+
+# ---------------------------------------------------------------------------
+# Mixed gases with uneven windows: a host gas of 1-level cells and a 1 % dopant
+# of heavier synthetic gases spread uniformly over the cells.
+DOPANT_Z = (7, 18, 36, 54)
+
+
+def batched_cells(ncells: int, seed: int = 4, dopant_fraction: float = 0.01, wmax: int = 6):
+    """(cell_gas, cell_w): gas index 0 is the 1-level gas (w = 1); a Bernoulli
+    dopant mask picks cells whose gas is uniform over DOPANT_Z (indices 1..4)
+    with w uniform on 1..wmax clamped to Z."""
+    rng = np.random.default_rng(seed)
+    dop = rng.random(ncells) < dopant_fraction
+    gas = np.zeros(ncells, np.uint8)
+    w = np.ones(ncells, np.uint8)
+    nd = int(dop.sum())
+    gi = rng.integers(1, len(DOPANT_Z) + 1, nd).astype(np.uint8)
+    zs = np.array((1,) + DOPANT_Z)[gi]
+    gas[dop] = gi
+    w[dop] = np.minimum(rng.integers(1, wmax + 1, nd), zs).astype(np.uint8)
+    return gas, w
+
+
+_SM_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def hash_field(n: int, seed: int, step: int, E_lo: float = 10.0, E_hi: float = 5000.0, dtype=np.float64):
+    """Log-uniform field per (seed, step, cell) from the SplitMix64 finaliser
+    (Steele, Lea & Flood 2014) of seed + gamma (step n + i + 1); the same
+    definition as the device generator adk_field_hash."""
+    with np.errstate(over="ignore"):
+        ctr = np.uint64(step) * np.uint64(n) + np.arange(n, dtype=np.uint64) + np.uint64(1)
+        z = np.uint64(seed) + _SM_GAMMA * ctr
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    llo = math.log(E_lo)
+    return np.exp(llo + u * (math.log(E_hi) - llo)).astype(dtype)
+
+
+def plan_window_state(cell_gas, cell_w, gas_Z, rows: int, seed: int, fill: float = 0.625, dtype=np.float64):
+    """Random window states for a mesh of mixed gases in the plan layout
+    pops[rows][n]: each (gas, w) group gets random_window_state draws; rows
+    above a cell's window hold `fill` (they must be left untouched)."""
+    n = cell_gas.size
+    pops = np.full((rows, n), fill, dtype=np.float64)
+    lo = np.zeros(n, np.uint8)
+    for g, z in enumerate(gas_Z):
+        for w in range(1, rows):
+            idx = np.nonzero((cell_gas == g) & (cell_w == w))[0]
+            if idx.size == 0:
+                continue
+            comp, l = random_window_state(idx.size, int(z), w, seed=seed + 10 * g + w)
+            pops[: w + 1, idx] = comp
+            lo[idx] = l
+    return pops.astype(dtype), lo

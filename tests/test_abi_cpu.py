@@ -140,3 +140,50 @@ def test_gas_create_out_pointer_required(L):
     bad, keep2 = adkion._desc([-5.0], [0], [0])
     assert L.adk_gas_create(ctypes.byref(bad), None, ctypes.byref(h)) == adkion.ADK_EINVAL
     assert h.value is None
+
+
+def test_plan_validation_before_device(L):
+    vp = ctypes.c_void_p
+    out = vp()
+    one = (vp * 1)(vp(16))
+    cg = np.zeros(4, np.uint8)
+    cw = np.ones(4, np.uint8)
+    f = L.adk_plan_create
+    c = lambda a: a.ctypes.data_as(vp)
+    assert f(one, 1, c(cg), c(cw), 4, 0, 1e-8, 0, None) == adkion.ADK_EINVAL
+    assert f(None, 1, c(cg), c(cw), 4, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 0, c(cg), c(cw), 4, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 9, c(cg), c(cw), 4, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_ERANGE
+    assert f(one, 1, c(cg), c(cw), -1, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_ERANGE
+    assert f(one, 1, None, c(cw), 4, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 5, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 0, -1.0, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 0, 1e-8, 3, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert out.value is None
+    info = adkion._PlanInfo()
+    assert L.adk_plan_get_info(None, ctypes.byref(info)) == adkion.ADK_EINVAL
+    assert L.adk_plan_step(None, vp(16), 1e-16, vp(16), vp(16), None) == adkion.ADK_EINVAL
+    assert L.adk_plan_destroy(None) == adkion.ADK_OK
+    fh = L.adk_field_hash
+    assert fh(vp(16), -1, 1, 0, 10.0, 20.0, 0, None) == adkion.ADK_EINVAL
+    assert fh(vp(16), 4, 1, -1, 10.0, 20.0, 0, None) == adkion.ADK_EINVAL
+    assert fh(vp(16), 4, 1, 0, 0.0, 20.0, 0, None) == adkion.ADK_EINVAL
+    assert fh(vp(16), 4, 1, 0, 30.0, 20.0, 0, None) == adkion.ADK_EINVAL
+    assert fh(None, 0, 1, 0, 10.0, 20.0, 0, None) == adkion.ADK_OK
+
+
+def test_batched_cells_generator():
+    g, w = wl.batched_cells(200000, seed=4)
+    assert abs((g > 0).mean() - 0.01) < 0.002
+    assert np.all(w[g == 0] == 1)
+    zs = np.array((1,) + wl.DOPANT_Z)
+    assert np.all(w <= np.minimum(6, zs[g]))
+    assert set(np.unique(g[g > 0])) == {1, 2, 3, 4}
+
+
+def test_hash_field_is_loguniform():
+    E = wl.hash_field(200000, 4, 0)
+    assert E.min() >= 10.0 and E.max() <= 5000.0
+    u = np.log(E / 10.0) / np.log(500.0)
+    assert abs(u.mean() - 0.5) < 0.005 and abs(u.var() - 1 / 12) < 0.002
+    assert not np.array_equal(wl.hash_field(100, 4, 0), wl.hash_field(100, 4, 1))

@@ -1,0 +1,147 @@
+"""Batched plan (cells of several gases with uneven windows, one persistent
+launch) against the oracle, per (gas, window) group, from identical inputs."""
+import numpy as np
+import pytest
+
+from paper_2202_10647_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "mixed": 1e-6}
+DT = 1.334e-16
+ZS = (1,) + wl.DOPANT_Z
+
+
+@pytest.fixture(scope="module")
+def env(orc):
+    import torch
+    from paper_2202_10647_amd import adkion
+    assert torch.cuda.is_available()
+    tables = [wl.synthetic_gas(z) for z in ZS]
+    gases = [adkion.Gas.from_table(t) for t in tables]
+    specs = [orc.GasSpec(t.U, t.l, t.m) for t in tables]
+    return torch, adkion, gases, specs
+
+
+def plan_state(cell_gas, cell_w, rows, seed):
+    return wl.plan_window_state(cell_gas, cell_w, ZS, rows, seed)
+
+
+def oracle_plan(orc, specs, cell_gas, cell_w, E, pops, lo, eps):
+    ref = pops.copy()
+    rlo = lo.copy()
+    for g in range(len(ZS)):
+        for w in range(1, 7):
+            idx = np.nonzero((cell_gas == g) & (cell_w == w))[0]
+            if idx.size == 0:
+                continue
+            p2, l2 = orc.ionize_step(specs[g], E[idx], DT, pops[: w + 1, idx], lo[idx], w, eps)
+            ref[: w + 1, idx] = p2
+            rlo[idx] = l2
+    return ref, rlo
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f64"])
+@pytest.mark.parametrize("cpl", [1, 2, 4, 0])
+def test_plan_matches_oracle(env, orc, prec, cpl):
+    torch, ak, gases, specs = env
+    n = 40000 + 123
+    cell_gas, cell_w = wl.batched_cells(n, seed=9, dopant_fraction=0.3)
+    plan = ak.Plan(gases, cell_gas, cell_w, prec=prec, eps=1e-8, cells_per_lane=cpl)
+    info = plan.info
+    assert info["rows"] == 7 and info["ngas"] == 5
+    if cpl:
+        assert info["cells_per_lane"] == cpl
+    else:
+        assert info["cells_per_lane"] in (1, 2, 4)
+    npdt = np.float32 if prec == "mixed" else np.float64
+    tdt = torch.float32 if prec == "mixed" else torch.float64
+    pops, lo = plan_state(cell_gas, cell_w, info["rows"], seed=100 + cpl)
+    pops = pops.astype(npdt)
+    E = wl.hash_field(n, seed=17, step=3, dtype=npdt)
+    E[::41] = 0.0
+    Pt = torch.from_numpy(pops).cuda()
+    Lt = torch.from_numpy(lo).cuda()
+    plan.step(torch.from_numpy(E).cuda(), DT, Pt, Lt)
+    torch.cuda.synchronize()
+    out, l2 = Pt.cpu().numpy().astype(np.float64), Lt.cpu().numpy()
+    ref, rlo = oracle_plan(orc, specs, cell_gas, cell_w, E.astype(np.float64), pops.astype(np.float64), lo, 1e-8)
+    assert np.array_equal(l2, rlo)
+    err = np.max(np.abs(out - ref))
+    assert err <= TOL[prec], err
+    # rows above each cell's window are untouched
+    for w in range(1, 6):
+        idx = np.nonzero(cell_w == w)[0]
+        assert np.all(out[w + 1:, idx] == np.float64(npdt(0.625)))
+    # a second launch of the same plan (counters were reset by the first)
+    plan.step(torch.from_numpy(E).cuda(), DT, Pt, Lt)
+    torch.cuda.synchronize()
+    ref2, rlo2 = oracle_plan(orc, specs, cell_gas, cell_w, E.astype(np.float64), out.astype(npdt).astype(np.float64),
+                             l2, 1e-8)
+    assert np.array_equal(Lt.cpu().numpy(), rlo2)
+    assert np.max(np.abs(Pt.cpu().numpy().astype(np.float64) - ref2)) <= TOL[prec]
+    plan.close()
+
+
+def test_plan_graph_replay(env, orc):
+    """Eight plan steps captured in one HIP graph, replayed three times with
+    eager work in between: bitwise equal to eager launches."""
+    torch, ak, gases, specs = env
+    n = 30000
+    cell_gas, cell_w = wl.batched_cells(n, seed=3, dopant_fraction=0.2)
+    plan = ak.Plan(gases, cell_gas, cell_w, prec="mixed", cells_per_lane=2)
+    rows = plan.info["rows"]
+    pops, lo = plan_state(cell_gas, cell_w, rows, seed=5)
+    P0 = torch.from_numpy(pops.astype(np.float32)).cuda()
+    L0 = torch.from_numpy(lo).cuda()
+    fields = torch.stack([torch.from_numpy(wl.hash_field(n, 11, s, dtype=np.float32)) for s in range(8)]).cuda()
+    P, L = P0.clone(), L0.clone()
+    for s in range(8):
+        plan.step(fields[s], DT, P, L)
+    torch.cuda.synchronize()
+    want_p, want_l = P.clone(), L.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for s in range(8):
+            plan.step(fields[s], DT, P, L)
+    for rep in range(3):
+        P.copy_(P0)
+        L.copy_(L0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(P, want_p) and torch.equal(L, want_l), rep
+        _ = float(P.sum().item())
+    del g
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f64"])
+def test_field_hash_matches_host_definition(env, prec):
+    torch, ak, gases, specs = env
+    n = 100003
+    tdt = torch.float32 if prec == "mixed" else torch.float64
+    E = torch.empty(n, dtype=tdt, device="cuda")
+    ak.field_hash(E, seed=4, step=12, E_lo=10.0, E_hi=5000.0)
+    g = E.cpu().numpy().astype(np.float64)
+    h = wl.hash_field(n, 4, 12, 10.0, 5000.0, dtype=np.float64)
+    rel = np.abs(g - h) / h
+    # exp of an argument up to ~8.5 rounded two ways: a few double ulps
+    assert rel.max() < (1.2e-7 if prec == "mixed" else 5e-15)
+    assert g.min() >= 10.0 * (1 - 1e-6) and g.max() <= 5000.0 * (1 + 1e-6)
+
+
+def test_plan_errors(env):
+    torch, ak, gases, specs = env
+    with pytest.raises(ak.AdkError) as e:
+        ak.Plan(gases[:2], np.array([0, 2], np.uint8), np.array([1, 1], np.uint8))
+    assert e.value.status == ak.ADK_ERANGE  # gas index out of range
+    with pytest.raises(ak.AdkError) as e:
+        ak.Plan(gases[:1], np.array([0], np.uint8), np.array([2], np.uint8))
+    assert e.value.status == ak.ADK_ERANGE  # w > Z
+    with pytest.raises(ak.AdkError) as e:
+        ak.Plan(gases, np.array([3], np.uint8), np.array([7], np.uint8))
+    assert e.value.status == ak.ADK_ERANGE  # w > ADK_PLAN_MAX_W
+    p = ak.Plan(gases, np.zeros(0, np.uint8), np.zeros(0, np.uint8))
+    assert p.info["ntiles"] == 0
+    p.close()
