@@ -199,8 +199,9 @@ __device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &c
     const double EL = fabs((double)cur.E);
     int p = cur.lo;
     p = p < Z ? p : Z;
-    // whole wavefront below the field cutoff and no shift due: T = I
-    if (__all(EL < E_cut && (double)cur.N[0] >= eps)) {
+    // T = I for the whole wavefront: every cell is either fully stripped
+    // (window [Z, Z], no rate) or below the field cutoff with no shift due
+    if (__all(p >= Z || (EL < E_cut && (double)cur.N[0] >= eps))) {
         static_for<0, W + 1>([&](auto ss) {
             constexpr int s = decltype(ss)::value;
             pops[(int64_t)s * n + c] = cur.N[s];
@@ -225,7 +226,7 @@ __device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &c
     window_rates<P, W>(sc, p, f, has_poly, x);
     double out[W + 1];
     chain_apply<P, W>(x, N, out);
-    const bool finite = EL <= 1.7976931348623157e308;
+    const bool finite = EL <= 1.7976931348623157e308 || p >= Z;  // no rate when stripped
     static_for<0, W + 1>([&](auto ss) {
         constexpr int s = decltype(ss)::value;
         // slots past level Z hold no population (rounding of the top row);
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void step_full_kernel(StepArgs a, const typ
             window_rates<P, W>(sc, p, f, has_poly, x);
             chain_apply<P, W>(x, N, out);
         }
-        const bool finite = EL <= 1.7976931348623157e308;
+        const bool finite = EL <= 1.7976931348623157e308 || p >= Z;  // no rate when stripped
         for (int k = p0; k < p; ++k) pops[(int64_t)k * n + c] = R(0);
         static_for<0, W + 1>([&](auto ss) {
             constexpr int s = decltype(ss)::value;

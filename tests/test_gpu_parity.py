@@ -390,3 +390,30 @@ def test_graph_replay_matches_eager(torch_dev, ak, orc):
             assert torch.equal(P, want_p) and torch.equal(L, want_l), f"replay {rep} ({tdt})"
             _ = (P.sum() + 1).item()  # eager work between replays
         del g
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_stripped_cells_and_nonfinite_field(torch_dev, ak, orc, prec):
+    """Fully stripped cells (lo = Z) keep their state for any field, also a
+    non-finite one; cells with an active window turn NaN for a NaN field."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, 7)
+    n = 640
+    comp, lo = wl.random_window_state(n, 7, 3, seed=44)
+    lo[: n // 2] = 7
+    comp[:, : n // 2] = 0.0
+    comp[0, : n // 2] = 1.0
+    E = wl.loguniform_field(n, 10.0, 5000.0, seed=45)
+    E[::7] = np.nan
+    E[3::11] = np.inf
+    pops = comp.astype(npdt(prec))
+    out, lo2 = run_step(torch, ak, gas, E.astype(npdt(prec)), pops, lo, w=3, eps=1e-8, layout="compact")
+    assert np.array_equal(out[:, : n // 2], pops[:, : n // 2]) and np.all(lo2[: n // 2] == 7)
+    bad = ~np.isfinite(E)
+    act = np.arange(n) >= n // 2
+    assert np.all(np.isnan(out[0, bad & act & (lo2 < 7)]))
+    ok = ~bad
+    ref, rlo = orc.ionize_step(spec, E[ok].astype(npdt(prec)).astype(np.float64), DT,
+                               pops[:, ok].astype(np.float64), lo[ok], 3, 1e-8)
+    assert np.array_equal(lo2[ok], rlo)
+    compare(out[:, ok], ref, prec, "stripped/nonfinite")
