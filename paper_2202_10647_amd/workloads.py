@@ -251,3 +251,67 @@ def plan_window_state(cell_gas, cell_w, gas_Z, rows: int, seed: int, fill: float
             pops[: w + 1, idx] = comp
             lo[idx] = l
     return pops.astype(dtype), lo
+
+
+def _splitmix_u01(seed: int, ctr: np.ndarray) -> np.ndarray:
+    """Uniform doubles in [0, 1) from the SplitMix64 finaliser of
+    seed + gamma * ctr (53 high bits)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + _SM_GAMMA * ctr.astype(np.uint64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+
+
+#: trained input range of the band-column surrogate: field [GV/m], step [s]
+SURROGATE_RANGE = dict(E_lo=10.0, E_hi=5000.0, dt_lo=0.02e-15, dt_hi=0.2e-15)
+
+
+def surrogate_samples(n: int, seed: int, Z: int, start: int = 0, E_lo: float = 10.0, E_hi: float = 5000.0,
+                      dt_lo: float = 0.02e-15, dt_hi: float = 0.2e-15):
+    """Training samples start..start+n-1 of the set drawn by `seed`: sample i
+    takes three uniforms from counters 3i+1, 3i+2, 3i+3 and maps them to a
+    log-uniform field E in [E_lo, E_hi], a log-uniform step dt in
+    [dt_lo, dt_hi] and a uniform source level k in 0..Z-1.  The device
+    sampler of adk_mlp_train uses the same definition."""
+    i = np.arange(start, start + n, dtype=np.uint64)
+    u0 = _splitmix_u01(seed, np.uint64(3) * i + np.uint64(1))
+    u1 = _splitmix_u01(seed, np.uint64(3) * i + np.uint64(2))
+    u2 = _splitmix_u01(seed, np.uint64(3) * i + np.uint64(3))
+    lE, lt = math.log(E_lo), math.log(dt_lo)
+    E = np.exp(lE + u0 * (math.log(E_hi) - lE))
+    dt = np.exp(lt + u1 * (math.log(dt_hi) - lt))
+    k = np.minimum(np.floor(u2 * Z), Z - 1).astype(np.int32)
+    return E, dt, k
+
+
+MLP_HIDDEN = 64
+MLP_EMB = 16
+
+
+def mlp_nparams(Z: int) -> int:
+    """Flat parameter count: emb[Z][16], W1u[64], W1v[64], W1e[64][16], b1[64],
+    W2[64][64], b2[64], W3[64][64], b3[64], W4[4][64], b4[4]."""
+    return Z * MLP_EMB + 2 * MLP_HIDDEN + MLP_HIDDEN * MLP_EMB + MLP_HIDDEN + 2 * (MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN) \
+        + 4 * MLP_HIDDEN + 4
+
+
+def mlp_init(Z: int, seed: int = 2022) -> np.ndarray:
+    """Seeded initial parameters (float32, flat, in the order above):
+    embeddings N(0, 1), weights uniform within +-sqrt(6 / fan_in) (He et al.
+    2015), biases zero."""
+    rng = np.random.default_rng(seed)
+    H, D = MLP_HIDDEN, MLP_EMB
+    b0 = math.sqrt(6.0 / (2 + D))
+    bh = math.sqrt(6.0 / H)
+    parts = [
+        rng.standard_normal(Z * D),
+        rng.uniform(-b0, b0, H), rng.uniform(-b0, b0, H), rng.uniform(-b0, b0, H * D), np.zeros(H),
+        rng.uniform(-bh, bh, H * H), np.zeros(H),
+        rng.uniform(-bh, bh, H * H), np.zeros(H),
+        rng.uniform(-bh, bh, 4 * H), np.zeros(4),
+    ]
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == mlp_nparams(Z)
+    return flat

@@ -1,0 +1,217 @@
+"""Pins of the CPU reference of the band-column surrogate network: bfloat16
+rounding, the [out][in] weight layout, softmax invariants, the backward pass
+against central finite differences, the Adam update, and the band-column
+update against the analytic oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2202_10647_amd import workloads as wl
+
+
+def test_param_count_and_init():
+    for Z in (1, 7, 36, 54):
+        assert mlp.nparams(Z) == wl.mlp_nparams(Z) == 16 * Z + 9796
+    p = wl.mlp_init(36, seed=1)
+    assert p.dtype == np.float32 and p.size == 10372
+    b = mlp.unpack(p, 36)
+    assert np.all(b["b1"] == 0) and np.all(b["b4"] == 0)
+    assert np.abs(b["W2"]).max() <= math.sqrt(6 / 64)
+
+
+def test_bf16_rounding():
+    # 8 significant bits, ties to even
+    assert mlp.bf16(1.0) == 1.0
+    assert mlp.bf16(1.0 + 2.0 ** -8) == 1.0            # tie -> even (1.0)
+    assert mlp.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6  # tie -> even
+    assert mlp.bf16(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert mlp.bf16(-3.14159) == -3.140625
+    assert mlp.bf16(0.0) == 0.0
+    x = np.random.default_rng(0).standard_normal(10000) * 100
+    r = mlp.bf16(x)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8)
+    # values already in bfloat16 are fixed points
+    assert np.array_equal(mlp.bf16(r), r)
+    # agrees with truncating a float32 after adding the rounding bias
+    # (the usual bit-level definition), on values exact in float32
+    f = x.astype(np.float32)
+    bits = f.view(np.uint32).astype(np.uint64)
+    rb = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16) << 16
+    ref = rb.astype(np.uint32).view(np.float32).astype(np.float64)
+    assert np.array_equal(mlp.bf16(f.astype(np.float64)), ref)
+
+
+def _routing_net(Z, a=3, b=10, c=20, j=2):
+    """A network that carries max(u, 0) from input to logit j along one
+    path: W1u[a] = 1, W2[b][a] = 1, W3[c][b] = 1, W4[j][c] = 1."""
+    blocks = {name: np.zeros(shape) for name, shape in mlp.block_shapes(Z)}
+    blocks["W1u"][a] = 1.0
+    blocks["W2"][b, a] = 1.0
+    blocks["W3"][c, b] = 1.0
+    blocks["W4"][j, c] = 1.0
+    return blocks
+
+
+@pytest.mark.parametrize("bf16_ops", [False, True])
+def test_weight_layout_out_in(bf16_ops):
+    Z = 5
+    blocks = _routing_net(Z)
+    u = np.array([0.75, -0.5, 0.3])
+    Q, _ = mlp.forward(mlp.pack(blocks, Z), Z, u, np.zeros(3), np.zeros(3, int), bf16_ops)
+    h = np.maximum(u, 0.0)
+    if bf16_ops:
+        h = mlp.bf16(h)
+    want = np.exp(h) / (np.exp(h) + 3.0)
+    assert np.allclose(Q[:, 2], want, rtol=1e-15, atol=0)
+    assert np.allclose(Q[:, 0], 1.0 / (np.exp(h) + 3.0), rtol=1e-15, atol=0)
+    # the transposed path carries nothing
+    blocks = _routing_net(Z)
+    blocks["W2"] = blocks["W2"].T.copy()
+    Q, _ = mlp.forward(mlp.pack(blocks, Z), Z, u, np.zeros(3), np.zeros(3, int), bf16_ops)
+    assert np.allclose(Q, 0.25)
+
+
+def test_embedding_selects_level():
+    Z = 6
+    blocks = _routing_net(Z)
+    blocks["W1u"][:] = 0.0
+    blocks["emb"][4, 7] = 2.0
+    blocks["W1e"][3, 7] = 1.0  # hidden 3 reads embedding component 7
+    k = np.array([0, 4, 5, 4])
+    Q, _ = mlp.forward(mlp.pack(blocks, Z), Z, np.zeros(4), np.zeros(4), k, False)
+    want = np.where(k == 4, np.exp(2.0) / (np.exp(2.0) + 3.0), 0.25)
+    assert np.allclose(Q[:, 2], want, rtol=1e-15)
+
+
+def test_softmax_invariants():
+    Z = 36
+    p = wl.mlp_init(Z, 3).astype(np.float64)
+    rng = np.random.default_rng(1)
+    u, v, k = rng.uniform(-1, 1, 500), rng.uniform(-1, 1, 500), rng.integers(0, Z, 500)
+    Q, _ = mlp.forward(p, Z, u, v, k)
+    assert np.all(Q > 0) and np.allclose(Q.sum(axis=1), 1.0, atol=1e-15)
+    b = mlp.unpack(p.copy(), Z)
+    b["b4"] += 7.5
+    Q2, _ = mlp.forward(mlp.pack(b, Z), Z, u, v, k)
+    assert np.allclose(Q, Q2, atol=1e-15)
+
+
+def _targets(n, rng):
+    P = rng.dirichlet(np.ones(4) * 0.5, n)
+    P[::3, 3] = 0.0  # exact zeros occur in real band columns
+    return P / P.sum(axis=1, keepdims=True)
+
+
+def test_backward_matches_finite_differences():
+    """Central differences of the smooth (FP64) network against the
+    analytic backward pass, for every parameter block."""
+    Z = 4
+    rng = np.random.default_rng(7)
+    p = wl.mlp_init(Z, 11).astype(np.float64)
+    b = mlp.unpack(p.copy(), Z)
+    for name in ("b1", "b2", "b3", "b4"):
+        b[name][:] = rng.uniform(-0.3, 0.3, b[name].shape)
+    p = mlp.pack(b, Z)
+    n = 9
+    u, v, k = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.integers(0, Z, n)
+    P = _targets(n, rng)
+    L0, g = mlp.loss_and_grad(p, Z, u, v, k, P, bf16_ops=False)
+    assert L0 > 0
+    off = 0
+    h = 1e-6
+    for name, shape in mlp.block_shapes(Z):
+        m = int(np.prod(shape))
+        for i in rng.choice(m, size=min(m, 12), replace=False):
+            q = p.copy()
+            q[off + i] += h
+            Lp = mlp.loss(mlp.forward(q, Z, u, v, k, False)[0], P)
+            q[off + i] -= 2 * h
+            Lm = mlp.loss(mlp.forward(q, Z, u, v, k, False)[0], P)
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - g[off + i]) <= 1e-7 * max(1.0, abs(fd)) + 1e-9, (name, i, fd, g[off + i])
+        off += m
+
+
+def test_bf16_backward_is_straight_through():
+    """With bf16 operands the backward pass is the FP64 backward of the
+    network whose weights and activations are the rounded values: equal to
+    the smooth gradient when the parameters are already bfloat16 and every
+    activation is exact (a network whose hidden values are small integers)."""
+    Z = 3
+    blocks = _routing_net(Z)
+    blocks["b2"][:] = 1.0
+    blocks["b3"][:] = -2.0
+    blocks["b4"][:] = [0.5, -0.25, 0.0, 1.0]
+    p = mlp.pack(blocks, Z)
+    u = np.array([1.0, 2.0, 3.0])
+    P = np.array([[0.1, 0.2, 0.3, 0.4], [1, 0, 0, 0], [0.25, 0.25, 0.5, 0.0]])
+    L1, g1 = mlp.loss_and_grad(p, Z, u, np.zeros(3), np.zeros(3, int), P, bf16_ops=True)
+    L0, g0 = mlp.loss_and_grad(p, Z, u, np.zeros(3), np.zeros(3, int), P, bf16_ops=False)
+    assert L1 == L0
+    assert np.array_equal(g1, g0)
+
+
+def test_adam_first_step_and_bias_correction():
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    p0 = np.zeros(4)
+    p1, m, v = mlp.adam_step(p0, g, np.zeros(4), np.zeros(4), 1, lr=0.01)
+    # after one step the bias-corrected moments are g and g^2
+    assert np.allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-15, atol=0)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+    # constant gradient: every later step is again lr * g/(|g| + eps)
+    p, mm, vv = p1, m, v
+    for t in range(2, 6):
+        q, mm, vv = mlp.adam_step(p, g, mm, vv, t, lr=0.01)
+        assert np.allclose(q - p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-18)
+        p = q
+
+
+@pytest.mark.parametrize("w", [1, 2, 3])
+def test_band_update_with_exact_columns_is_the_step(orc, w):
+    """Band columns taken from the analytic oracle reproduce the oracle's
+    own windowed step: the lumping at the window top is exact."""
+    Z = 7
+    t = wl.synthetic_gas(Z)
+    spec = orc.GasSpec(t.U, t.l, t.m)
+    n = 600
+    N, lo = wl.random_window_state(n, Z, w, seed=5)
+    E = wl.loguniform_field(n, 10.0, 3000.0, seed=6)
+    dt = 1.3e-16
+    ref, rlo = orc.ionize_step(spec, E, dt, N, lo, w, 0.0)
+    cols = []
+    for s in range(w):
+        ks = np.minimum(lo.astype(int) + s, Z - 1)
+        cols.append(mlp.exact_band_columns(orc, spec, Z, E, dt, ks))
+    got = mlp.band_update(N, lo, w, Z, cols, np.ones(n, bool))
+    assert np.array_equal(rlo, lo)
+    assert np.max(np.abs(got - ref)) < 1e-14
+
+
+def test_exact_band_columns_closed_forms(orc):
+    """Band columns are probability vectors; for a single level with a
+    stripped successor the column is (e^-x, 1 - e^-x, 0, 0)."""
+    Z = 7
+    t = wl.synthetic_gas(Z)
+    spec = orc.GasSpec(t.U, t.l, t.m)
+    E, dt, k = wl.surrogate_samples(400, 3, Z)
+    cols = mlp.exact_band_columns(orc, spec, Z, E, dt, k)
+    assert np.all(cols >= 0) and np.allclose(cols.sum(axis=0), 1.0, atol=1e-14)
+    top = k == Z - 1
+    x = orc.rates(spec, E[top], Z - 1, 1)[0] * dt[top]
+    assert np.allclose(cols[0, top], np.exp(-x), rtol=1e-13, atol=1e-300)
+    assert np.allclose(cols[1, top], -np.expm1(-x), rtol=1e-13, atol=1e-300)
+    assert np.all(cols[2:, top] == 0)
+
+
+def test_surrogate_samples_definition():
+    E, dt, k = wl.surrogate_samples(20000, 9, 36)
+    assert E.min() >= 10 and E.max() <= 5000 and dt.min() >= 2e-17 and dt.max() <= 2e-16
+    assert k.min() == 0 and k.max() == 35
+    # counters are global: a slice starting at i equals the tail of the full draw
+    E2, dt2, k2 = wl.surrogate_samples(100, 9, 36, start=19900)
+    assert np.array_equal(E2, E[19900:]) and np.array_equal(k2, k[19900:])
+    # log-uniform: log E is uniform
+    le = (np.log(E) - np.log(10)) / np.log(500)
+    assert abs(le.mean() - 0.5) < 0.01 and abs(le.var() - 1 / 12) < 0.005
