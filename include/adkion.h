@@ -210,6 +210,138 @@ int adk_plan_destroy(adk_plan *plan);
 int adk_field_hash(void *E, int64_t n, uint64_t seed, int64_t step, double E_lo, double E_hi, adk_prec prec,
                    hipStream_t stream);
 
+
+/* ---------------------------------------------------------------------------
+ * Band-column surrogate.  The exact step (Eqs. (2)-(5)) moves the population
+ * of a source level k to k, k+1, k+2, ...; within the reduced window of
+ * Sec. 3 (three rates, absorbing top) only four destinations matter: k, k+1,
+ * k+2 and "k+3 or beyond", which the window top absorbs.  A small network
+ * predicts that column, P(k -> k+d), d = 0..3, from (|E|, dt, k):
+ *
+ *   u = log10|E| and v = log10(dt omega_a) (dt in units of tau_a = 1/omega_a),
+ *       each mapped from its trained range onto [-1, 1];
+ *   z1 = W1u u + W1v v + W1e emb[k] + b1, h1 = relu(z1)   (FP32)
+ *   h2 = relu(W2 h1 + b2), h3 = relu(W3 h2 + b3), z4 = W4 h3 + b4
+ *        (bfloat16 operands on the matrix cores, FP32 accumulation)
+ *   P = softmax(z4)  (FP32): non-negative, sums to 1, so a step built from such
+ *        columns conserves the total population.
+ *
+ * Parameters: one flat FP32 vector, weights stored [out][in], blocks in this
+ * order: emb[Z][16], W1u[64], W1v[64], W1e[64][16], b1[64], W2[64][64],
+ * b2[64], W3[64][64], b3[64], W4[4][64], b4[4]; adk_mlp_nparams(Z) entries.
+ * Training minimises the batch mean of the cross entropy -sum_d P_d log Q_d
+ * against exact columns from the FP64 analytic solver, with Adam (Kingma &
+ * Ba 2015) and a cosine learning-rate schedule.  Every reduction of the
+ * training step has a fixed order, so training is bitwise reproducible.
+ */
+#define ADK_MLP_HIDDEN 64
+#define ADK_MLP_EMB 16
+#define ADK_MLP_BAND 4
+
+typedef struct adk_mlp adk_mlp; /* opaque: FP32 master weights, Adam moments, training buffers */
+
+typedef struct {
+    double E_lo, E_hi;   /* trained field range, GV/m (0 < E_lo < E_hi)        */
+    double dt_lo, dt_hi; /* trained step range, s (0 < dt_lo < dt_hi)         */
+} adk_mlp_range;         /* NULL => [10, 5000] GV/m and [0.02, 0.2] fs          */
+
+typedef struct {
+    int64_t nsamples;    /* training set size (samples 0..nsamples-1 of seed)  */
+    int32_t iters;       /* Adam steps to take in this call                     */
+    int32_t total_iters; /* horizon of the cosine schedule (>= 1)               */
+    int32_t batch;       /* samples per step, 1..nsamples                       */
+    double lr, lr_min;   /* schedule lr(t) = lr_min + (lr - lr_min)(1 + cos(pi min(t,T)/T))/2 */
+    uint64_t seed;       /* training-set seed                                   */
+} adk_train_cfg;
+
+/* Number of FP32 parameters for a gas of Z levels: 16 Z + 9796; -1 if Z is
+ * outside [1, ADK_MAX_Z]. */
+int64_t adk_mlp_nparams(int32_t Z);
+
+/* Create a network for `gas` (its Z and omega_a) from host FP32 parameters
+ * params[adk_mlp_nparams(Z)] (copied; initial values are the caller's, e.g. a
+ * seeded draw).  range NULL => defaults above.  Adam moments start at zero,
+ * step count 0.  Synchronous; allocates device memory.  Errors: ADK_EINVAL
+ * (null gas/params/out, range not ordered or not positive/finite, non-finite
+ * parameter), ADK_EDEVICE/ADK_ENOMEM. */
+int adk_mlp_create(const adk_gas *gas, const float *params, const adk_mlp_range *range, adk_mlp **out);
+
+/* Free a network (NULL accepted); no enqueued work may still use it. */
+int adk_mlp_destroy(adk_mlp *mlp);
+
+/* Host copies of the state: params, Adam moments m and v (each
+ * [adk_mlp_nparams(Z)], any may be NULL) and the number of Adam steps taken
+ * (step may be NULL).  Synchronous.  ADK_EINVAL for a NULL mlp. */
+int adk_mlp_get_state(const adk_mlp *mlp, float *params, float *m, float *v, int64_t *step);
+
+/* Exact band columns from the FP64 analytic solver (training targets):
+ * for sample i, the step dt[i] of a unit population at level k[i] with a
+ * window of three rates and absorbing top (Eqs. (2)-(5) restricted as in
+ * Sec. 3), i.e. cols[d][i] = T[k+d, k] for d < 3 and the remainder for d = 3;
+ * levels past Z carry no rate.  Device arrays E[n] (double, GV/m), dt[n]
+ * (double, s), k[n] (int32, 0 <= k < Z), cols[4][n] (double).  Errors:
+ * ADK_EINVAL (null gas or arrays with n > 0, n < 0).  k outside [0, Z) or
+ * dt <= 0 yields NaN columns for that sample. */
+int adk_band_columns(const adk_gas *gas, const double *E, const double *dt, const int32_t *k, int64_t n,
+                     double *cols, hipStream_t stream);
+
+/* Network output Q[4][n] (float, device) for device inputs E[n], dt[n]
+ * (double) and k[n] (int32, clamped to [0, Z-1]).  Errors: ADK_EINVAL. */
+int adk_mlp_forward(const adk_mlp *mlp, const double *E, const double *dt, const int32_t *k, int64_t n,
+                    float *Q, hipStream_t stream);
+
+/* Loss and gradient of the current parameters over the n given samples
+ * (targets from adk_band_columns, computed inside): grad[adk_mlp_nparams(Z)]
+ * and loss[1] are device floats.  The backward pass treats the bfloat16
+ * rounding of the forward pass as the identity.  Allocates scratch on first
+ * use of a larger n.  Errors: ADK_EINVAL (null arguments, n < 1, gas with
+ * another Z than the network's), ADK_EDEVICE/ADK_ENOMEM. */
+int adk_mlp_loss_grad(adk_mlp *mlp, const adk_gas *gas, const double *E, const double *dt, const int32_t *k,
+                      int64_t n, float *grad, float *loss, hipStream_t stream);
+
+/* Train on the analytic solver's columns: the training set is samples
+ * 0..nsamples-1 of cfg->seed (sample i: E log-uniform in the field range, dt
+ * log-uniform in the step range, k uniform in 0..Z-1, from three uniforms
+ * u_j = (z >> 11) 2^-53, z the SplitMix64 finaliser of
+ * seed + 0x9E3779B97F4A7C15 * (3i + j + 1), j = 0, 1, 2), generated and
+ * labelled on the device.  Adam step t (counted over the life of the
+ * network, so training may be split over calls or resumed from a saved
+ * state) uses batch number t mod floor(nsamples / batch).  Adam: beta1 0.9,
+ * beta2 0.999, epsilon 1e-8.  loss_out (host, may be NULL) receives the batch
+ * loss of each step taken; the call then synchronises the stream.  Errors:
+ * ADK_EINVAL (null arguments, iters < 0, total_iters < 1, batch < 1 or >
+ * nsamples, lr or lr_min negative or non-finite, gas with another Z than the
+ * network's), ADK_EDEVICE/ADK_ENOMEM. */
+int adk_mlp_train(adk_mlp *mlp, const adk_gas *gas, const adk_train_cfg *cfg, float *loss_out,
+                  hipStream_t stream);
+
+/* Save the whole state (parameters, Adam moments, step count, ranges) to a
+ * binary file; adk_mlp_load restores it for `gas` (same Z) so that further
+ * training continues bitwise as if uninterrupted.  Synchronous.  Errors:
+ * ADK_EINVAL (null arguments, unreadable/unwritable or malformed file, Z
+ * mismatch), ADK_EDEVICE/ADK_ENOMEM. */
+int adk_mlp_save(const adk_mlp *mlp, const char *path);
+int adk_mlp_load(const adk_gas *gas, const char *path, adk_mlp **out);
+
+/* One ionization step in surrogate form (compact layout, float populations):
+ * the window shift at the start of the step is that of ionize_step; then a
+ * cell whose |E| lies in the trained field range (and dt in the trained step
+ * range) advances with the network's band columns, one per source level of
+ * its window, destinations past the window top lumped into the top; every
+ * other cell takes the analytic step of ionize_step (ADK_MIXED).  win->prec
+ * must be ADK_MIXED, win->layout ADK_LAYOUT_COMPACT, 1 <= win->w <= 3.
+ * counters (device, 2 x uint64, may be NULL) are incremented by: [0] cells
+ * with a window below the top level that fell back to the analytic step with
+ * |E| at or above the gas's field cutoff (below it the step is the identity
+ * either way), [1] (cell, source level) pairs evaluated by the network.
+ * Allocates nothing and never synchronises.  Errors: ADK_EINVAL (null
+ * arguments with ncells > 0, dt <= 0 or non-finite, eps < 0, prec or layout
+ * other than above, network and gas of different Z), ADK_ERANGE (w outside
+ * [1, 3] or w > Z). */
+int adk_surrogate_step(const adk_gas *gas, const adk_mlp *mlp, const void *E, int64_t ncells, double dt,
+                       void *pops, uint8_t *lo, const adk_window *win, unsigned long long *counters,
+                       hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,9 @@ ADK_MAX_Z, ADK_MAX_W, ADK_M_AVERAGE = 64, 8, -1
 #: every function the header declares (checked by the CPU test suite)
 EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "adk_gas_destroy",
            "adk_gas_levels", "adk_rates", "adk_chain_advance", "ionize_step", "adk_plan_create",
-           "adk_plan_step", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash")
+           "adk_plan_step", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash", "adk_mlp_nparams",
+           "adk_mlp_create", "adk_mlp_destroy", "adk_mlp_get_state", "adk_band_columns", "adk_mlp_forward",
+           "adk_mlp_loss_grad", "adk_mlp_train", "adk_mlp_save", "adk_mlp_load", "adk_surrogate_step")
 ADK_PLAN_MAX_GAS, ADK_PLAN_MAX_W = 8, 6
 
 
@@ -47,6 +49,17 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("ngas", ctypes.c_int32), ("nbuckets", ctypes.c_int32), ("ntiles", ctypes.c_int32),
                 ("cells_per_lane", ctypes.c_int32), ("grid", ctypes.c_int32), ("rows", ctypes.c_int32),
                 ("from_cache", ctypes.c_int32), ("tuned_us", ctypes.c_double)]
+
+
+class _MlpRange(ctypes.Structure):
+    _fields_ = [("E_lo", ctypes.c_double), ("E_hi", ctypes.c_double), ("dt_lo", ctypes.c_double),
+                ("dt_hi", ctypes.c_double)]
+
+
+class _TrainCfg(ctypes.Structure):
+    _fields_ = [("nsamples", ctypes.c_int64), ("iters", ctypes.c_int32), ("total_iters", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_double), ("lr_min", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
 
 
 class _Window(ctypes.Structure):
@@ -96,6 +109,28 @@ def lib():
     L.adk_plan_destroy.argtypes = [vp]
     L.adk_field_hash.restype = ctypes.c_int
     L.adk_field_hash.argtypes = [vp, i64, ctypes.c_uint64, i64, dbl, dbl, ctypes.c_int, vp]
+    L.adk_mlp_nparams.restype = i64
+    L.adk_mlp_nparams.argtypes = [i32]
+    L.adk_mlp_create.restype = ctypes.c_int
+    L.adk_mlp_create.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_MlpRange), ctypes.POINTER(vp)]
+    L.adk_mlp_destroy.restype = ctypes.c_int
+    L.adk_mlp_destroy.argtypes = [vp]
+    L.adk_mlp_get_state.restype = ctypes.c_int
+    L.adk_mlp_get_state.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64)]
+    L.adk_band_columns.restype = ctypes.c_int
+    L.adk_band_columns.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    L.adk_mlp_forward.restype = ctypes.c_int
+    L.adk_mlp_forward.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    L.adk_mlp_loss_grad.restype = ctypes.c_int
+    L.adk_mlp_loss_grad.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp]
+    L.adk_mlp_train.restype = ctypes.c_int
+    L.adk_mlp_train.argtypes = [vp, vp, ctypes.POINTER(_TrainCfg), vp, vp]
+    L.adk_mlp_save.restype = ctypes.c_int
+    L.adk_mlp_save.argtypes = [vp, ctypes.c_char_p]
+    L.adk_mlp_load.restype = ctypes.c_int
+    L.adk_mlp_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.adk_surrogate_step.restype = ctypes.c_int
+    L.adk_surrogate_step.argtypes = [vp, vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp, vp]
     _lib = L
     return L
 
@@ -301,3 +336,135 @@ def field_hash(E, seed: int, step: int, E_lo: float = 10.0, E_hi: float = 5000.0
                               float(E_hi), _prec_of(E), _stream(stream))
     _check(st, "adk_field_hash")
     return E
+
+
+# ---------------------------------------------------------------------------
+# Band-column surrogate (see include/adkion.h)
+
+def mlp_nparams(Z: int) -> int:
+    return int(lib().adk_mlp_nparams(int(Z)))
+
+
+def band_columns(gas: Gas, E, dt, k, out=None, stream=None):
+    """Exact FP64 band columns cols[4][n] of samples (E, dt, k): float64 E and
+    dt, int32 k device tensors."""
+    import torch
+    n = E.numel()
+    if E.dtype != torch.float64 or dt.dtype != torch.float64 or k.dtype != torch.int32:
+        raise ValueError("E, dt must be float64 and k int32")
+    if dt.numel() != n or k.numel() != n:
+        raise ValueError("E, dt, k must have one length")
+    if out is None:
+        out = torch.empty((4, n), dtype=torch.float64, device=E.device)
+    st = lib().adk_band_columns(gas.handle, _dev(E, "E"), _dev(dt, "dt"), _dev(k, "k"), n, _dev(out, "cols"),
+                                _stream(stream))
+    _check(st, "adk_band_columns")
+    return out
+
+
+class Mlp:
+    """The band-column network of one gas (weights, Adam state, training)."""
+
+    def __init__(self, gas: Gas, params=None, E_range=(10.0, 5000.0), dt_range=(0.02e-15, 0.2e-15), _handle=None):
+        self._gas = gas
+        self.Z = gas.Z
+        self.nparams = mlp_nparams(gas.Z)
+        if _handle is not None:
+            self._h = _handle
+            return
+        prm = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if prm.size != self.nparams:
+            raise ValueError(f"params must have {self.nparams} entries")
+        rng = _MlpRange(float(E_range[0]), float(E_range[1]), float(dt_range[0]), float(dt_range[1]))
+        h = ctypes.c_void_p()
+        st = lib().adk_mlp_create(gas.handle, prm.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                  ctypes.byref(rng), ctypes.byref(h))
+        _check(st, "adk_mlp_create")
+        self._h = h
+
+    @classmethod
+    def load(cls, gas: Gas, path: str):
+        h = ctypes.c_void_p()
+        _check(lib().adk_mlp_load(gas.handle, str(path).encode(), ctypes.byref(h)), "adk_mlp_load")
+        return cls(gas, _handle=h)
+
+    def save(self, path: str):
+        _check(lib().adk_mlp_save(self._h, str(path).encode()), "adk_mlp_save")
+
+    def state(self):
+        """(params, m, v, step) as host float32 arrays and int."""
+        p = np.empty(self.nparams, np.float32)
+        m = np.empty(self.nparams, np.float32)
+        v = np.empty(self.nparams, np.float32)
+        step = ctypes.c_int64()
+        st = lib().adk_mlp_get_state(self._h, p.ctypes.data_as(ctypes.c_void_p), m.ctypes.data_as(ctypes.c_void_p),
+                                     v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(step))
+        _check(st, "adk_mlp_get_state")
+        return p, m, v, int(step.value)
+
+    def forward(self, E, dt, k, stream=None):
+        import torch
+        n = E.numel()
+        Q = torch.empty((4, n), dtype=torch.float32, device=E.device)
+        st = lib().adk_mlp_forward(self._h, _dev(E, "E"), _dev(dt, "dt"), _dev(k, "k"), n, _dev(Q, "Q"),
+                                   _stream(stream))
+        _check(st, "adk_mlp_forward")
+        return Q
+
+    def loss_grad(self, E, dt, k, stream=None):
+        import torch
+        n = E.numel()
+        g = torch.empty(self.nparams, dtype=torch.float32, device=E.device)
+        L = torch.empty(1, dtype=torch.float32, device=E.device)
+        st = lib().adk_mlp_loss_grad(self._h, self._gas.handle, _dev(E, "E"), _dev(dt, "dt"), _dev(k, "k"), n,
+                                     _dev(g, "grad"), _dev(L, "loss"), _stream(stream))
+        _check(st, "adk_mlp_loss_grad")
+        return L, g
+
+    def train(self, iters: int, nsamples: int = 1_000_000, batch: int = 4096, lr: float = 3e-3,
+              lr_min: float = 1e-5, total_iters: Optional[int] = None, seed: int = 1, stream=None) -> np.ndarray:
+        """Adam steps on the analytic solver's columns; returns the batch losses."""
+        cfg = _TrainCfg(int(nsamples), int(iters), int(total_iters or iters), int(batch), float(lr), float(lr_min),
+                        int(seed) & 0xFFFFFFFFFFFFFFFF)
+        out = np.zeros(max(1, int(iters)), np.float32)
+        st = lib().adk_mlp_train(self._h, self._gas.handle, ctypes.byref(cfg), out.ctypes.data_as(ctypes.c_void_p),
+                                 _stream(stream))
+        _check(st, "adk_mlp_train")
+        return out[: int(iters)]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().adk_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def surrogate_step(gas: Gas, mlp: Mlp, E, dt: float, pops, lo, w: int = 3, eps: float = 1e-8, counters=None,
+                   stream=None):
+    """Surrogate form of the step, in place on float32 pops[(w+1)][n] and lo;
+    counters: optional int64 device tensor of 2 entries (see adk_surrogate_step)."""
+    import torch
+    n = E.numel()
+    if E.dtype != torch.float32 or pops.dtype != torch.float32 or tuple(pops.shape) != (w + 1, n):
+        raise ValueError(f"E float32[{n}] and pops float32[{w + 1}][{n}] expected")
+    if lo.dtype != torch.uint8 or lo.numel() != n:
+        raise ValueError("lo must be uint8[ncells]")
+    cptr = None
+    if counters is not None:
+        if counters.dtype != torch.int64 or counters.numel() != 2:
+            raise ValueError("counters must be int64[2]")
+        cptr = _dev(counters, "counters")
+    win = _Window(int(w), float(eps), ADK_LAYOUT_COMPACT, ADK_MIXED)
+    st = lib().adk_surrogate_step(gas.handle, mlp.handle, _dev(E, "E"), n, float(dt), _dev(pops, "pops"),
+                                  _dev(lo, "lo"), ctypes.byref(win), cptr, _stream(stream))
+    _check(st, "adk_surrogate_step")
+    return pops, lo

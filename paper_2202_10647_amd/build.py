@@ -23,8 +23,9 @@ WIDTHS = range(1, 9)
 
 
 def _jobs(objdir):
-    """(command, object) pairs: host table builder, ABI, one kernel
-    instantiation per (precision, window width)."""
+    """(command, object) pairs: host table builder, ABI, batched plan,
+    surrogate network and step, one kernel instantiation per (precision,
+    window width)."""
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     jobs = []
     obj = os.path.join(objdir, "gas_table.o")
@@ -32,8 +33,9 @@ def _jobs(objdir):
                   "-o", obj], obj))
     obj = os.path.join(objdir, "abi.o")
     jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "abi.hip"), "-o", obj], obj))
-    obj = os.path.join(objdir, "plan.o")
-    jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "plan.hip"), "-o", obj], obj))
+    for name in ("plan", "mlp", "sur"):
+        obj = os.path.join(objdir, f"{name}.o")
+        jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", obj], obj))
     for prec in PRECS:
         for cpl in (1, 2, 4):
             obj = os.path.join(objdir, f"plan_{prec}_{cpl}.o")

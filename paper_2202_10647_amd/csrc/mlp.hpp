@@ -1,0 +1,255 @@
+// Band-column surrogate network on the matrix cores (gfx950).
+//
+// For a source level k, a field |E| and a step dt the network predicts the
+// column of exp(dt A) (Eqs. (2)-(5)) that starts at level k, cut to four
+// entries: the probabilities to end the step at k, k+1, k+2 and at k+3 or
+// beyond.  The reduced window of Sec. 3 (three rates, absorbing top) has
+// exactly this band, so a window step is a sum of such columns.
+//
+//   z1 = W1u u + W1v v + W1e emb[k] + b1,  h1 = relu(z1)            (VALU, FP32)
+//   h2 = relu(W2 h1 + b2),  h3 = relu(W3 h2 + b3),  z4 = W4 h3 + b4  (MFMA)
+//   Q  = softmax(z4)                                                 (VALU, FP32)
+//
+// Layers 2-4 run as v_mfma_f32_16x16x32_bf16: bfloat16 operands, FP32
+// accumulation.  A wavefront evaluates 16 samples at a time with the samples
+// on the N dimension, so that the accumulator tile of one layer (unit m, sample
+// n) is, after ReLU and conversion, the B operand of the next: lane (g, n),
+// g = lane / 16, holds units 16t + 4g + i (i < 4) of output tile t, and the
+// K = 32 chunk c of the next layer reads, in element i of lane (g, n), unit
+// hid(c, g, i) below.  The weight (A) operand uses the same unit order, so the
+// permutation cancels in the product.  Layer 1 is linear in the embedding, so
+// W1e emb[k] + b1 is tabulated per level once per workgroup; what remains per
+// sample is one or two FMAs per hidden unit.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "adkion.h"
+
+namespace adk {
+
+constexpr int kH = ADK_MLP_HIDDEN;  // hidden width
+constexpr int kEmb = ADK_MLP_EMB;   // embedding width
+constexpr int kBand = ADK_MLP_BAND; // output band
+constexpr int kWStride = 72;        // bf16 row stride of staged weights (spreads LDS banks)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Offsets of the parameter blocks in the flat FP32 vector (weights [out][in]).
+struct MlpLayout {
+    int Z, emb, W1u, W1v, W1e, b1, W2, b2, W3, b3, W4, b4, n;
+    __host__ __device__ static MlpLayout of(int Z)
+    {
+        MlpLayout L{};
+        int o = 0;
+        L.Z = Z;
+        L.emb = o; o += Z * kEmb;
+        L.W1u = o; o += kH;
+        L.W1v = o; o += kH;
+        L.W1e = o; o += kH * kEmb;
+        L.b1 = o; o += kH;
+        L.W2 = o; o += kH * kH;
+        L.b2 = o; o += kH;
+        L.W3 = o; o += kH * kH;
+        L.b3 = o; o += kH;
+        L.W4 = o; o += kBand * kH;
+        L.b4 = o; o += kBand;
+        L.n = o;
+        return L;
+    }
+};
+
+// Weights as staged in LDS by every workgroup that evaluates the network.
+struct MlpShared {
+    __bf16 W2[kH * kWStride];
+    __bf16 W3[kH * kWStride];
+    __bf16 W4[16 * kWStride];  // rows 4..15 zero: a full 16-row A tile
+    float b2[kH], b3[kH], b4[16];
+    float wu[kH], wv[kH];
+    float ctab[ADK_MAX_Z * kH];  // W1e emb[k] + b1 (+ W1v v when v is fixed)
+};
+
+// Hidden unit carried by element i of K chunk c in lane group g.
+__host__ __device__ constexpr int hid(int c, int g, int i)
+{
+    return 32 * c + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
+}
+
+// Stage the bf16 weights, the biases and the per-level layer-1 table; v is
+// folded into the table when fold_v (inference at one step size).
+__device__ inline void stage_mlp(MlpShared &s, const float *__restrict__ prm, const MlpLayout &L, float v,
+                                 bool fold_v)
+{
+    for (int t = threadIdx.x; t < kH * kH; t += blockDim.x) {
+        const int o = t / kH, i = t % kH;
+        s.W2[o * kWStride + i] = (__bf16)prm[L.W2 + t];
+        s.W3[o * kWStride + i] = (__bf16)prm[L.W3 + t];
+    }
+    for (int t = threadIdx.x; t < 16 * kH; t += blockDim.x) {
+        const int o = t / kH, i = t % kH;
+        s.W4[o * kWStride + i] = o < kBand ? (__bf16)prm[L.W4 + t] : (__bf16)0.0f;
+    }
+    for (int t = threadIdx.x; t < kH; t += blockDim.x) {
+        s.b2[t] = prm[L.b2 + t];
+        s.b3[t] = prm[L.b3 + t];
+        s.wu[t] = prm[L.W1u + t];
+        s.wv[t] = prm[L.W1v + t];
+    }
+    for (int t = threadIdx.x; t < 16; t += blockDim.x) s.b4[t] = t < kBand ? prm[L.b4 + t] : 0.0f;
+    for (int t = threadIdx.x; t < L.Z * kH; t += blockDim.x) {
+        const int k = t / kH, h = t % kH;
+        float acc = prm[L.b1 + h];
+        for (int j = 0; j < kEmb; ++j) acc = fmaf(prm[L.W1e + h * kEmb + j], prm[L.emb + k * kEmb + j], acc);
+        if (fold_v) acc = fmaf(prm[L.W1v + h], v, acc);
+        s.ctab[t] = acc;
+    }
+    __syncthreads();
+}
+
+// Per-lane operands of layers 2-4 and of layer 1, loaded from the staged
+// weights.
+struct MlpRegs {
+    bf16x8 A2[4][2], A3[4][2], A4[2];
+    f32x4 c2[4], c3[4], c4;  // biases in accumulator layout
+    float wu[16], wv[16];
+};
+
+__device__ __forceinline__ bf16x8 a_operand(const __bf16 *row, int c, int g)
+{
+    bf16x8 a;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = row[hid(c, g, i)];
+    return a;
+}
+
+__device__ __forceinline__ void load_regs(MlpRegs &r, const MlpShared &s, int lane)
+{
+    const int g = lane >> 4, m = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            r.A2[t][c] = a_operand(s.W2 + (16 * t + m) * kWStride, c, g);
+            r.A3[t][c] = a_operand(s.W3 + (16 * t + m) * kWStride, c, g);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            r.c2[t][i] = s.b2[16 * t + 4 * g + i];
+            r.c3[t][i] = s.b3[16 * t + 4 * g + i];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) r.A4[c] = a_operand(s.W4 + m * kWStride, c, g);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.c4[i] = s.b4[4 * g + i];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            r.wu[c * 8 + i] = s.wu[hid(c, g, i)];
+            r.wv[c * 8 + i] = s.wv[hid(c, g, i)];
+        }
+}
+
+__device__ __forceinline__ bf16x8 relu_pack(const f32x4 &lo, const f32x4 &hi)
+{
+    bf16x8 b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        b[i] = (__bf16)fmaxf(lo[i], 0.0f);
+        b[i + 4] = (__bf16)fmaxf(hi[i], 0.0f);
+    }
+    return b;
+}
+
+// Logits of the 16 samples of a group.  Every lane of the wavefront takes
+// part; lane (g, n) supplies sample n's inputs (u, v and its level's row of
+// the layer-1 table) and, for g = 0, receives its four logits.  With
+// USE_V the v term is added per sample (training); otherwise it is in ctab.
+template <bool USE_V>
+__device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *crow, float u, float v,
+                                            bf16x8 (&h1)[2], bf16x8 (&h2)[2], bf16x8 (&h3)[2])
+{
+    const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        float z[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            float a = crow[hid(c, g, i)];
+            if (USE_V) a = fmaf(r.wv[c * 8 + i], v, a);
+            z[i] = fmaf(r.wu[c * 8 + i], u, a);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) h1[c][i] = (__bf16)fmaxf(z[i], 0.0f);
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        acc[t] = r.c2[t];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], h1[c], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) h2[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        acc[t] = r.c3[t];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], h2[c], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) h3[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);
+    f32x4 z4 = r.c4;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) z4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A4[c], h3[c], z4, 0, 0, 0);
+    return z4;
+}
+
+// softmax of four logits; also returns log of the normaliser (for the loss).
+__device__ __forceinline__ f32x4 softmax4(const f32x4 &z, float &m, float &lse)
+{
+    m = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
+    f32x4 e;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) e[j] = __expf(z[j] - m);
+    const float s = (e[0] + e[1]) + (e[2] + e[3]);
+    const float inv = 1.0f / s;
+    lse = __logf(s);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) e[j] *= inv;
+    return e;
+}
+
+// Feature maps: u = log10|E| and v = log10(dt omega_a), each mapped from its
+// trained range onto [-1, 1]; u = fmaf(log2 |E|, au, bu).
+struct MlpFeatures {
+    float au, bu;  // u = au log2|E| + bu
+    double av, bv; // v = av log2(dt omega_a) + bv
+};
+
+}  // namespace adk
+
+#include "kernels.hpp"
+
+namespace adk {
+
+// Launch arguments of the surrogate-form step.
+struct SurArgs {
+    StepArgs st;           // analytic step of the fallback cells (ln dt folded)
+    const float *prm;      // FP32 master parameters
+    MlpLayout L;
+    float v;               // step feature (folded into the layer-1 table)
+    float au, bu;          // u = au log2|E| + bu
+    double E_lo, E_hi;     // trained field range; empty when dt is outside its range
+    double E_fast;         // below this |E| the step is the identity on either path
+    unsigned long long *counters;
+};
+
+}  // namespace adk
+
+hipError_t adk_surrogate_launch_1(const adk::SurArgs &, const float *, float *, uint8_t *, int64_t, hipStream_t);
+hipError_t adk_surrogate_launch_2(const adk::SurArgs &, const float *, float *, uint8_t *, int64_t, hipStream_t);
+hipError_t adk_surrogate_launch_3(const adk::SurArgs &, const float *, float *, uint8_t *, int64_t, hipStream_t);

@@ -26,7 +26,7 @@ def L():
 def header_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*([a-z_]+)\s*\(", src, flags=re.M))
+    return set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*([a-z_0-9]+)\s*\(", src, flags=re.M))
 
 
 def test_exports_every_declared_function(L):
@@ -187,3 +187,24 @@ def test_hash_field_is_loguniform():
     u = np.log(E / 10.0) / np.log(500.0)
     assert abs(u.mean() - 0.5) < 0.005 and abs(u.var() - 1 / 12) < 0.002
     assert not np.array_equal(wl.hash_field(100, 4, 0), wl.hash_field(100, 4, 1))
+
+
+def test_mlp_host_validation(L):
+    """Surrogate entry points reject bad arguments before touching a device."""
+    for Z in (1, 36, 64):
+        assert L.adk_mlp_nparams(Z) == 16 * Z + 9796 == wl.mlp_nparams(Z)
+    assert L.adk_mlp_nparams(0) == -1 and L.adk_mlp_nparams(65) == -1
+    h = ctypes.c_void_p()
+    prm = (ctypes.c_float * 10)()
+    assert L.adk_mlp_create(None, prm, None, ctypes.byref(h)) == adkion.ADK_EINVAL
+    assert L.adk_mlp_destroy(None) == adkion.ADK_OK
+    assert L.adk_mlp_get_state(None, None, None, None, None) == adkion.ADK_EINVAL
+    assert L.adk_band_columns(None, None, None, None, 5, None, None) == adkion.ADK_EINVAL
+    assert L.adk_mlp_forward(None, None, None, None, 5, None, None) == adkion.ADK_EINVAL
+    assert L.adk_mlp_loss_grad(None, None, None, None, None, 5, None, None, None) == adkion.ADK_EINVAL
+    assert L.adk_mlp_train(None, None, None, None, None) == adkion.ADK_EINVAL
+    assert L.adk_mlp_save(None, b"/nonexistent") == adkion.ADK_EINVAL
+    assert L.adk_mlp_load(None, b"/nonexistent", ctypes.byref(h)) == adkion.ADK_EINVAL
+    win = adkion._Window(3, 1e-8, adkion.ADK_LAYOUT_COMPACT, adkion.ADK_MIXED)
+    assert L.adk_surrogate_step(None, None, None, 4, 1e-16, None, None, ctypes.byref(win), None,
+                                None) == adkion.ADK_EINVAL
