@@ -225,6 +225,120 @@ def mesh3d_measure(ak, gas36, w, eps, steps, warmup):
     return res
 
 
+MLP_FLOPS_PER_EVAL = 2 * (2 * 64 * 64 + 64 * 4) + 2 * 64  # layers 2-4 on MFMA, layer 1 one FMA per unit
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_measure(ak, orc, gas36, spec36, w, eps, steps, train_iters, nsamples=1_000_000):
+    """Surrogate form on the 3D mesh: train the band-column network on the
+    device (analytic FP64 targets), check its columns on held-out samples
+    against the oracle, time surrogate steps over the mesh like mesh3d, and
+    judge one full-size call against the FP64 oracle (sampled cells) and
+    against the FP64 analytic step on the GPU (all cells)."""
+    import torch
+    from oracle import mlp as omlp
+    from paper_2202_10647_amd import workloads as wl
+    res = {"workload": "laser3d_256x256x512_Z36mavg_w3_surrogate",
+           "network": "3 x 64 ReLU, 16-dim level embedding, band-4 softmax; layers 2-4 BF16 MFMA, FP32 accumulate"}
+    net = ak.Mlp(gas36, wl.mlp_init(36, 2022))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(train_iters, nsamples=nsamples, batch=4096, lr=3e-3, lr_min=1e-5, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    res["training"] = dict(samples=nsamples, iters=train_iters, batch=4096, seconds=train_s,
+                           ms_per_iter=train_s / max(train_iters, 1) * 1e3,
+                           final_loss=float(np.mean(losses[-100:])), first_loss=float(losses[0]))
+    log(f"[surrogate] trained {train_iters} iters on {nsamples} samples in {train_s:.1f} s, "
+        f"loss {losses[0]:.4f} -> {np.mean(losses[-100:]):.5f}")
+    # held-out band columns against the oracle's exact columns
+    E, dt, k = wl.surrogate_samples(20000, 999, 36)
+    exact = omlp.exact_band_columns(orc, spec36, 36, E, dt, k)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (E, dt, k.astype(np.int32))]
+    Q = net.forward(*dev).cpu().numpy().astype(np.float64)
+    err = np.abs(Q - exact).max(axis=0)
+    res["heldout_column_error"] = dict(samples=int(err.size), mean=float(err.mean()),
+                                       p50=float(np.quantile(err, 0.5)), p99=float(np.quantile(err, 0.99)),
+                                       max=float(err.max()))
+    log(f"[surrogate] held-out column error: mean {err.mean():.2e}, p99 {np.quantile(err, 0.99):.2e}, "
+        f"max {err.max():.2e}")
+
+    mesh = wl.mesh_3d()
+    n = mesh.ncells
+    t_first = 200
+    fields = torch.empty((steps, n), dtype=torch.float32, device="cuda")
+    for i in range(steps):
+        fields[i] = mesh.field_torch(t_first + i, "cuda", torch.float32)
+    p = torch.zeros((w + 1, n), dtype=torch.float32, device="cuda")
+    p[0] = 1.0
+    lo = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    for i in range(t_first):  # run the pulse in (untimed), surrogate form throughout
+        ak.surrogate_step(gas36, net, mesh.field_torch(i, "cuda", torch.float32), mesh.dt, p, lo, w=w, eps=eps)
+    ak.surrogate_step(gas36, net, fields[0], mesh.dt, p.clone(), lo.clone(), w=w, eps=eps)  # warm
+    cnt.zero_()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for i in range(steps):
+        evs[i][0].record(stream)
+        ak.surrogate_step(gas36, net, fields[i], mesh.dt, p, lo, w=w, eps=eps, counters=cnt)
+        evs[i][1].record(stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    total = start.elapsed_time(end)
+    avg = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    units = window_units(lo, w, 36) * steps
+    fb, evals = (int(x) for x in cnt.cpu().numpy())
+    tflops = evals / steps * MLP_FLOPS_PER_EVAL / (avg * 1e-3) / 1e12
+    res.update(value=units / (total * 1e-3), unit="cell·level updates/s", ms_per_step=total / steps,
+               kernel_avg_us=avg * 1e3, timed_steps=f"{steps} steps from t={t_first} dt",
+               network_evals_per_step=evals / steps, fallback_cells_per_step=fb / steps,
+               mfma=dict(bound="mfma", achieved=tflops, peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                         frac=tflops / BF16_MFMA_PEAK_TFLOPS, flops_per_eval=MLP_FLOPS_PER_EVAL))
+    log(f"[surrogate] {total / steps * 1e3:.1f} us/step, kernel {avg * 1e3:.1f} us, {res['value']:.3e} "
+        f"cell-level/s, {evals / steps:.3e} network evals/step ({tflops:.1f} TFLOP/s BF16), "
+        f"{fb / steps:.0f} fallback cells/step")
+    del fields
+    # error of one full-size call from a seeded state: oracle on sampled cells,
+    # FP64 analytic GPU step on all cells
+    step = t_first + steps // 2
+    E64 = mesh.field(step)
+    comp, lo0 = wl.random_window_state(n, 36, w, seed=77)
+    E32 = E64.astype(np.float32)
+    P32 = comp.astype(np.float32)
+    Ps, Ls = torch.from_numpy(P32).cuda(), torch.from_numpy(lo0.copy()).cuda()
+    ak.surrogate_step(gas36, net, torch.from_numpy(E32).cuda(), mesh.dt, Ps, Ls, w=w, eps=eps)
+    Pf = torch.from_numpy(P32.astype(np.float64)).cuda()
+    Lf = torch.from_numpy(lo0.copy()).cuda()
+    ak.ionize_step(gas36, torch.from_numpy(E32.astype(np.float64)).cuda(), mesh.dt, Pf, Lf, w=w, eps=eps)
+    dfull = (Ps.to(torch.float64) - Pf).abs().amax(dim=0)
+    active = torch.from_numpy((np.abs(E32) >= 10.0) & (np.abs(E32) <= 5000.0)).cuda()
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(n, 65536, replace=False))
+    idx = torch.from_numpy(sample).cuda()
+    g = Ps[:, idx].cpu().numpy().astype(np.float64)
+    ref, rlo = orc.ionize_step(spec36, E32[sample].astype(np.float64), mesh.dt, P32[:, sample].astype(np.float64),
+                               lo0[sample], w, eps)
+    d_or = np.abs(g - ref).max(axis=0)
+    res["error_vs_fp64"] = dict(
+        oracle_sample=dict(cells=int(sample.size), max_abs=float(d_or.max()), mean_abs=float(d_or.mean()),
+                           p99=float(np.quantile(d_or, 0.99)),
+                           lo_mismatch=int(np.sum(Ls[idx].cpu().numpy() != rlo))),
+        gpu_fp64_all_cells=dict(cells=n, max_abs=float(dfull.max()), mean_abs=float(dfull.mean()),
+                                in_range_cells=int(active.sum()),
+                                max_abs_in_range=float(dfull[active].max()) if bool(active.any()) else 0.0),
+        state="seeded random window states, field of step %d" % step)
+    log(f"[surrogate] one call vs FP64: oracle sample max {d_or.max():.2e} mean {d_or.mean():.2e}; "
+        f"GPU FP64 all cells max {float(dfull.max()):.2e} mean {float(dfull.mean()):.2e}")
+    del Ps, Ls, Pf, Lf, p, lo
+    net.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
     """Mixed gases with uneven windows (1-level host gas, 1 % dopants of 7, 18,
     36 and 54 levels, w in 1..6): one persistent plan launch per step.  Each
@@ -349,6 +463,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--batched-cells", type=int, default=1 << 24)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=40)
+    ap.add_argument("--surrogate-train-iters", type=int, default=24000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the ionization step has no "
@@ -387,11 +504,18 @@ def main():
     torch.cuda.empty_cache()
 
     parity = None if args.no_parity else parity_check(adkion, oracle, gas, spec, mesh, w, eps, 1000, 2024)
-    mesh3d = None
-    if not args.no_mesh3d:
+    mesh3d = surrogate = None
+    if not (args.no_mesh3d and args.no_surrogate):
         g36 = wl.synthetic_gas(36)
         gas36 = adkion.Gas.from_table(g36)
-        mesh3d = mesh3d_measure(adkion, gas36, w, eps, args.mesh3d_steps, 200)
+        if not args.no_mesh3d:
+            mesh3d = mesh3d_measure(adkion, gas36, w, eps, args.mesh3d_steps, 200)
+        if not args.no_surrogate:
+            surrogate = surrogate_measure(adkion, oracle, gas36, oracle.GasSpec(g36.U, g36.l, g36.m), w, eps,
+                                          args.surrogate_steps, args.surrogate_train_iters)
+            if mesh3d:
+                surrogate["speedup_vs_fp64_analytic"] = surrogate["value"] / mesh3d["f64"]["value"]
+                surrogate["speedup_vs_mixed_analytic"] = surrogate["value"] / mesh3d["mixed"]["value"]
         gas36.close()
     batched = None if args.no_batched else batched_measure(adkion, oracle, args.batched_steps, args.batched_cells)
     cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, spec, mesh, w, eps, 1000, 7,
@@ -428,6 +552,7 @@ def main():
         "parity": parity,
         "mesh3d": mesh3d,
         "batched": batched,
+        "surrogate": surrogate,
         "cpu_baseline": cpu,
     }
     gas.close()

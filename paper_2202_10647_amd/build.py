@@ -35,7 +35,9 @@ def _jobs(objdir):
     jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "abi.hip"), "-o", obj], obj))
     for name in ("plan", "mlp", "sur"):
         obj = os.path.join(objdir, f"{name}.o")
-        jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", obj], obj))
+        # matrix-core results in ordinary VGPRs (no accumulator-register copies)
+        extra = ["-mllvm", "-amdgpu-mfma-vgpr-form"] if name != "plan" else []
+        jobs.append((["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", obj], obj))
     for prec in PRECS:
         for cpl in (1, 2, 4):
             obj = os.path.join(objdir, f"plan_{prec}_{cpl}.o")

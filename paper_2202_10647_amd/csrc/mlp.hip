@@ -165,7 +165,8 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(FwdArgs a)
         const int64_t si = a.off + ii;
         const int k = a.K[si];
         bf16x8 h1[2], h2[2], h3[2];
-        const f32x4 z = mlp_logits<true>(r, s.ctab + k * kH, a.U[si], a.V[si], h1, h2, h3);
+        const f32x4 z = mlp_logits<true>(r, s.b2 + opaque_zero(), s.ctab + k * kH, a.U[si], a.V[si], 0, h1,
+                                                   h2, h3);
         if (ok && a.H1) {
             store_h(a.H1, ii, g, h1);
             store_h(a.H2, ii, g, h2);

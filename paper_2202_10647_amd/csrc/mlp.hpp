@@ -62,11 +62,11 @@ struct MlpLayout {
 };
 
 // Weights as staged in LDS by every workgroup that evaluates the network.
-struct MlpShared {
+struct alignas(16) MlpShared {
     __bf16 W2[kH * kWStride];
     __bf16 W3[kH * kWStride];
-    __bf16 W4[16 * kWStride];  // rows 4..15 zero: a full 16-row A tile
-    float b2[kH], b3[kH], b4[16];
+    __bf16 W4[16 * kWStride];  // rows 0..3 used (a lane with A row m reads row m mod 4)
+    float b2[kH], b3[kH], b4[16];  // contiguous with wu and wv (see mlp_logits)
     float wu[kH], wv[kH];
     float ctab[ADK_MAX_Z * kH];  // W1e emb[k] + b1 (+ W1v v when v is fixed)
 };
@@ -108,12 +108,12 @@ __device__ inline void stage_mlp(MlpShared &s, const float *__restrict__ prm, co
     __syncthreads();
 }
 
-// Per-lane operands of layers 2-4 and of layer 1, loaded from the staged
-// weights.
+// Per-lane weight operands of layers 2-4, loaded once from the staged
+// weights and kept in registers (72 VGPRs).  Biases and the layer-1 weights
+// are read from LDS per group (the same few addresses for every sample,
+// so those reads are broadcasts).
 struct MlpRegs {
     bf16x8 A2[4][2], A3[4][2], A4[2];
-    f32x4 c2[4], c3[4], c4;  // biases in accumulator layout
-    float wu[16], wv[16];
 };
 
 __device__ __forceinline__ bf16x8 a_operand(const __bf16 *row, int c, int g)
@@ -134,61 +134,89 @@ __device__ __forceinline__ void load_regs(MlpRegs &r, const MlpShared &s, int la
             r.A2[t][c] = a_operand(s.W2 + (16 * t + m) * kWStride, c, g);
             r.A3[t][c] = a_operand(s.W3 + (16 * t + m) * kWStride, c, g);
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            r.c2[t][i] = s.b2[16 * t + 4 * g + i];
-            r.c3[t][i] = s.b3[16 * t + 4 * g + i];
-        }
     }
 #pragma unroll
-    for (int c = 0; c < 2; ++c) r.A4[c] = a_operand(s.W4 + m * kWStride, c, g);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) r.c4[i] = s.b4[4 * g + i];
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            r.wu[c * 8 + i] = s.wu[hid(c, g, i)];
-            r.wv[c * 8 + i] = s.wv[hid(c, g, i)];
-        }
+    for (int c = 0; c < 2; ++c) r.A4[c] = a_operand(s.W4 + (m & 3) * kWStride, c, g);
+}
+
+// Four consecutive floats of LDS (16-byte aligned) as an accumulator tile.
+__device__ __forceinline__ f32x4 lds4(const float *p) { return *(const f32x4 *)p; }
+
+// A zero the compiler cannot see through (keeps LDS reads in their loop).
+__device__ __forceinline__ int opaque_zero()
+{
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Two floats to a pair of bfloat16 (round to nearest even), one instruction.
+__device__ __forceinline__ unsigned pack2(float a, float b)
+{
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+
+// ReLU on packed bfloat16 values: a bfloat16 read as a 16-bit integer has the
+// sign of the value, so max(., 0) over the integers (v_pk_max_i16) zeroes the
+// negative entries (and -0) and keeps the rest.  Rounding to nearest keeps the
+// sign, so relu(bf16(x)) = bf16(relu(x)).
+__device__ __forceinline__ bf16x8 relu_bf16(u32x4 w)
+{
+    const i16x8 v = __builtin_elementwise_max(__builtin_bit_cast(i16x8, w), (i16x8)0);
+    return __builtin_bit_cast(bf16x8, v);
 }
 
 __device__ __forceinline__ bf16x8 relu_pack(const f32x4 &lo, const f32x4 &hi)
 {
-    bf16x8 b;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        b[i] = (__bf16)fmaxf(lo[i], 0.0f);
-        b[i + 4] = (__bf16)fmaxf(hi[i], 0.0f);
-    }
-    return b;
+    const u32x4 w = {pack2(lo[0], lo[1]), pack2(lo[2], lo[3]), pack2(hi[0], hi[1]), pack2(hi[2], hi[3])};
+    return relu_bf16(w);
 }
 
 // Logits of the 16 samples of a group.  Every lane of the wavefront takes
 // part; lane (g, n) supplies sample n's inputs (u, v and its level's row of
 // the layer-1 table) and, for g = 0, receives its four logits.  With
 // USE_V the v term is added per sample (training); otherwise it is in ctab.
+//
+// sf points at MlpShared::b2 (followed by b3, b4, wu and wv); callers pass it
+// through an opaque per-iteration offset so that these reads stay inside
+// their loop instead of occupying registers for the whole kernel.
+//
+// The output tile has the four logits in rows 4 qo .. 4 qo + 3 (the other
+// rows are zero), so lane (qo, n) receives sample n's logits: lane group qo
+// is chosen by the caller (the lanes that own the samples).
 template <bool USE_V>
-__device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *crow, float u, float v,
-                                            bf16x8 (&h1)[2], bf16x8 (&h2)[2], bf16x8 (&h3)[2])
+__device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *sf, const float *crow, float u, float v,
+                                            int qo, bf16x8 (&h1)[2], bf16x8 (&h2)[2], bf16x8 (&h3)[2])
 {
     const int g = (threadIdx.x & 63) >> 4;
+    const float *b2 = sf, *b3 = sf + kH, *b4 = sf + 2 * kH, *wu = b4 + 16, *wv = wu + kH;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
+        const f32x4 c0 = lds4(crow + hid(c, g, 0)), c1 = lds4(crow + hid(c, g, 4));
+        const f32x4 u0 = lds4(wu + hid(c, g, 0)), u1 = lds4(wu + hid(c, g, 4));
         float z[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            float a = crow[hid(c, g, i)];
-            if (USE_V) a = fmaf(r.wv[c * 8 + i], v, a);
-            z[i] = fmaf(r.wu[c * 8 + i], u, a);
+        for (int i = 0; i < 4; ++i) {
+            float a0 = c0[i], a1 = c1[i];
+            if (USE_V) {
+                a0 = fmaf(wv[hid(c, g, i)], v, a0);
+                a1 = fmaf(wv[hid(c, g, i + 4)], v, a1);
+            }
+            z[i] = fmaf(u0[i], u, a0);
+            z[i + 4] = fmaf(u1[i], u, a1);
         }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) h1[c][i] = (__bf16)fmaxf(z[i], 0.0f);
+        const u32x4 w = {pack2(z[0], z[1]), pack2(z[2], z[3]), pack2(z[4], z[5]), pack2(z[6], z[7])};
+        h1[c] = relu_bf16(w);
     }
     f32x4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        acc[t] = r.c2[t];
+        acc[t] = lds4(b2 + 16 * t + 4 * g);
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], h1[c], acc[t], 0, 0, 0);
     }
@@ -196,15 +224,20 @@ __device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *crow,
     for (int c = 0; c < 2; ++c) h2[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        acc[t] = r.c3[t];
+        acc[t] = lds4(b3 + 16 * t + 4 * g);
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], h2[c], acc[t], 0, 0, 0);
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) h3[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);
-    f32x4 z4 = r.c4;
+    const bool rows_q = ((threadIdx.x & 15) >> 2) == qo;  // this lane supplies A row m = lane & 15
+    const f32x4 b4v = lds4(b4);
+    f32x4 z4 = g == qo ? b4v : (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int c = 0; c < 2; ++c) z4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A4[c], h3[c], z4, 0, 0, 0);
+    for (int c = 0; c < 2; ++c) {
+        const bf16x8 a4 = rows_q ? r.A4[c] : (bf16x8){};
+        z4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a4, h3[c], z4, 0, 0, 0);
+    }
     return z4;
 }
 
@@ -216,7 +249,7 @@ __device__ __forceinline__ f32x4 softmax4(const f32x4 &z, float &m, float &lse)
 #pragma unroll
     for (int j = 0; j < 4; ++j) e[j] = __expf(z[j] - m);
     const float s = (e[0] + e[1]) + (e[2] + e[3]);
-    const float inv = 1.0f / s;
+    const float inv = __builtin_amdgcn_rcpf(s);  // s in [1, 4]
     lse = __logf(s);
 #pragma unroll
     for (int j = 0; j < 4; ++j) e[j] *= inv;

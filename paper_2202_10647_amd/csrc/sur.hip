@@ -14,7 +14,7 @@ namespace adk {
 namespace {
 
 template <int W>
-__global__ __launch_bounds__(kBlock) void surrogate_kernel(SurArgs a, const float *__restrict__ E,
+__global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const float *__restrict__ E,
                                                            float *__restrict__ pops, uint8_t *__restrict__ lo,
                                                            int64_t n)
 {
@@ -28,8 +28,6 @@ __global__ __launch_bounds__(kBlock) void surrogate_kernel(SurArgs a, const floa
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    MlpRegs r;
-    load_regs(r, ms, lane);
     unsigned long long n_fb = 0, n_eval = 0;
 
     // wavefront-uniform loop: every lane stays active for the matrix ops
@@ -71,9 +69,11 @@ __global__ __launch_bounds__(kBlock) void surrogate_kernel(SurArgs a, const floa
         const bool in = EL >= a.E_lo && EL <= a.E_hi;
         const bool use_mlp = act && in;
         const bool use_an = act && !in;
-        double out[W + 1];
+        // float from here on: stored values, and for the network's cells also
+        // the populations it redistributes (its columns are float)
+        float out[W + 1];
 #pragma unroll
-        for (int s = 0; s <= W; ++s) out[s] = N[s];
+        for (int s = 0; s <= W; ++s) out[s] = (float)N[s];
 
         if (__any(use_an)) {
             const Field f = field_terms<RateEval<PolicyMixed>::kLogTerms>(EL, slog);
@@ -83,54 +83,66 @@ __global__ __launch_bounds__(kBlock) void surrogate_kernel(SurArgs a, const floa
             chain_apply<PolicyMixed, W>(x, N, o2);
             if (use_an) {
 #pragma unroll
-                for (int s = 0; s <= W; ++s) out[s] = o2[s];
+                for (int s = 0; s <= W; ++s) out[s] = (float)o2[s];
             }
         }
 
         const int top = act ? (W < Z - p ? W : Z - p) : 0;  // absorbing slot
         if (__any(use_mlp)) {
+            // weight operands reloaded per wavefront pass (not held across
+            // the analytic branch)
+            MlpRegs r;
+            load_regs(r, *(const MlpShared *)((const char *)&ms + opaque_zero()), lane);
             const float u = fmaf(__log2f(fabsf(Ef)), a.au, a.bu);
-            float Qc[W][kBand] = {};
+            // inputs of sample n of group q come from the cell of lane 16 q + n
+            float uq[4];
+            int pq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uq[q] = __shfl(u, 16 * q + (lane & 15));
+                pq[q] = __shfl(p, 16 * q + (lane & 15));
+            }
+            const int g = lane >> 4;
+            // N' = sum over source slots s of column_s x N[s] (float: the
+            // columns themselves are float); destinations past the top slot
+            // are lumped into it, which keeps its own population
+            float acc[W + kBand];
+#pragma unroll
+            for (int j = 0; j < W + kBand; ++j) acc[j] = 0.0f;
 #pragma unroll
             for (int s = 0; s < W; ++s) {
-#pragma unroll
+                float Qs[kBand] = {};
+                // groups of 16 cells with no cell needing source slot s are skipped
+                const unsigned long long need = __ballot(use_mlp && s < top);
+#pragma unroll 1
                 for (int q = 0; q < 4; ++q) {
-                    // sample n of the group is the cell of lane 16 q + n
-                    const int src = 16 * q + (lane & 15);
-                    const float uq = __shfl(u, src);
-                    const int pq = __shfl(p, src);
-                    const int k = pq + s < Z - 1 ? pq + s : Z - 1;
+                    if (((need >> (16 * q)) & 0xFFFFull) == 0) continue;
+                    const float un = q == 0 ? uq[0] : (q == 1 ? uq[1] : (q == 2 ? uq[2] : uq[3]));
+                    const int pn = q == 0 ? pq[0] : (q == 1 ? pq[1] : (q == 2 ? pq[2] : pq[3]));
+                    const int k = pn + s < Z - 1 ? pn + s : Z - 1;
                     bf16x8 h1[2], h2[2], h3[2];
-                    const f32x4 z = mlp_logits<false>(r, ms.ctab + k * kH, uq, 0.0f, h1, h2, h3);
+                    // the logits of the cell of lane 16 q + n land in that lane
+                    const f32x4 z = mlp_logits<false>(r, ms.b2 + opaque_zero(), ms.ctab + k * kH, un, 0.0f, q,
+                                                      h1, h2, h3);
                     float zm, lse;
                     const f32x4 Q = softmax4(z, zm, lse);
-                    // lanes 0..15 hold the columns; the owner lane 16 q + n reads lane n
+                    if (g == q) {
 #pragma unroll
-                    for (int d = 0; d < kBand; ++d) {
-                        const float qv = __shfl(Q[d], lane & 15);
-                        if ((lane >> 4) == q) Qc[s][d] = qv;
+                        for (int d = 0; d < kBand; ++d) Qs[d] = Q[d];
                     }
                 }
+                const float ns = s < top ? out[s] : 0.0f;  // = N[s] on the network's cells
+#pragma unroll
+                for (int d = 0; d < kBand; ++d) acc[s + d] = fmaf(Qs[d], ns, acc[s + d]);
             }
-            // N' = sum over source slots of column x N[s]; destinations past
-            // the top slot are lumped into it, which keeps its own population
-            double acc[W + kBand];
+            float Ntop = 0.0f, tail = 0.0f;
 #pragma unroll
-            for (int j = 0; j < W + kBand; ++j) acc[j] = 0.0;
+            for (int j = 0; j <= W; ++j) Ntop = j == top ? out[j] : Ntop;
 #pragma unroll
-            for (int s = 0; s < W; ++s) {
-                const double ns = s < top ? N[s] : 0.0;
-#pragma unroll
-                for (int d = 0; d < kBand; ++d) acc[s + d] = fma((double)Qc[s][d], ns, acc[s + d]);
-            }
-            double Ntop = 0.0, tail = 0.0;
-#pragma unroll
-            for (int j = 0; j <= W; ++j) Ntop = j == top ? N[j] : Ntop;
-#pragma unroll
-            for (int j = 0; j < W + kBand; ++j) tail += j >= top ? acc[j] : 0.0;
+            for (int j = 0; j < W + kBand; ++j) tail += j >= top ? acc[j] : 0.0f;
             if (use_mlp) {
 #pragma unroll
-                for (int j = 0; j <= W; ++j) out[j] = j < top ? acc[j] : (j == top ? Ntop + tail : 0.0);
+                for (int j = 0; j <= W; ++j) out[j] = j < top ? acc[j] : (j == top ? Ntop + tail : 0.0f);
             }
         }
 
@@ -142,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void surrogate_kernel(SurArgs a, const floa
             const bool finite = EL <= 1.7976931348623157e308 || p >= Z;
 #pragma unroll
             for (int s = 0; s <= W; ++s) {
-                const float v = finite ? (float)out[s] : NAN;
+                const float v = finite ? out[s] : NAN;
                 pops[(int64_t)s * n + c] = (p + s <= Z) ? v : 0.0f;
             }
             lo[c] = (uint8_t)p;
