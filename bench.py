@@ -37,6 +37,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(key):
+    """HBM bytes per launch of the headline kernel from the committed byte-counter
+    summary, or None when the step kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "step_compact_mixed_w3_mesh2d_bytes.txt")
+    csrc = os.path.join(ROOT, "paper_2202_10647_amd", "csrc")
+    try:
+        vals = {}
+        for line in open(path):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for f in ("kernels.hpp", "chain.hpp", "inst.hip"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+        if h.hexdigest() != vals.get("kernel_sources_sha256"):
+            return None
+        return float(vals[key])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def bytes_per_cell(w, prec):
     """Algorithmic HBM bytes per cell per step, compact layout: E read, window
     index read + write, w+1 populations read + written."""
@@ -463,6 +485,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--batched-cells", type=int, default=1 << 24)
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device to device three times (a kernel of known traffic "
+                         "for calibrating profiler byte counters)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=40)
     ap.add_argument("--surrogate-train-iters", type=int, default=24000)
@@ -482,6 +507,16 @@ def main():
         build.build()
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     torch.cuda.set_device(0)
+
+    if args.calibration_copy_mib > 0:
+        nfl = args.calibration_copy_mib * (1 << 20) // 4
+        src = torch.ones(nfl, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[calibration] copied {args.calibration_copy_mib} MiB device to device 3 times")
+        del src, dst
 
     w, eps = args.window, args.eps
     mesh = wl.mesh_2d()
@@ -539,7 +574,11 @@ def main():
                    "eps": eps, "layout": "compact", "precision": "mixed", "dt_s": mesh.dt,
                    "timed_steps": f"steps 0..{K - 1} of the {mesh.steps}-step run", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": m["achieved_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": m["achieved_gbps"] / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": m["achieved_gbps"] / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic("traffic_bytes_per_launch_mixed") if w == 3 else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
+                                     "calibrated on a 512 MiB copy; profiles/step_compact_mixed_w3_mesh2d_bytes.txt)",
+                     "algorithmic_bytes_per_launch": bytes_per_cell(w, "mixed") * n,
                      "kernel": f"step_compact_kernel<PolicyMixed,{w}>",
                      "bytes_per_cell": bytes_per_cell(w, "mixed"), "kernel_avg_us": m["kernel_ms"] * 1e3,
                      "timing": "HIP events around one graph replay of the timed steps / steps"},
