@@ -187,13 +187,13 @@ __device__ __forceinline__ void load_cell(CellLoad<R, W> &d, const R *__restrict
 }
 
 // One cell of a compact-layout step from its loaded data: window shift,
-// rates, exact chain update, store.  Called by all active lanes of a
-// wavefront together (the fast path and the solver use wavefront votes).
+// rates, exact chain update; the new window in o / olo.  Called by all
+// active lanes of a wavefront together (the fast path and the solver use
+// wavefront votes).
 template <class P, int W>
-__device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &cur, const double *sc,
-                                          const double *slog, int Z, bool has_poly, double eps, double E_cut,
-                                          typename P::real *__restrict__ pops, uint8_t *__restrict__ lo, int64_t n,
-                                          int64_t c)
+__device__ __forceinline__ void step_cell_out(const CellLoad<typename P::real, W> &cur, const double *sc,
+                                              const double *slog, int Z, bool has_poly, double eps, double E_cut,
+                                              typename P::real (&o)[W + 1], int &olo)
 {
     using R = typename P::real;
     const double EL = fabs((double)cur.E);
@@ -202,11 +202,8 @@ __device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &c
     // T = I for the whole wavefront: every cell is either fully stripped
     // (window [Z, Z], no rate) or below the field cutoff with no shift due
     if (__all(p >= Z || (EL < E_cut && (double)cur.N[0] >= eps))) {
-        static_for<0, W + 1>([&](auto ss) {
-            constexpr int s = decltype(ss)::value;
-            pops[(int64_t)s * n + c] = cur.N[s];
-        });
-        lo[c] = (uint8_t)p;
+        static_for<0, W + 1>([&](auto ss) { o[decltype(ss)::value] = cur.N[decltype(ss)::value]; });
+        olo = p;
         return;
     }
     double N[W + 1];
@@ -232,11 +229,32 @@ __device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &c
         // slots past level Z hold no population (rounding of the top row);
         // a non-finite field makes the whole window NaN
         const R v = finite ? (R)out[s] : R(NAN);
-        pops[(int64_t)s * n + c] = (p + s <= Z) ? v : R(0);
+        o[s] = (p + s <= Z) ? v : R(0);
     });
-    lo[c] = (uint8_t)p;
+    olo = p;
 }
 
+template <class P, int W>
+__device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &cur, const double *sc,
+                                          const double *slog, int Z, bool has_poly, double eps, double E_cut,
+                                          typename P::real *__restrict__ pops, uint8_t *__restrict__ lo, int64_t n,
+                                          int64_t c)
+{
+    typename P::real o[W + 1];
+    int l;
+    step_cell_out<P, W>(cur, sc, slog, Z, has_poly, eps, E_cut, o, l);
+    static_for<0, W + 1>([&](auto ss) {
+        constexpr int s = decltype(ss)::value;
+        pops[(int64_t)s * n + c] = o[s];
+    });
+    lo[c] = (uint8_t)l;
+}
+
+// A wavefront whose 64 cells all take T = I (fully stripped, or below the
+// field cutoff with no shift due) stores nothing: its windows are unchanged
+// in place.  Grid-stride loop, software pipelined: the loads of a lane's
+// next cell are issued before the current cell is computed, so their
+// latency overlaps the arithmetic.
 template <class P, int W>
 __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const typename P::real *__restrict__ E,
                                                               typename P::real *__restrict__ pops,
@@ -245,15 +263,21 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const 
     using R = typename P::real;
     __shared__ double sc[kDevTableLen];
     const double *slog = sc + kCoefRows * kCoefStride;
-    stage_coefficients(sc, a.tab, a.ln_dt);
+    const int Z = a.Z;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     CellLoad<R, W> nxt;
-    if (c < n) load_cell(nxt, E, pops, lo, n, c);
+    if (c < n) load_cell(nxt, E, pops, lo, n, c);  // in flight while the table is staged
+    stage_coefficients(sc, a.tab, a.ln_dt);
     for (; c < n; c += stride) {
         const CellLoad<R, W> cur = nxt;
         if (c + stride < n) load_cell(nxt, E, pops, lo, n, c + stride);
-        step_cell<P, W>(cur, sc, slog, a.Z, a.has_poly != 0, a.eps, a.E_cut, pops, lo, n, c);
+        const int p = cur.lo < Z ? cur.lo : Z;
+        if (__all(p >= Z || (fabs((double)cur.E) < a.E_cut && (double)cur.N[0] >= a.eps))) {
+            if (p != cur.lo) lo[c] = (uint8_t)p;  // an index past Z is clamped
+            continue;
+        }
+        step_cell<P, W>(cur, sc, slog, Z, a.has_poly != 0, a.eps, a.E_cut, pops, lo, n, c);
     }
 }
 
@@ -365,13 +389,15 @@ StepArgs step_args(const adk_gas *g, double dt, double eps);
 
 // Grid of a grid-stride kernel: every workgroup resident at once (occupancy
 // from the compiled resource usage), no more groups than cells need.
-template <class K>
-int resident_grid(K kernel, int64_t n)
+// (The occupancy is cached per kernel: the template parameter is the kernel
+// itself, so kernels of one signature do not share the cache.)
+template <auto Kernel>
+int resident_grid(int64_t n)
 {
     static int per_cu = 0;
     if (per_cu <= 0) {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, kBlock, 0) != hipSuccess || b <= 0) b = 4;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, Kernel, kBlock, 0) != hipSuccess || b <= 0) b = 4;
         per_cu = b;
     }
     const int64_t need = (n + kBlock - 1) / kBlock;
@@ -386,11 +412,11 @@ hipError_t launch_step(const adk_gas *g, const void *E, int64_t n, double dt, vo
     using R = typename P::real;
     const StepArgs a = step_args(g, dt, win->eps);
     if (win->layout == ADK_LAYOUT_COMPACT) {
-        const int grid = resident_grid(step_compact_kernel<P, W>, n);
+        const int grid = resident_grid<step_compact_kernel<P, W>>(n);
         hipLaunchKernelGGL((step_compact_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E,
                            (R *)pops, lo, n);
     } else {
-        const int grid = resident_grid(step_full_kernel<P, W>, n);
+        const int grid = resident_grid<step_full_kernel<P, W>>(n);
         hipLaunchKernelGGL((step_full_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E,
                            (R *)pops, lo, n);
     }
