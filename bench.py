@@ -176,16 +176,20 @@ def parity_check(ak, orc, gas, spec, mesh, w, eps, step, seed):
         E = E64.astype(npdt)
         P = comp.astype(npdt)
         Pt, Lt = torch.from_numpy(P).cuda(), torch.from_numpy(lo.copy()).cuda()
-        ak.ionize_step(gas, torch.from_numpy(E).cuda(), mesh.dt, Pt, Lt, w=w, eps=eps)
+        dne = torch.empty(n, dtype=tdt, device="cuda")
+        ak.ionize_step(gas, torch.from_numpy(E).cuda(), mesh.dt, Pt, Lt, w=w, eps=eps, dne=dne)
         idx = torch.from_numpy(sample).cuda()
         g = Pt[:, idx].cpu().numpy().astype(np.float64)
         gl = Lt[idx].cpu().numpy()
+        gy = dne[idx].cpu().numpy().astype(np.float64)
         ref, rlo = orc.ionize_step(spec, E[sample].astype(np.float64), mesh.dt, P[:, sample].astype(np.float64),
                                    lo[sample], w, eps)
+        yref = orc.electron_yield(P[:, sample].astype(np.float64), lo[sample], ref, rlo, spec.Z)
         out[prec] = dict(max_abs_err=float(np.max(np.abs(g - ref))), lo_mismatch=int(np.sum(gl != rlo)),
-                         cells=int(sample.size))
+                         cells=int(sample.size), electron_yield_max_abs_err=float(np.max(np.abs(gy - yref))))
         log(f"[parity] {prec}: max |dN| = {out[prec]['max_abs_err']:.2e} over {sample.size} cells, "
-            f"lo mismatches {out[prec]['lo_mismatch']}")
+            f"lo mismatches {out[prec]['lo_mismatch']}, electron yield max err "
+            f"{out[prec]['electron_yield_max_abs_err']:.2e}")
     return out
 
 
@@ -244,6 +248,102 @@ def mesh3d_measure(ak, gas36, w, eps, steps, warmup):
     res["speedup_mixed_vs_f64"] = res["mixed"]["value"] / res["f64"]["value"]
     res["workload"] = "laser3d_256x256x512_Z36mavg_w3"
     res["timed_steps"] = f"{steps} steps from t={t_first} dt"
+    return res
+
+
+def yield_measure(ak, gas36, w, eps, steps):
+    """Cost of the fused electron yield on the 3D mesh (mixed): the same
+    steps with and without the dne output, per-launch HIP events."""
+    import torch
+    from paper_2202_10647_amd import workloads as wl
+    mesh = wl.mesh_3d()
+    n = mesh.ncells
+    t_first = 200
+    fields = torch.empty((steps, n), dtype=torch.float32, device="cuda")
+    for i in range(steps):
+        fields[i] = mesh.field_torch(t_first + i, "cuda", torch.float32)
+    p0 = torch.zeros((w + 1, n), dtype=torch.float32, device="cuda")
+    p0[0] = 1.0
+    l0 = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    for i in range(t_first):
+        ak.ionize_step(gas36, mesh.field_torch(i, "cuda", torch.float32), mesh.dt, p0, l0, w=w, eps=eps)
+    dne = torch.empty(n, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, d in (("without", None), ("with_yield", dne)):
+        p, lo = p0.clone(), l0.clone()
+        ak.ionize_step(gas36, fields[0], mesh.dt, p.clone(), lo.clone(), w=w, eps=eps, dne=d)  # warm
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for i in range(steps):
+            evs[i][0].record(stream)
+            ak.ionize_step(gas36, fields[i], mesh.dt, p, lo, w=w, eps=eps, dne=d)
+            evs[i][1].record(stream)
+        torch.cuda.synchronize()
+        res[name] = float(np.mean([a.elapsed_time(b) for a, b in evs])) * 1e3
+    res["overhead"] = res["with_yield"] / res["without"] - 1.0
+    res["bytes_per_cell"] = {"without": bytes_per_cell(w, "mixed"), "with_yield": bytes_per_cell(w, "mixed") + 4}
+    res["workload"] = "laser3d_256x256x512_Z36mavg_w3_mixed"
+    log(f"[yield] mesh3d mixed: {res['without']:.1f} us/launch without, {res['with_yield']:.1f} us with the "
+        f"fused electron yield ({100 * res['overhead']:+.1f} %)")
+    del fields, p0, l0, dne
+    torch.cuda.empty_cache()
+    return res
+
+
+def subcycle_measure(ak, orc, gas, spec, mesh, w, eps, step, seed, nsubs=(8, 64, 512)):
+    """What the analytic solution avoids: one full-size FP64 step of the 2D
+    mesh from a seeded state, analytic vs sub-cycled explicit RK4 with nsub
+    substeps, timed with HIP events; errors against the oracle's exact step
+    on sampled cells; the share of sampled cells whose RK4 substep exceeds
+    the stability limit (max W dt / nsub > 2.78)."""
+    import torch
+    from paper_2202_10647_amd import workloads as wl
+    n = mesh.ncells
+    E = mesh.field(step)
+    comp, lo = wl.random_window_state(n, spec.Z, w, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    sample = np.sort(rng.choice(n, 65536, replace=False))
+    exact, elo = orc.ionize_step(spec, E[sample], mesh.dt, comp[:, sample], lo[sample], w, eps)
+    Wall = orc.rates(spec, np.abs(E[sample]))
+    from oracle import mlp as omlp
+    _, p = omlp.window_shift(comp[:, sample], lo[sample], spec.Z, eps)
+    xmax = np.zeros(sample.size)
+    for s in range(w):
+        k = p + s
+        ok = k < spec.Z
+        xmax[ok] = np.maximum(xmax[ok], Wall[k[ok], np.nonzero(ok)[0]] * mesh.dt)
+    Et = torch.from_numpy(E).cuda()
+    idx = torch.from_numpy(sample).cuda()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        P, L = torch.from_numpy(comp).cuda(), torch.from_numpy(lo.copy()).cuda()
+        fn(P.clone(), L.clone())  # warm
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn(P, L)
+        b.record(stream)
+        torch.cuda.synchronize()
+        d = np.abs(P[:, idx].cpu().numpy() - exact)
+        fin = np.isfinite(d).all(axis=0)
+        err = float(np.max(d[:, fin])) if fin.any() else None
+        return a.elapsed_time(b) * 1e3, (err, int((~fin).sum()))
+
+    res = {"workload": f"laser2d_1024x1024_Z{spec.Z}_w{w}_f64_one_call_t{step}", "sampled_cells": int(sample.size)}
+    us, (err, nonfin) = timed(lambda P, L: ak.ionize_step(gas, Et, mesh.dt, P, L, w=w, eps=eps))
+    res["analytic"] = {"us": us, "max_abs_err": err, "nonfinite_cells": nonfin}
+    log(f"[subcycle] analytic FP64: {us:.1f} us, max |dN| {err:.1e}")
+    for k in nsubs:
+        us, (err, nonfin) = timed(lambda P, L: ak.subcycle_step(gas, Et, mesh.dt, P, L, w, k, eps=eps))
+        unstable = float(np.mean(xmax / k > 2.78))
+        res[f"rk4_nsub_{k}"] = {"us": us, "max_abs_err_finite_cells": err, "nonfinite_cells": nonfin,
+                                "unstable_cell_fraction": unstable}
+        log(f"[subcycle] RK4 x {k}: {us:.1f} us, max |dN| over finite cells {err}, non-finite {nonfin}, "
+            f"unstable cells {100 * unstable:.2f} %")
+    del Et
+    torch.cuda.empty_cache()
     return res
 
 
@@ -489,6 +589,7 @@ def main():
                     help="first copy this many MiB device to device three times (a kernel of known traffic "
                          "for calibrating profiler byte counters)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-subcycle", action="store_true")
     ap.add_argument("--surrogate-steps", type=int, default=40)
     ap.add_argument("--surrogate-train-iters", type=int, default=24000)
     args = ap.parse_args()
@@ -539,12 +640,14 @@ def main():
     torch.cuda.empty_cache()
 
     parity = None if args.no_parity else parity_check(adkion, oracle, gas, spec, mesh, w, eps, 1000, 2024)
+    subcycle = None if args.no_subcycle else subcycle_measure(adkion, oracle, gas, spec, mesh, w, eps, 1000, 2025)
     mesh3d = surrogate = None
     if not (args.no_mesh3d and args.no_surrogate):
         g36 = wl.synthetic_gas(36)
         gas36 = adkion.Gas.from_table(g36)
         if not args.no_mesh3d:
             mesh3d = mesh3d_measure(adkion, gas36, w, eps, args.mesh3d_steps, 200)
+            mesh3d["electron_yield"] = yield_measure(adkion, gas36, w, eps, args.mesh3d_steps)
         if not args.no_surrogate:
             surrogate = surrogate_measure(adkion, oracle, gas36, oracle.GasSpec(g36.U, g36.l, g36.m), w, eps,
                                           args.surrogate_steps, args.surrogate_train_iters)
@@ -592,6 +695,7 @@ def main():
         "mesh3d": mesh3d,
         "batched": batched,
         "surrogate": surrogate,
+        "subcycled_baseline": subcycle,
         "cpu_baseline": cpu,
     }
     gas.close()

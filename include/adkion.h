@@ -149,6 +149,30 @@ int adk_chain_advance(int32_t w, const void *W, int64_t ncells, double dt, void 
 int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops,
                 uint8_t *lo, const adk_window *win, hipStream_t stream);
 
+/* ionize_step (compact layout) that also writes each cell's electron yield
+ * of the step, the quantity the particle code downstream turns into new
+ * electrons (Sec. 1 and Sec. 4; electron density from the charge-state
+ * populations, Fig. 2(c)): dne[c] = sum_s (lo'+s) N'_s - sum_s (lo+s) N_s,
+ * the change of the mean charge per atom (lo' and N' after the step, lo read
+ * as min(lo, Z)).  dne[ncells] is a device array of the precision's type,
+ * computed in double from the same registers as the populations.  Errors: as
+ * ionize_step, and ADK_EINVAL for a layout other than ADK_LAYOUT_COMPACT or
+ * a null dne with ncells > 0. */
+int ionize_step_yield(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops,
+                      uint8_t *lo, const adk_window *win, void *dne, hipStream_t stream);
+
+/* Comparison baseline, not the method: ionize_step (compact layout, ADK_F64)
+ * with the chain integrated by nsub explicit classical Runge-Kutta substeps
+ * of dt/nsub instead of its analytic solution (rates frozen over the step,
+ * window shift and top as in ionize_step).  Sub-cycled time stepping of
+ * the rate equations is what the exact solution of Sec. 3 replaces (Sec. 1);
+ * this entry point measures that cost and its error on identical inputs.
+ * Arrays as ionize_step (double).  Errors: as ionize_step, and ADK_EINVAL
+ * for nsub < 1, a precision other than ADK_F64 or a layout other than
+ * ADK_LAYOUT_COMPACT. */
+int adk_subcycle_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops, uint8_t *lo,
+                      const adk_window *win, int32_t nsub, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Batched step over cells of several gases with uneven window widths.
  * Cells are independent (Sec. 3), so one launch can serve a mesh whose cells

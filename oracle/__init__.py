@@ -166,3 +166,15 @@ def ionize_step(gas: GasSpec, E, dt, pops, lo, w, eps, layout=0, consts=None):
 
 def max_threads() -> int:
     return int(_load().orc_max_threads())
+
+
+def electron_yield(pops_in, lo_in, pops_out, lo_out, Z):
+    """Electron yield of a step per atom, compact layout: the change of the
+    mean charge sum_k k N_k (the electron density of Fig. 2(c) per atom),
+    sum_s (lo' + s) N'_s - sum_s (lo + s) N_s, with lo read as min(lo, Z)."""
+    Pi = np.asarray(pops_in, np.float64)
+    Po = np.asarray(pops_out, np.float64)
+    li = np.minimum(np.asarray(lo_in, np.int64), Z)
+    lq = np.asarray(lo_out, np.int64)
+    s = np.arange(Pi.shape[0])[:, None]
+    return ((lq[None, :] + s) * Po).sum(axis=0) - ((li[None, :] + s) * Pi).sum(axis=0)

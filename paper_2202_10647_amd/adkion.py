@@ -23,7 +23,8 @@ ADK_MAX_Z, ADK_MAX_W, ADK_M_AVERAGE = 64, 8, -1
 
 #: every function the header declares (checked by the CPU test suite)
 EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "adk_gas_destroy",
-           "adk_gas_levels", "adk_rates", "adk_chain_advance", "ionize_step", "adk_plan_create",
+           "adk_gas_levels", "adk_rates", "adk_chain_advance", "ionize_step", "ionize_step_yield",
+           "adk_subcycle_step", "adk_plan_create",
            "adk_plan_step", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash", "adk_mlp_nparams",
            "adk_mlp_create", "adk_mlp_destroy", "adk_mlp_get_state", "adk_band_columns", "adk_mlp_forward",
            "adk_mlp_loss_grad", "adk_mlp_train", "adk_mlp_save", "adk_mlp_load", "adk_surrogate_step")
@@ -98,6 +99,10 @@ def lib():
     L.adk_chain_advance.argtypes = [i32, vp, i64, dbl, vp, ctypes.c_int, vp]
     L.ionize_step.restype = ctypes.c_int
     L.ionize_step.argtypes = [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp]
+    L.adk_subcycle_step.restype = ctypes.c_int
+    L.adk_subcycle_step.argtypes = [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), i32, vp]
+    L.ionize_step_yield.restype = ctypes.c_int
+    L.ionize_step_yield.argtypes = [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp, vp]
     L.adk_plan_create.restype = ctypes.c_int
     L.adk_plan_create.argtypes = [ctypes.POINTER(vp), i32, vp, vp, i64, ctypes.c_int, dbl, i32,
                                   ctypes.POINTER(vp)]
@@ -258,10 +263,12 @@ def chain_advance(W, dt: float, pops, stream=None):
 
 
 def ionize_step(gas: Gas, E, dt: float, pops, lo, w: int, eps: float = 1e-8, layout: str = "compact",
-                stream=None):
+                stream=None, dne=None):
     """One ionization step, in place on pops and lo (see include/adkion.h).
 
-    float64 tensors select ADK_F64, float32 tensors ADK_MIXED."""
+    float64 tensors select ADK_F64, float32 tensors ADK_MIXED.  With dne (a
+    device tensor of E's dtype and size, compact layout) the step also writes
+    each cell's electron yield (ionize_step_yield)."""
     import torch
     lay = {"compact": ADK_LAYOUT_COMPACT, "full": ADK_LAYOUT_FULL}[layout]
     n = E.numel()
@@ -271,9 +278,32 @@ def ionize_step(gas: Gas, E, dt: float, pops, lo, w: int, eps: float = 1e-8, lay
     if lo.dtype != torch.uint8 or lo.numel() != n:
         raise ValueError("lo must be uint8[ncells]")
     win = _Window(int(w), float(eps), lay, _prec_of(E))
+    if dne is not None:
+        if dne.dtype != E.dtype or dne.numel() != n:
+            raise ValueError("dne must match E in dtype and size")
+        st = lib().ionize_step_yield(gas.handle, _dev(E, "E"), n, float(dt), _dev(pops, "pops"), _dev(lo, "lo"),
+                                     ctypes.byref(win), _dev(dne, "dne"), _stream(stream))
+        _check(st, "ionize_step_yield")
+        return pops, lo
     st = lib().ionize_step(gas.handle, _dev(E, "E"), n, float(dt), _dev(pops, "pops"), _dev(lo, "lo"),
                            ctypes.byref(win), _stream(stream))
     _check(st, "ionize_step")
+    return pops, lo
+
+
+def subcycle_step(gas: Gas, E, dt: float, pops, lo, w: int, nsub: int, eps: float = 1e-8, stream=None):
+    """Comparison baseline: the step with nsub explicit RK4 substeps instead of
+    the analytic chain solution (float64 tensors, compact layout), in place."""
+    import torch
+    n = E.numel()
+    if E.dtype != torch.float64 or pops.dtype != torch.float64 or tuple(pops.shape) != (w + 1, n):
+        raise ValueError(f"E float64[{n}] and pops float64[{w + 1}][{n}] expected")
+    if lo.dtype != torch.uint8 or lo.numel() != n:
+        raise ValueError("lo must be uint8[ncells]")
+    win = _Window(int(w), float(eps), ADK_LAYOUT_COMPACT, ADK_F64)
+    st = lib().adk_subcycle_step(gas.handle, _dev(E, "E"), n, float(dt), _dev(pops, "pops"), _dev(lo, "lo"),
+                                 ctypes.byref(win), int(nsub), _stream(stream))
+    _check(st, "adk_subcycle_step")
     return pops, lo
 
 

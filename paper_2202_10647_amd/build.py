@@ -33,10 +33,10 @@ def _jobs(objdir):
                   "-o", obj], obj))
     obj = os.path.join(objdir, "abi.o")
     jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "abi.hip"), "-o", obj], obj))
-    for name in ("plan", "mlp", "sur"):
+    for name in ("plan", "mlp", "sur", "subcycle"):
         obj = os.path.join(objdir, f"{name}.o")
         # matrix-core results in ordinary VGPRs (no accumulator-register copies)
-        extra = ["-mllvm", "-amdgpu-mfma-vgpr-form"] if name != "plan" else []
+        extra = ["-mllvm", "-amdgpu-mfma-vgpr-form"] if name in ("mlp", "sur") else []
         jobs.append((["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", obj], obj))
     for prec in PRECS:
         for cpl in (1, 2, 4):

@@ -222,7 +222,24 @@ int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, vo
     if (ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
     if (ncells == 0) return ADK_OK;
     const hipError_t e = (win->prec == ADK_F64 ? kStepF64 : kStepMixed)[win->w](gas, E, ncells, dt, pops, lo,
-                                                                               win, stream);
+                                                                               win, nullptr, stream);
+    return status_of(e);
+}
+
+int ionize_step_yield(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops, uint8_t *lo,
+                      const adk_window *win, void *dne, hipStream_t stream)
+{
+    if (!win || win->layout != ADK_LAYOUT_COMPACT) return ADK_EINVAL;
+    if (ncells > 0 && !dne) return ADK_EINVAL;
+    if (!gas || ncells < 0) return ADK_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
+    if (!(win->eps >= 0.0) || !std::isfinite(win->eps)) return ADK_EINVAL;
+    if (!valid_prec(win->prec)) return ADK_EINVAL;
+    if (win->w < 1 || win->w > ADK_MAX_W || win->w > gas->Z) return ADK_ERANGE;
+    if (ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
+    if (ncells == 0) return ADK_OK;
+    const hipError_t e = (win->prec == ADK_F64 ? kStepF64 : kStepMixed)[win->w](gas, E, ncells, dt, pops, lo,
+                                                                               win, dne, stream);
     return status_of(e);
 }
 

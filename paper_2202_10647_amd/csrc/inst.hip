@@ -15,9 +15,9 @@
 #define ADK_NAME(kind) ADK_CAT(ADK_CAT(ADK_CAT(ADK_CAT(adk_, kind), _), ADK_CAT(ADK_INST_PREC, _)), ADK_INST_W)
 
 hipError_t ADK_NAME(step)(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,
-                          const adk_window *win, hipStream_t st)
+                          const adk_window *win, void *dne, hipStream_t st)
 {
-    return adk::launch_step<ADK_POLICY, ADK_INST_W>(g, E, n, dt, pops, lo, win, st);
+    return adk::launch_step<ADK_POLICY, ADK_INST_W>(g, E, n, dt, pops, lo, win, dne, st);
 }
 
 hipError_t ADK_NAME(advance)(const void *Wr, int64_t n, double dt, void *pops, hipStream_t st)

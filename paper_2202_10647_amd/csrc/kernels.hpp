@@ -49,6 +49,11 @@ struct StepArgs {
     double E_cut;        // below this |E| every rate of the gas is < 1e-30 per step
 };
 
+// Host helpers (abi.hip).
+int num_cus();
+int grid_for(int64_t n);
+StepArgs step_args(const adk_gas *g, double dt, double eps);
+
 // log2 of a positive finite double v: v = m 2^k with m in [1/2, 1); the top
 // six fraction bits of m select c_j ~ 1/m from the table, r = m c_j - 1 is
 // formed with one rounding (|r| < 0.0078) and log2(1 + r) is a short series,
@@ -255,10 +260,15 @@ __device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &c
 // in place.  Grid-stride loop, software pipelined: the loads of a lane's
 // next cell are issued before the current cell is computed, so their
 // latency overlaps the arithmetic.
-template <class P, int W>
+//
+// With YIELD the kernel also writes the cell's electron yield of the step,
+// dne[c] = sum_s (lo' + s) N'_s - sum_s (lo + s) N_s: the change of the mean
+// charge (electrons released per atom), from the same registers.
+template <class P, int W, bool YIELD>
 __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const typename P::real *__restrict__ E,
                                                               typename P::real *__restrict__ pops,
-                                                              uint8_t *__restrict__ lo, int64_t n)
+                                                              uint8_t *__restrict__ lo, int64_t n,
+                                                              typename P::real *__restrict__ dne)
 {
     using R = typename P::real;
     __shared__ double sc[kDevTableLen];
@@ -275,9 +285,26 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const 
         const int p = cur.lo < Z ? cur.lo : Z;
         if (__all(p >= Z || (fabs((double)cur.E) < a.E_cut && (double)cur.N[0] >= a.eps))) {
             if (p != cur.lo) lo[c] = (uint8_t)p;  // an index past Z is clamped
+            if (YIELD) dne[c] = R(0);
             continue;
         }
-        step_cell<P, W>(cur, sc, slog, Z, a.has_poly != 0, a.eps, a.E_cut, pops, lo, n, c);
+        R o[W + 1];
+        int l;
+        step_cell_out<P, W>(cur, sc, slog, Z, a.has_poly != 0, a.eps, a.E_cut, o, l);
+        static_for<0, W + 1>([&](auto ss) {
+            constexpr int s = decltype(ss)::value;
+            pops[(int64_t)s * n + c] = o[s];
+        });
+        lo[c] = (uint8_t)l;
+        if (YIELD) {
+            double q0 = 0.0, q1 = 0.0;
+            static_for<0, W + 1>([&](auto ss) {
+                constexpr int s = decltype(ss)::value;
+                q0 = fma((double)(p + s), (double)cur.N[s], q0);
+                q1 = fma((double)(l + s), (double)o[s], q1);
+            });
+            dne[c] = (R)(q1 - q0);
+        }
     }
 }
 
@@ -326,6 +353,84 @@ __global__ __launch_bounds__(kBlock) void step_full_kernel(StepArgs a, const typ
         });
         lo[c] = (uint8_t)p;
     }
+}
+
+// Comparison baseline (not the method): the same step with the chain
+// integrated by nsub explicit classical Runge-Kutta (RK4) substeps of
+// dt / nsub instead of the analytic solution, rates frozen over the step as
+// in the analytic method.  This is the sub-cycled ("fractional") time
+// stepping that the exact solution avoids.  FP64, compact layout.
+template <int W>
+__device__ __forceinline__ void chain_deriv(const double (&x)[W], const double (&y)[W + 1], double (&d)[W + 1])
+{
+    d[0] = -x[0] * y[0];
+    static_for<1, W>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        d[j] = fma(x[j - 1], y[j - 1], -x[j] * y[j]);
+    });
+    d[W] = x[W - 1] * y[W - 1];
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void subcycle_kernel(StepArgs a, const double *__restrict__ E,
+                                                          double *__restrict__ pops, uint8_t *__restrict__ lo,
+                                                          int64_t n, int nsub)
+{
+    __shared__ double sc[kDevTableLen];
+    const double *slog = sc + kCoefRows * kCoefStride;
+    stage_coefficients(sc, a.tab, a.ln_dt);
+    const int Z = a.Z;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const double h = 1.0 / nsub;  // substep in units of dt (x = W dt)
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < n; c += stride) {
+        const double EL = fabs(E[c]);
+        int p = lo[c];
+        p = p < Z ? p : Z;
+        double y[W + 1];
+        static_for<0, W + 1>([&](auto ss) { y[decltype(ss)::value] = pops[(int64_t)decltype(ss)::value * n + c]; });
+        while (p < Z && y[0] < a.eps) {
+            y[0] += y[1];
+            static_for<1, W>([&](auto ss) {
+                constexpr int s = decltype(ss)::value;
+                y[s] = y[s + 1];
+            });
+            y[W] = 0.0;
+            ++p;
+        }
+        const Field f = field_terms<RateEval<PolicyF64>::kLogTerms>(EL, slog);
+        double x[W];
+        window_rates<PolicyF64, W>(sc, p, f, a.has_poly != 0, x);
+        for (int it = 0; it < nsub; ++it) {
+            double k1[W + 1], k2[W + 1], k3[W + 1], k4[W + 1], t[W + 1];
+            chain_deriv<W>(x, y, k1);
+            static_for<0, W + 1>([&](auto jj) { t[decltype(jj)::value] = fma(0.5 * h, k1[decltype(jj)::value], y[decltype(jj)::value]); });
+            chain_deriv<W>(x, t, k2);
+            static_for<0, W + 1>([&](auto jj) { t[decltype(jj)::value] = fma(0.5 * h, k2[decltype(jj)::value], y[decltype(jj)::value]); });
+            chain_deriv<W>(x, t, k3);
+            static_for<0, W + 1>([&](auto jj) { t[decltype(jj)::value] = fma(h, k3[decltype(jj)::value], y[decltype(jj)::value]); });
+            chain_deriv<W>(x, t, k4);
+            static_for<0, W + 1>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                y[j] += (h / 6.0) * (k1[j] + 2.0 * (k2[j] + k3[j]) + k4[j]);
+            });
+        }
+        const bool finite = EL <= 1.7976931348623157e308 || p >= Z;
+        static_for<0, W + 1>([&](auto ss) {
+            constexpr int s = decltype(ss)::value;
+            const double v = finite ? y[s] : NAN;
+            pops[(int64_t)s * n + c] = (p + s <= Z) ? v : 0.0;
+        });
+        lo[c] = (uint8_t)p;
+    }
+}
+
+template <int W>
+hipError_t launch_subcycle(const adk_gas *g, const double *E, int64_t n, double dt, double *pops, uint8_t *lo,
+                           double eps, int nsub, hipStream_t st)
+{
+    const StepArgs a = step_args(g, dt, eps);
+    hipLaunchKernelGGL((subcycle_kernel<W>), dim3(grid_for(n)), dim3(kBlock), 0, st, a, E, pops, lo, n, nsub);
+    return hipGetLastError();
 }
 
 // Chain advance with given rates W[w][n] (1/s), pops[(w+1)][n].
@@ -407,14 +512,20 @@ int resident_grid(int64_t n)
 
 template <class P, int W>
 hipError_t launch_step(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,
-                       const adk_window *win, hipStream_t st)
+                       const adk_window *win, void *dne, hipStream_t st)
 {
     using R = typename P::real;
     const StepArgs a = step_args(g, dt, win->eps);
     if (win->layout == ADK_LAYOUT_COMPACT) {
-        const int grid = resident_grid<step_compact_kernel<P, W>>(n);
-        hipLaunchKernelGGL((step_compact_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E,
-                           (R *)pops, lo, n);
+        if (dne) {
+            const int grid = resident_grid<step_compact_kernel<P, W, true>>(n);
+            hipLaunchKernelGGL((step_compact_kernel<P, W, true>), dim3(grid), dim3(kBlock), 0, st, a,
+                               (const R *)E, (R *)pops, lo, n, (R *)dne);
+        } else {
+            const int grid = resident_grid<step_compact_kernel<P, W, false>>(n);
+            hipLaunchKernelGGL((step_compact_kernel<P, W, false>), dim3(grid), dim3(kBlock), 0, st, a,
+                               (const R *)E, (R *)pops, lo, n, (R *)nullptr);
+        }
     } else {
         const int grid = resident_grid<step_full_kernel<P, W>>(n);
         hipLaunchKernelGGL((step_full_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E,
@@ -433,7 +544,7 @@ hipError_t launch_advance(const void *Wr, int64_t n, double dt, void *pops, hipS
 }
 
 using StepFn = hipError_t (*)(const adk_gas *, const void *, int64_t, double, void *, uint8_t *,
-                              const adk_window *, hipStream_t);
+                              const adk_window *, void *, hipStream_t);
 using AdvanceFn = hipError_t (*)(const void *, int64_t, double, void *, hipStream_t);
 
 }  // namespace adk
@@ -441,7 +552,7 @@ using AdvanceFn = hipError_t (*)(const void *, int64_t, double, void *, hipStrea
 // Non-template entry of each instantiation: adk_step_<prec>_<W>, adk_advance_<prec>_<W>.
 #define ADK_DECLARE_INST(PREC, W)                                                                          \
     hipError_t adk_step_##PREC##_##W(const adk_gas *, const void *, int64_t, double, void *, uint8_t *,    \
-                                     const adk_window *, hipStream_t);                                     \
+                                     const adk_window *, void *, hipStream_t);                             \
     hipError_t adk_advance_##PREC##_##W(const void *, int64_t, double, void *, hipStream_t);
 #define ADK_DECLARE_PREC(PREC)                                                                             \
     ADK_DECLARE_INST(PREC, 1)                                                                              \

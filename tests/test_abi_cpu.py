@@ -208,3 +208,11 @@ def test_mlp_host_validation(L):
     win = adkion._Window(3, 1e-8, adkion.ADK_LAYOUT_COMPACT, adkion.ADK_MIXED)
     assert L.adk_surrogate_step(None, None, None, 4, 1e-16, None, None, ctypes.byref(win), None,
                                 None) == adkion.ADK_EINVAL
+
+
+def test_yield_host_validation(L):
+    win = adkion._Window(3, 1e-8, adkion.ADK_LAYOUT_FULL, adkion.ADK_MIXED)
+    assert L.ionize_step_yield(None, None, 4, 1e-16, None, None, ctypes.byref(win), None, None) == adkion.ADK_EINVAL
+    win = adkion._Window(3, 1e-8, adkion.ADK_LAYOUT_COMPACT, adkion.ADK_MIXED)
+    assert L.ionize_step_yield(None, None, 4, 1e-16, None, None, ctypes.byref(win), None, None) == adkion.ADK_EINVAL
+    assert L.ionize_step_yield(None, None, 0, 1e-16, None, None, None, None, None) == adkion.ADK_EINVAL

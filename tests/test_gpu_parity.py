@@ -417,3 +417,74 @@ def test_stripped_cells_and_nonfinite_field(torch_dev, ak, orc, prec):
                                pops[:, ok].astype(np.float64), lo[ok], 3, 1e-8)
     assert np.array_equal(lo2[ok], rlo)
     compare(out[:, ok], ref, prec, "stripped/nonfinite")
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("Z,w", [(7, 1), (18, 3), (36, 3), (54, 6)])
+def test_electron_yield_matches_oracle(torch_dev, ak, orc, prec, Z, w):
+    """The fused electron yield (ionize_step_yield) against the oracle's yield
+    of its own step from the same inputs; the populations and window indices
+    of the yield variant equal those of ionize_step bit for bit.  Bound:
+    the per-level tolerance times the sum of the window's charges."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, Z)
+    n = 5 * 256 + 91
+    comp, lo = wl.random_window_state(n, Z, w, seed=Z * 7 + w)
+    E = wl.loguniform_field(n, 1.0, 20000.0, seed=Z + 2 * w)
+    E[::23] = 0.0
+    E[5 * 256:] = 0.0  # a trailing block of identity wavefronts: yield 0
+    comp[0, 5 * 256:] = np.maximum(comp[0, 5 * 256:], 0.5)
+    pops = comp.astype(npdt(prec))
+    E = E.astype(npdt(prec))
+    Et = torch.from_numpy(E).cuda()
+    P1, L1 = torch.from_numpy(pops).cuda(), torch.from_numpy(lo).cuda()
+    P2, L2 = P1.clone(), L1.clone()
+    dne = torch.full((n,), 7.0, dtype=Et.dtype, device="cuda")
+    ak.ionize_step(gas, Et, DT, P1, L1, w=w, eps=1e-8, dne=dne)
+    ak.ionize_step(gas, Et, DT, P2, L2, w=w, eps=1e-8)
+    torch.cuda.synchronize()
+    assert torch.equal(P1, P2) and torch.equal(L1, L2)
+    ref, rlo = orc.ionize_step(spec, E.astype(np.float64), DT, pops.astype(np.float64), lo, w, 1e-8)
+    y_ref = orc.electron_yield(pops.astype(np.float64), lo, ref, rlo, Z)
+    y = dne.cpu().numpy().astype(np.float64)
+    bound = TOL[prec] * (w + 1) * (int(lo.max()) + w + 1)
+    assert np.max(np.abs(y - y_ref)) <= bound, (np.max(np.abs(y - y_ref)), bound)
+    assert np.all(y[5 * 256:] == 0.0)
+    # the yield variant is compact-layout only
+    Pf = torch.zeros((Z + 1, n), dtype=Et.dtype, device="cuda")
+    with pytest.raises(ak.AdkError) as e:
+        ak.ionize_step(gas, Et, DT, Pf, L1, w=w, layout="full", dne=dne)
+    assert e.value.status == ak.ADK_EINVAL
+
+
+@pytest.mark.parametrize("Z,w,nsub", [(7, 1, 5), (18, 3, 64), (36, 3, 200), (54, 6, 32)])
+def test_subcycle_baseline_matches_oracle(torch_dev, ak, orc, Z, w, nsub):
+    """The sub-cycled RK4 comparison baseline against its CPU reference on
+    identical inputs (FP64).  Cells whose substep is past RK4's stability
+    limit are compared relative to their (growing) magnitude."""
+    from oracle import subcycle
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, Z)
+    n = 4 * 256 + 45
+    comp, lo = wl.random_window_state(n, Z, w, seed=Z + 31 * w)
+    E = wl.loguniform_field(n, 5.0, 150.0, seed=Z * 3 + w)
+    E[::19] = 0.0
+    Et = torch.from_numpy(E).cuda()
+    Pt, Lt = torch.from_numpy(comp.copy()).cuda(), torch.from_numpy(lo.copy()).cuda()
+    ak.subcycle_step(gas, Et, DT, Pt, Lt, w, nsub, eps=1e-8)
+    torch.cuda.synchronize()
+    got, glo = Pt.cpu().numpy(), Lt.cpu().numpy()
+    ref, rlo, x = subcycle.subcycle_step(orc, spec, E, DT, comp, lo, w, 1e-8, nsub)
+    assert np.array_equal(glo, rlo)
+    stable = x.max(axis=0) / nsub < 2.0
+    assert stable.mean() > 0.5
+    assert np.max(np.abs(got - ref)[:, stable]) <= 1e-12
+    # past the stability limit both sides grow without bound (and may
+    # overflow): compare relative to magnitude where the reference is finite
+    # and far from overflow
+    u = ~stable
+    ok = np.isfinite(ref[:, u]) & (np.abs(ref[:, u]) < 1e250)
+    rel = np.abs(got[:, u] - ref[:, u]) / np.maximum(np.abs(ref[:, u]), 1.0)
+    assert np.max(rel[ok], initial=0.0) <= 1e-9
+    with pytest.raises(ak.AdkError):
+        ak.subcycle_step(gas, Et, DT, Pt, Lt, w, 0)

@@ -166,3 +166,41 @@ def test_reduced_window_tracks_full_chain(orc):
     assert worst[3] < 2e-2
     assert worst[4] < 1e-4
     assert worst[2] > 10 * worst[3]
+
+
+def test_electron_yield_closed_forms(orc):
+    """Electron yield of a step: one level from the neutral state gives
+    1 - exp(-W dt) (Eq. (6)); a shift without field moves the folded residual
+    up one charge; in general the yield equals sum_k k (N'_k - N_k) over the
+    full chain (full layout, Sec. 3)."""
+    Z = 7
+    t = wl.synthetic_gas(Z)
+    spec = orc.GasSpec(t.U, t.l, t.m)
+    dt = 1.3e-16
+    E = wl.loguniform_field(500, 10.0, 2000.0, seed=3)
+    N = np.zeros((2, E.size))
+    N[0] = 1.0
+    lo = np.zeros(E.size, np.uint8)
+    out, lo2 = orc.ionize_step(spec, E, dt, N, lo, 1, 0.0)
+    x = orc.rates(spec, E, 0, 1)[0] * dt
+    y = orc.electron_yield(N, lo, out, lo2, Z)
+    assert np.allclose(y, -np.expm1(-x), rtol=1e-13, atol=1e-300)
+    # shift only: N_lo = 3e-9 < eps at zero field
+    N = np.array([[3e-9], [0.4], [0.6 - 3e-9], [0.0]])
+    lo = np.array([2], np.uint8)
+    out, lo2 = orc.ionize_step(spec, np.zeros(1), dt, N, lo, 3, 1e-8)
+    assert lo2[0] == 3
+    assert abs(orc.electron_yield(N, lo, out, lo2, Z)[0] - 3e-9) < 2e-15  # rounding of sums near 3
+    # random windows: compact yield = full-chain charge change
+    w = 3
+    comp, lo = wl.random_window_state(2000, Z, w, seed=11)
+    E = wl.loguniform_field(2000, 10.0, 3000.0, seed=12)
+    full = np.zeros((Z + 1, 2000))
+    for s in range(w + 1):
+        ok = lo.astype(int) + s <= Z
+        full[lo[ok].astype(int) + s, np.nonzero(ok)[0]] = comp[s, ok]
+    outc, loc = orc.ionize_step(spec, E, dt, comp, lo, w, 1e-8)
+    outf, _ = orc.ionize_step(spec, E, dt, full, lo, w, 1e-8, layout=1)
+    k = np.arange(Z + 1)[:, None]
+    yf = (k * outf).sum(axis=0) - (k * full).sum(axis=0)
+    assert np.max(np.abs(orc.electron_yield(comp, lo, outc, loc, Z) - yf)) < 1e-13
