@@ -1,0 +1,48 @@
+"""Full-vs-reduced window study on the GPU (the synthetic stand-in for the
+paper's Fig. 2b/2c comparison of the 4-level system with the full system):
+the wide window that bench.py's study uses as its reference tracks the
+oracle's full chain along a pulse trajectory, and the reduced windows order
+as the paper reports (3 levels clearly worse than 4)."""
+import numpy as np
+import pytest
+
+from paper_2202_10647_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_wide_window_tracks_full_chain_and_reduced_windows_order(orc):
+    import torch
+    from paper_2202_10647_amd import adkion as ak
+    Z = 18
+    g = wl.synthetic_gas(Z)
+    gas = ak.Gas.from_table(g)
+    spec = orc.GasSpec(g.U, g.l, g.m)
+    mesh = wl.mesh_2d()
+    idx = np.array([512 * 1024 + 300, 540 * 1024 + 300])
+    steps = 1200
+    pf, lf = wl.neutral_state(idx.size, Z + 1)
+    runs = {(8, 1e-12): None, (4, 1e-8): None, (3, 1e-8): None, (2, 1e-8): None}
+    for key in runs:
+        w = key[0]
+        P = torch.zeros((w + 1, idx.size), dtype=torch.float64, device="cuda")
+        P[0] = 1.0
+        runs[key] = (P, torch.zeros(idx.size, dtype=torch.uint8, device="cuda"))
+    worst = {key: 0.0 for key in runs}
+    for step in range(steps):
+        E = mesh.field_at(step, idx)
+        pf, lf = orc.ionize_step(spec, E, mesh.dt, pf, lf, w=Z, eps=0.0, layout=1)
+        Et = torch.from_numpy(E).cuda()
+        for (w, eps), (P, L) in runs.items():
+            ak.ionize_step(gas, Et, mesh.dt, P, L, w=w, eps=eps)
+            p, l = P.cpu().numpy(), L.cpu().numpy()
+            for c in range(idx.size):
+                full = np.zeros(Z + 1)
+                k = np.arange(l[c], min(l[c] + w, Z) + 1)
+                full[k] = p[k - l[c], c]
+                worst[(w, eps)] = max(worst[(w, eps)], np.max(np.abs(full - pf[:, c])))
+    assert lf.max() == 0 and runs[(3, 1e-8)][1].min() >= 8  # the pulse ionized past level 8
+    assert worst[(8, 1e-12)] < 1e-10, worst
+    assert worst[(4, 1e-8)] < 1e-4, worst
+    assert worst[(2, 1e-8)] > 10 * worst[(3, 1e-8)] > 10 * worst[(4, 1e-8)], worst
+    gas.close()
