@@ -347,17 +347,26 @@ int adk_mlp_train(adk_mlp *mlp, const adk_gas *gas, const adk_train_cfg *cfg, fl
 int adk_mlp_save(const adk_mlp *mlp, const char *path);
 int adk_mlp_load(const adk_gas *gas, const char *path, adk_mlp **out);
 
+/* Rate below which a source level's column is the identity in the
+ * surrogate step: W_k dt < ADK_SURROGATE_NEGLIGIBLE on the rising branch of
+ * Eq. (1) keeps the level's population to within that fraction. */
+#define ADK_SURROGATE_NEGLIGIBLE 1e-9
+
 /* One ionization step in surrogate form (compact layout, float populations):
  * the window shift at the start of the step is that of ionize_step; then a
  * cell whose |E| lies in the trained field range (and dt in the trained step
- * range) advances with the network's band columns, one per source level of
- * its window, destinations past the window top lumped into the top; every
- * other cell takes the analytic step of ionize_step (ADK_MIXED).  win->prec
+ * range) advances with band columns, one per source level of its window,
+ * destinations past the window top lumped into the top: the network's
+ * column, or the identity column for a source level whose rate at this
+ * field is negligible (W_k dt < ADK_SURROGATE_NEGLIGIBLE, judged by a
+ * per-level field threshold computed on the host once per dt); every other
+ * cell takes the analytic step of ionize_step (ADK_MIXED).  win->prec
  * must be ADK_MIXED, win->layout ADK_LAYOUT_COMPACT, 1 <= win->w <= 3.
  * counters (device, 2 x uint64, may be NULL) are incremented by: [0] cells
  * with a window below the top level that fell back to the analytic step with
  * |E| at or above the gas's field cutoff (below it the step is the identity
- * either way), [1] (cell, source level) pairs evaluated by the network.
+ * either way), [1] (cell, source level) pairs evaluated by the network
+ * (negligible sources excluded).
  * Allocates nothing and never synchronises.  Errors: ADK_EINVAL (null
  * arguments with ncells > 0, dt <= 0 or non-finite, eps < 0, prec or layout
  * other than above, network and gas of different Z), ADK_ERANGE (w outside

@@ -212,11 +212,18 @@ def window_shift(N, lo, Z, eps):
     return N, p
 
 
+#: a source level whose rate gives W dt below this keeps its population
+#: (identity column) in the surrogate form of the step
+NEGLIGIBLE_XDT = 1e-9
+
+
 def surrogate_step(orc, spec, Z, params, rng: Range, E, dt, pops, lo, w, eps, bf16_ops=True):
     """Reference of the surrogate form of the step: cells whose |E| lies in
-    the trained range (and a step dt in range) take the network's band
-    columns after the window shift; all other cells take the exact step of
-    the analytic oracle `orc.ionize_step`."""
+    the trained range (and a step dt in range) take band columns after the
+    window shift, the network's for source levels with W dt >= NEGLIGIBLE_XDT
+    and the identity column for the others; all other cells take the exact
+    step of the analytic oracle `orc.ionize_step`.  Also returns the window
+    rates times dt, x[w][n] (0 past level Z-1)."""
     E = np.abs(np.asarray(E, np.float64))
     ana, alo = orc.ionize_step(spec, E, dt, np.asarray(pops, np.float64), np.asarray(lo, np.uint8), w, eps)
     dt_ok = rng.dt_lo <= dt <= rng.dt_hi
@@ -224,14 +231,20 @@ def surrogate_step(orc, spec, Z, params, rng: Range, E, dt, pops, lo, w, eps, bf
     N, p = window_shift(pops, lo, Z, eps)
     use &= p < Z
     u, v = rng.features(np.where(use, E, rng.E_lo), dt)
+    Wall = orc.rates(spec, np.where(np.isfinite(E), E, 0.0))
+    x = np.zeros((w, E.size))
     cols = []
     for s in range(w):
-        ks = np.minimum(p + s, Z - 1)
-        Q, _ = forward(params, Z, u, v, ks, bf16_ops)
-        cols.append(Q.T)
+        k = p + s
+        ok = k < Z
+        x[s, ok] = Wall[k[ok], np.nonzero(ok)[0]] * dt
+        Q, _ = forward(params, Z, u, v, np.minimum(k, Z - 1), bf16_ops)
+        Q = Q.T
+        Q[:, x[s] < NEGLIGIBLE_XDT] = np.array([1.0, 0.0, 0.0, 0.0])[:, None]
+        cols.append(Q)
     band = band_update(N, p, w, Z, cols, use)
     out = np.where(use[None, :], band, ana)
-    return out, np.where(use, p, alo).astype(np.uint8), use
+    return out, np.where(use, p, alo).astype(np.uint8), use, x
 
 
 def exact_band_columns(orc, spec, Z, E, dt, k):

@@ -130,6 +130,37 @@ double field_cutoff(const adk_gas &g, double dt)
     return cut * g.consts.E_a * (1.0 - 1e-9);
 }
 
+void level_thresholds(const adk_gas &g, double dt, double theta, float *thr)
+{
+    const double target = std::log(theta);
+    const double ln2 = std::log(2.0), log2e = 1.0 / ln2;
+    for (int k = 0; k < g.Z; ++k) {
+        const double *r = g.h_coef + 8 * k;
+        const double a2 = (r[0] + std::log(dt)) * log2e, al = r[1], b2 = r[2] * log2e;
+        auto lnx = [&](double lu) {
+            const double u = std::exp(lu);
+            const double poly = 1.0 + u * (r[3] + u * (r[4] + u * r[5]));
+            return (a2 + al * lu * log2e - b2 / u) * ln2 + std::log(poly);
+        };
+        const double lu_star = al < 0.0 ? std::log(b2 * ln2 / -al) : std::log(1e8);
+        double lo = std::log(1e-30), hi = lu_star;
+        if (!(lnx(hi) > target)) {  // below theta at every field
+            thr[k] = INFINITY;
+            continue;
+        }
+        if (lnx(lo) > target) {
+            thr[k] = 0.0f;
+            continue;
+        }
+        for (int it = 0; it < 200 && hi - lo > 1e-12; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            (lnx(mid) > target ? hi : lo) = mid;
+        }
+        // rounded down: every field below thr[k] is below the crossing
+        thr[k] = std::nextafter((float)(std::exp(lo) * g.consts.E_a * (1.0 - 1e-9)), 0.0f);
+    }
+}
+
 }  // namespace adk
 
 extern "C" int adk_gas_coeffs(const adk_gas_desc *desc, const adk_constants *consts, double *coef_out)

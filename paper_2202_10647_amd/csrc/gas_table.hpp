@@ -18,6 +18,9 @@ struct adk_gas {
     std::mutex cut_mu;
     double cut_dt = -1.0;
     double cut_E = 0.0;
+    // per-level negligible-rate fields of the last step used by the surrogate
+    double thr_dt = -1.0;
+    float thr_E[ADK_MAX_Z] = {};
 };
 
 namespace adk {
@@ -27,5 +30,8 @@ int validate_desc(const adk_gas_desc *d, const adk_constants *consts);
 void build_coeffs(const adk_gas_desc &d, const adk_constants &c, double *coef);
 // |E| (GV/m) below which W dt < 1e-30 for every level of the gas.
 double field_cutoff(const adk_gas &g, double dt);
+// Per level k, the field (GV/m) below which W_k dt < theta on the rising
+// branch of Eq. (1) (+inf if W_k dt < theta at every field, 0 if nowhere).
+void level_thresholds(const adk_gas &g, double dt, double theta, float *thr);
 
 }  // namespace adk

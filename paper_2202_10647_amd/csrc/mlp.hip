@@ -21,6 +21,7 @@ namespace adk {
 namespace {
 
 constexpr int kCh = 32;       // samples per backward workgroup
+constexpr double kNegligibleXdt = ADK_SURROGATE_NEGLIGIBLE;
 constexpr int kPS = kH + 1;   // padded LDS row stride of the backward pass
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 
@@ -151,7 +152,8 @@ __device__ __forceinline__ void store_h(__bf16 *H, int64_t row, int g, const bf1
 __global__ __launch_bounds__(kBlock) void fwd_kernel(FwdArgs a)
 {
     __shared__ MlpShared s;
-    stage_mlp(s, a.prm, a.L, 0.0f, false);
+    __shared__ float ctab[ADK_MAX_Z * kH];
+    stage_mlp(s, ctab, a.prm, a.L, 0.0f, false);
     const int lane = threadIdx.x & 63, g = lane >> 4, nn = lane & 15;
     MlpRegs r;
     load_regs(r, s, lane);
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(FwdArgs a)
         const int64_t si = a.off + ii;
         const int k = a.K[si];
         bf16x8 h1[2], h2[2], h3[2];
-        const f32x4 z = mlp_logits<true>(r, s.b2 + opaque_zero(), s.ctab + k * kH, a.U[si], a.V[si], 0, h1,
+        const f32x4 z = mlp_logits<true>(r, s.b2 + opaque_zero(), ctab + k * kH, a.U[si], a.V[si], 0, h1,
                                                    h2, h3);
         if (ok && a.H1) {
             store_h(a.H1, ii, g, h1);
@@ -948,6 +950,15 @@ int adk_surrogate_step(const adk_gas *gas, const adk_mlp *m, const void *E, int6
     a.E_hi = dt_ok ? m->range.E_hi : -INFINITY;
     a.E_fast = dt_ok ? std::fmin(a.st.E_cut, m->range.E_lo) : a.st.E_cut;
     a.counters = counters;
+    {
+        adk_gas *g = const_cast<adk_gas *>(gas);
+        std::lock_guard<std::mutex> lock(g->cut_mu);
+        if (g->thr_dt != dt) {
+            level_thresholds(*g, dt, kNegligibleXdt, g->thr_E);
+            g->thr_dt = dt;
+        }
+        for (int k = 0; k < ADK_MAX_Z; ++k) a.thr[k] = k < gas->Z ? g->thr_E[k] : 0.0f;
+    }
     hipError_t e;
     switch (win->w) {
     case 1: e = adk_surrogate_launch_1(a, (const float *)E, (float *)pops, lo, ncells, stream); break;

@@ -61,14 +61,14 @@ struct MlpLayout {
     }
 };
 
-// Weights as staged in LDS by every workgroup that evaluates the network.
+// Weights as staged in LDS by every workgroup that evaluates the network
+// (the per-level layer-1 table, Z x 64 floats, is staged beside it).
 struct alignas(16) MlpShared {
     __bf16 W2[kH * kWStride];
     __bf16 W3[kH * kWStride];
-    __bf16 W4[16 * kWStride];  // rows 0..3 used (a lane with A row m reads row m mod 4)
+    __bf16 W4[kBand * kWStride];   // a lane with A row m reads row m mod 4
     float b2[kH], b3[kH], b4[16];  // contiguous with wu and wv (see mlp_logits)
     float wu[kH], wv[kH];
-    float ctab[ADK_MAX_Z * kH];  // W1e emb[k] + b1 (+ W1v v when v is fixed)
 };
 
 // Hidden unit carried by element i of K chunk c in lane group g.
@@ -77,19 +77,19 @@ __host__ __device__ constexpr int hid(int c, int g, int i)
     return 32 * c + (i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4));
 }
 
-// Stage the bf16 weights, the biases and the per-level layer-1 table; v is
-// folded into the table when fold_v (inference at one step size).
-__device__ inline void stage_mlp(MlpShared &s, const float *__restrict__ prm, const MlpLayout &L, float v,
-                                 bool fold_v)
+// Stage the bf16 weights, the biases and the per-level layer-1 table ctab
+// (W1e emb[k] + b1, plus W1v v when fold_v: inference at one step size).
+__device__ inline void stage_mlp(MlpShared &s, float *ctab, const float *__restrict__ prm, const MlpLayout &L,
+                                 float v, bool fold_v)
 {
     for (int t = threadIdx.x; t < kH * kH; t += blockDim.x) {
         const int o = t / kH, i = t % kH;
         s.W2[o * kWStride + i] = (__bf16)prm[L.W2 + t];
         s.W3[o * kWStride + i] = (__bf16)prm[L.W3 + t];
     }
-    for (int t = threadIdx.x; t < 16 * kH; t += blockDim.x) {
+    for (int t = threadIdx.x; t < kBand * kH; t += blockDim.x) {
         const int o = t / kH, i = t % kH;
-        s.W4[o * kWStride + i] = o < kBand ? (__bf16)prm[L.W4 + t] : (__bf16)0.0f;
+        s.W4[o * kWStride + i] = (__bf16)prm[L.W4 + t];
     }
     for (int t = threadIdx.x; t < kH; t += blockDim.x) {
         s.b2[t] = prm[L.b2 + t];
@@ -103,7 +103,7 @@ __device__ inline void stage_mlp(MlpShared &s, const float *__restrict__ prm, co
         float acc = prm[L.b1 + h];
         for (int j = 0; j < kEmb; ++j) acc = fmaf(prm[L.W1e + h * kEmb + j], prm[L.emb + k * kEmb + j], acc);
         if (fold_v) acc = fmaf(prm[L.W1v + h], v, acc);
-        s.ctab[t] = acc;
+        ctab[t] = acc;
     }
     __syncthreads();
 }
@@ -279,6 +279,7 @@ struct SurArgs {
     double E_lo, E_hi;     // trained field range; empty when dt is outside its range
     double E_fast;         // below this |E| the step is the identity on either path
     unsigned long long *counters;
+    float thr[ADK_MAX_Z];  // source level k is negligible (identity column) for |E| < thr[k]
 };
 
 }  // namespace adk

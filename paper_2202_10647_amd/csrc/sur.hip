@@ -2,32 +2,59 @@
 //
 // A wavefront takes 64 cells.  The window shift at the start of the step is
 // that of the analytic step.  Cells whose |E| lies in the network's trained
-// range then advance with predicted band columns: for each source slot s of
-// the window the wavefront evaluates the network on 4 groups of 16 cells (the
-// matrix-core tile), and the owner lane of each cell collects its columns by
-// lane shuffles.  Cells outside the range take the analytic chain solution
-// (mixed precision); a wavefront runs each branch only if one of its lanes
-// needs it.
+// range then advance with predicted band columns, one per source level of
+// the window: the (cell, source) pairs whose rate is not negligible are
+// packed into a list in LDS, evaluated 16 at a time (the matrix-core tile),
+// and each cell reads its columns back.  Cells outside the range take the
+// analytic chain solution (mixed precision); a wavefront runs each branch
+// only if one of its lanes needs it.
 #include "mlp.hpp"
 
 namespace adk {
 namespace {
 
+// Visibility of this wavefront's LDS writes to its own later reads (a
+// wavefront's LDS operations execute in order; the fences keep the compiler
+// from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Dynamic LDS: the layer-1 table ctab[Z][64], then per wavefront the list of
+// (cell, source) pairs that need the network (u and level k, 64 W entries)
+// and their columns (64 W float4).
+template <int W>
+constexpr size_t sur_dyn_bytes(int Z)
+{
+    return (size_t)Z * kH * sizeof(float) + (size_t)(kBlock / 64) * 64 * W * (sizeof(float2) + sizeof(f32x4));
+}
+
 template <int W>
 __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const float *__restrict__ E,
-                                                           float *__restrict__ pops, uint8_t *__restrict__ lo,
-                                                           int64_t n)
+                                                              float *__restrict__ pops, uint8_t *__restrict__ lo,
+                                                              int64_t n)
 {
     __shared__ double sc[kDevTableLen];
     __shared__ MlpShared ms;
-    stage_coefficients(sc, a.st.tab, a.st.ln_dt);
-    stage_mlp(ms, a.prm, a.L, a.v, true);
-    const double *slog = sc + kCoefRows * kCoefStride;
+    __shared__ float sthr[ADK_MAX_Z];
+    extern __shared__ __align__(16) unsigned char dyn[];
     const int Z = a.st.Z;
-    const bool has_poly = a.st.has_poly != 0;
     const int lane = threadIdx.x & 63;
+    float *ctab = (float *)dyn;
+    float2 *cand = (float2 *)(dyn + (size_t)Z * kH * sizeof(float)) + (threadIdx.x >> 6) * 64 * W;
+    f32x4 *res = (f32x4 *)(dyn + (size_t)Z * kH * sizeof(float) + (size_t)(kBlock / 64) * 64 * W * sizeof(float2)) +
+                 (threadIdx.x >> 6) * 64 * W;
+    for (int t = threadIdx.x; t < Z; t += blockDim.x) sthr[t] = a.thr[t];
+    stage_coefficients(sc, a.st.tab, a.st.ln_dt);
+    stage_mlp(ms, ctab, a.prm, a.L, a.v, true);
+    const double *slog = sc + kCoefRows * kCoefStride;
+    const bool has_poly = a.st.has_poly != 0;
     const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    const unsigned long long below = (1ull << lane) - 1ull;  // lanes under this one
     unsigned long long n_fb = 0, n_eval = 0;
 
     // wavefront-uniform loop: every lane stays active for the matrix ops
@@ -36,23 +63,19 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
         const bool valid = c < n;
         float Ef = 0.0f;
         float Nf[W + 1];
-        int p = Z;
+        int lo0 = Z;
 #pragma unroll
         for (int s = 0; s <= W; ++s) Nf[s] = 0.0f;
         if (valid) {
             Ef = E[c];
 #pragma unroll
             for (int s = 0; s <= W; ++s) Nf[s] = pops[(int64_t)s * n + c];
-            p = lo[c];
-            p = p < Z ? p : Z;
+            lo0 = lo[c];
         }
+        int p = lo0 < Z ? lo0 : Z;
         const double EL = fabs((double)Ef);
         if (__all(p >= Z || (EL < a.E_fast && (double)Nf[0] >= a.st.eps))) {
-            if (valid) {
-#pragma unroll
-                for (int s = 0; s <= W; ++s) pops[(int64_t)s * n + c] = Nf[s];
-                lo[c] = (uint8_t)p;
-            }
+            if (valid && p != lo0) lo[c] = (uint8_t)p;  // windows unchanged in place
             continue;
         }
         double N[W + 1];
@@ -89,51 +112,57 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
 
         const int top = act ? (W < Z - p ? W : Z - p) : 0;  // absorbing slot
         if (__any(use_mlp)) {
-            // weight operands reloaded per wavefront pass (not held across
-            // the analytic branch)
-            MlpRegs r;
-            load_regs(r, *(const MlpShared *)((const char *)&ms + opaque_zero()), lane);
+            // the (cell, source) pairs that need the network, packed densely:
+            // a source level whose rate is negligible at this field (W dt <
+            // 1e-9, |E| below its threshold) keeps its population (identity
+            // column) without an evaluation
             const float u = fmaf(__log2f(fabsf(Ef)), a.au, a.bu);
-            // inputs of sample n of group q come from the cell of lane 16 q + n
-            float uq[4];
-            int pq[4];
+            int cnt = 0;
+            int pos[W];
+            bool need[W];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uq[q] = __shfl(u, 16 * q + (lane & 15));
-                pq[q] = __shfl(p, 16 * q + (lane & 15));
+            for (int s = 0; s < W; ++s) {
+                const int k = p + s;
+                need[s] = use_mlp && s < top && !(EL < (double)sthr[k < Z ? k : Z - 1]);
+                const unsigned long long m = __ballot(need[s]);
+                pos[s] = cnt + __popcll(m & below);
+                if (need[s]) cand[pos[s]] = make_float2(u, __int_as_float(k));
+                cnt += __popcll(m);
             }
-            const int g = lane >> 4;
-            // N' = sum over source slots s of column_s x N[s] (float: the
-            // columns themselves are float); destinations past the top slot
-            // are lumped into it, which keeps its own population
+            wave_lds_sync();
+            if (cnt > 0) {
+                // weight operands loaded per wavefront pass (not held across
+                // the analytic branch)
+                MlpRegs r;
+                load_regs(r, *(const MlpShared *)((const char *)&ms + opaque_zero()), lane);
+                for (int g0 = 0; g0 < cnt; g0 += 16) {
+                    const int t = g0 + (lane & 15);
+                    const bool ok = t < cnt;
+                    const float2 cu = cand[ok ? t : 0];
+                    const int k = __float_as_int(cu.y);
+                    bf16x8 h1[2], h2[2], h3[2];
+                    // sample n of the group is candidate g0 + n; its logits land in lane n
+                    const f32x4 z = mlp_logits<false>(r, ms.b2 + opaque_zero(), ctab + k * kH, cu.x, 0.0f, 0, h1,
+                                                      h2, h3);
+                    float zm, lse;
+                    const f32x4 Q = softmax4(z, zm, lse);
+                    if (lane < 16 && ok) res[t] = Q;
+                }
+                wave_lds_sync();
+            }
+            n_eval += (unsigned long long)cnt;
+            // N' = sum over source slots s of column_s x N[s] (float);
+            // destinations past the top slot are lumped into it, which keeps
+            // its own population
             float acc[W + kBand];
 #pragma unroll
             for (int j = 0; j < W + kBand; ++j) acc[j] = 0.0f;
 #pragma unroll
             for (int s = 0; s < W; ++s) {
-                float Qs[kBand] = {};
-                // groups of 16 cells with no cell needing source slot s are skipped
-                const unsigned long long need = __ballot(use_mlp && s < top);
-#pragma unroll 1
-                for (int q = 0; q < 4; ++q) {
-                    if (((need >> (16 * q)) & 0xFFFFull) == 0) continue;
-                    const float un = q == 0 ? uq[0] : (q == 1 ? uq[1] : (q == 2 ? uq[2] : uq[3]));
-                    const int pn = q == 0 ? pq[0] : (q == 1 ? pq[1] : (q == 2 ? pq[2] : pq[3]));
-                    const int k = pn + s < Z - 1 ? pn + s : Z - 1;
-                    bf16x8 h1[2], h2[2], h3[2];
-                    // the logits of the cell of lane 16 q + n land in that lane
-                    const f32x4 z = mlp_logits<false>(r, ms.b2 + opaque_zero(), ms.ctab + k * kH, un, 0.0f, q,
-                                                      h1, h2, h3);
-                    float zm, lse;
-                    const f32x4 Q = softmax4(z, zm, lse);
-                    if (g == q) {
-#pragma unroll
-                        for (int d = 0; d < kBand; ++d) Qs[d] = Q[d];
-                    }
-                }
+                const f32x4 Q = need[s] ? res[pos[s]] : (f32x4){1.0f, 0.0f, 0.0f, 0.0f};
                 const float ns = s < top ? out[s] : 0.0f;  // = N[s] on the network's cells
 #pragma unroll
-                for (int d = 0; d < kBand; ++d) acc[s + d] = fmaf(Qs[d], ns, acc[s + d]);
+                for (int d = 0; d < kBand; ++d) acc[s + d] = fmaf(Q[d], ns, acc[s + d]);
             }
             float Ntop = 0.0f, tail = 0.0f;
 #pragma unroll
@@ -147,8 +176,6 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
         }
 
         n_fb += (unsigned long long)__popcll(__ballot(use_an && EL >= a.st.E_cut));
-#pragma unroll
-        for (int s = 0; s < W; ++s) n_eval += (unsigned long long)__popcll(__ballot(use_mlp && s < top));
 
         if (valid) {
             const bool finite = EL <= 1.7976931348623157e308 || p >= Z;
@@ -169,17 +196,14 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
 template <int W>
 hipError_t launch(const SurArgs &a, const float *E, float *pops, uint8_t *lo, int64_t n, hipStream_t st)
 {
-    static int per_cu = 0;
-    if (per_cu <= 0) {
-        int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, surrogate_kernel<W>, kBlock, 0) != hipSuccess || b <= 0)
-            b = 2;
-        per_cu = b;
-    }
+    const size_t dyn = sur_dyn_bytes<W>(a.st.Z);
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, surrogate_kernel<W>, kBlock, dyn) != hipSuccess || b <= 0)
+        b = 2;
     const int64_t need = (n + kBlock - 1) / kBlock;
-    const int64_t cap = (int64_t)num_cus() * per_cu;
+    const int64_t cap = (int64_t)num_cus() * b;
     const int grid = (int)(need < cap ? need : cap);
-    hipLaunchKernelGGL(surrogate_kernel<W>, dim3(grid), dim3(kBlock), 0, st, a, E, pops, lo, n);
+    hipLaunchKernelGGL(surrogate_kernel<W>, dim3(grid), dim3(kBlock), dyn, st, a, E, pops, lo, n);
     return hipGetLastError();
 }
 

@@ -205,13 +205,22 @@ def test_surrogate_step_matches_reference(env, orc, w):
     cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
     ak.surrogate_step(gas, net, torch.from_numpy(E).cuda(), DT, Pt, Lt, w=w, eps=eps, counters=cnt)
     got, glo = Pt.cpu().numpy().astype(np.float64), Lt.cpu().numpy()
-    ref, rlo, use = mlp.surrogate_step(orc, spec, Z, params.astype(np.float64), RNG, E.astype(np.float64), DT,
-                                       N.astype(np.float64), lo, w, eps)
+    ref, rlo, use, x = mlp.surrogate_step(orc, spec, Z, params.astype(np.float64), RNG, E.astype(np.float64), DT,
+                                          N.astype(np.float64), lo, w, eps)
     assert np.array_equal(glo, rlo)
     ana = ~use
     assert np.max(np.abs(got[:, ana] - ref[:, ana])) <= 1e-6
-    d = np.abs(got[:, use] - ref[:, use]).max(axis=0)
+    # a source whose W dt lies within a factor 3 of the negligible threshold
+    # may be judged either way by the two sides' rate evaluations
+    th = mlp.NEGLIGIBLE_XDT
+    clear = ~np.any((x > th / 3) & (x < 3 * th), axis=0)
+    sel = use & clear
+    assert sel.sum() > 0.9 * use.sum()
+    d = np.abs(got[:, sel] - ref[:, sel]).max(axis=0)
     assert np.quantile(d, 0.9) <= 1e-5 and d.max() <= 1e-2, np.quantile(d, [0.5, 0.9, 0.99, 1.0])
+    # negligible sources keep their population exactly (identity columns)
+    negl = sel & np.all((x < th) | (np.arange(w)[:, None] >= np.minimum(w, Z - rlo.astype(int))[None, :]), axis=0)
+    assert np.max(np.abs(got[:, negl] - ref[:, negl]), initial=0.0) <= 1e-6
     # conservation and non-negativity of the network columns
     assert np.allclose(got[:, use].sum(axis=0), N[:, use].astype(np.float64).sum(axis=0), atol=3e-6)
     assert np.all(got[:, use] >= 0)
@@ -220,7 +229,9 @@ def test_surrogate_step_matches_reference(env, orc, w):
     E64 = E.astype(np.float64)
     fb = (~use) & (p_shift < Z) & (E64 > 5000.0)
     assert c[0] == fb.sum()
-    assert c[1] == np.minimum(w, Z - p_shift[use]).sum()
+    top = np.minimum(w, Z - p_shift)
+    needed = (np.arange(w)[:, None] < top[None, :]) & (x >= th)
+    assert abs(int(c[1]) - int(needed[:, use].sum())) <= int((~clear & use).sum()) * w
     net.close()
 
 
