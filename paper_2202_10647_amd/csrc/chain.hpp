@@ -103,7 +103,7 @@ struct PolicyF64 {
 struct PolicyMixed {
     using real = float;
     static constexpr double kDeltaPhi = 0.5;
-    static constexpr int kPhiDegree = 8;           // 0.5^9/10! < 1e-9
+    static constexpr int kPhiDegree = 7;           // 0.5^8/9! ~ 1.1e-8, below float rounding
     static constexpr double kDelta3 = 1.0;
     static constexpr double kTaylorRelTol = 1e-9;
     static constexpr double kSkipProduct = 1e-12;

@@ -135,7 +135,8 @@ struct RateEval<PolicyMixed> {
         // relative error stays a few float ulps whatever the size of t.
         const double t = fmax(fmin(rate_exponent2(row, f), 45.0), -160.0);
         const double ti = rint(t);
-        float x = ldexpf(exp2f((float)(t - ti)), (int)ti);
+        // |t - ti| <= 1/2: the hardware exp2 (no range reduction needed)
+        float x = ldexpf(__builtin_amdgcn_exp2f((float)(t - ti)), (int)ti);
         if (has_poly) x *= (float)mavg_poly(row, f);
         return fminf(x, kXMax<float>);
     }
