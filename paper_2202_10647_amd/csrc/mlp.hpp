@@ -241,6 +241,71 @@ __device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *sf, c
     return z4;
 }
 
+// Two independent groups A and B through the same weights, interleaved
+// stage by stage so that each stage has twice the independent matrix-core
+// and vector work in flight (inference, v folded into the table).
+__device__ __forceinline__ void mlp_logits_x2(const MlpRegs &r, const float *sf, const float *crowA, float uA,
+                                              const float *crowB, float uB, int qo, f32x4 &zA, f32x4 &zB)
+{
+    const int g = (threadIdx.x & 63) >> 4;
+    const float *b2 = sf, *b3 = sf + kH, *b4 = sf + 2 * kH, *wu = b4 + 16;
+    bf16x8 hA[2], hB[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const f32x4 w0 = lds4(wu + hid(c, g, 0)), w1 = lds4(wu + hid(c, g, 4));
+        const f32x4 a0 = lds4(crowA + hid(c, g, 0)), a1 = lds4(crowA + hid(c, g, 4));
+        const f32x4 c0 = lds4(crowB + hid(c, g, 0)), c1 = lds4(crowB + hid(c, g, 4));
+        const u32x4 wa = {pack2(fmaf(w0[0], uA, a0[0]), fmaf(w0[1], uA, a0[1])),
+                          pack2(fmaf(w0[2], uA, a0[2]), fmaf(w0[3], uA, a0[3])),
+                          pack2(fmaf(w1[0], uA, a1[0]), fmaf(w1[1], uA, a1[1])),
+                          pack2(fmaf(w1[2], uA, a1[2]), fmaf(w1[3], uA, a1[3]))};
+        const u32x4 wb = {pack2(fmaf(w0[0], uB, c0[0]), fmaf(w0[1], uB, c0[1])),
+                          pack2(fmaf(w0[2], uB, c0[2]), fmaf(w0[3], uB, c0[3])),
+                          pack2(fmaf(w1[0], uB, c1[0]), fmaf(w1[1], uB, c1[1])),
+                          pack2(fmaf(w1[2], uB, c1[2]), fmaf(w1[3], uB, c1[3]))};
+        hA[c] = relu_bf16(wa);
+        hB[c] = relu_bf16(wb);
+    }
+    f32x4 accA[4], accB[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        accA[t] = accB[t] = lds4(b2 + 16 * t + 4 * g);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            accA[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], hA[c], accA[t], 0, 0, 0);
+            accB[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], hB[c], accB[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        hA[c] = relu_pack(accA[2 * c], accA[2 * c + 1]);
+        hB[c] = relu_pack(accB[2 * c], accB[2 * c + 1]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        accA[t] = accB[t] = lds4(b3 + 16 * t + 4 * g);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            accA[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], hA[c], accA[t], 0, 0, 0);
+            accB[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], hB[c], accB[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        hA[c] = relu_pack(accA[2 * c], accA[2 * c + 1]);
+        hB[c] = relu_pack(accB[2 * c], accB[2 * c + 1]);
+    }
+    const bool rows_q = ((threadIdx.x & 15) >> 2) == qo;
+    const f32x4 b4v = lds4(b4);
+    zA = zB = g == qo ? b4v : (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const bf16x8 a4 = rows_q ? r.A4[c] : (bf16x8){};
+        zA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a4, hA[c], zA, 0, 0, 0);
+        zB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a4, hB[c], zB, 0, 0, 0);
+    }
+}
+
 // softmax of four logits; also returns log of the normaliser (for the loss).
 __device__ __forceinline__ f32x4 softmax4(const f32x4 &z, float &m, float &lse)
 {

@@ -135,13 +135,31 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
                 // the analytic branch)
                 MlpRegs r;
                 load_regs(r, *(const MlpShared *)((const char *)&ms + opaque_zero()), lane);
-                for (int g0 = 0; g0 < cnt; g0 += 16) {
+                // two groups of 16 at a time (independent work interleaved),
+                // then a last single group when the count leaves one
+                int g0 = 0;
+                for (; g0 + 16 < cnt; g0 += 32) {
+                    const int ta = g0 + (lane & 15), tb = ta + 16;
+                    const bool okb = tb < cnt;
+                    const float2 ca = cand[ta], cb = cand[okb ? tb : 0];
+                    f32x4 za, zb;
+                    // sample n of a group is candidate g0 + n (g0 + 16 + n); its logits land in lane n
+                    mlp_logits_x2(r, ms.b2 + opaque_zero(), ctab + __float_as_int(ca.y) * kH, ca.x,
+                                  ctab + __float_as_int(cb.y) * kH, cb.x, 0, za, zb);
+                    float zm, lse;
+                    const f32x4 Qa = softmax4(za, zm, lse);
+                    const f32x4 Qb = softmax4(zb, zm, lse);
+                    if (lane < 16) {
+                        res[ta] = Qa;
+                        if (okb) res[tb] = Qb;
+                    }
+                }
+                if (g0 < cnt) {
                     const int t = g0 + (lane & 15);
                     const bool ok = t < cnt;
                     const float2 cu = cand[ok ? t : 0];
                     const int k = __float_as_int(cu.y);
                     bf16x8 h1[2], h2[2], h3[2];
-                    // sample n of the group is candidate g0 + n; its logits land in lane n
                     const f32x4 z = mlp_logits<false>(r, ms.b2 + opaque_zero(), ctab + k * kH, cu.x, 0.0f, 0, h1,
                                                       h2, h3);
                     float zm, lse;
