@@ -262,7 +262,9 @@ int adk_field_hash(void *E, int64_t n, uint64_t seed, int64_t step, double E_lo,
 #define ADK_MLP_EMB 16
 #define ADK_MLP_BAND 4
 
-typedef struct adk_mlp adk_mlp; /* opaque: FP32 master weights, Adam moments, training buffers */
+typedef struct adk_mlp adk_mlp; /* opaque: FP32 master weights, Adam moments, training buffers.
+                                  * Calls on one network use its scratch buffers: order them (one
+                                  * stream, or synchronise between streams). */
 
 typedef struct {
     double E_lo, E_hi;   /* trained field range, GV/m (0 < E_lo < E_hi)        */

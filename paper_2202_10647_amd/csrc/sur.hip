@@ -215,9 +215,13 @@ template <int W>
 hipError_t launch(const SurArgs &a, const float *E, float *pops, uint8_t *lo, int64_t n, hipStream_t st)
 {
     const size_t dyn = sur_dyn_bytes<W>(a.st.Z);
-    int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, surrogate_kernel<W>, kBlock, dyn) != hipSuccess || b <= 0)
-        b = 2;
+    static int per_cu[ADK_MAX_Z + 1] = {};  // occupancy per level count (LDS grows with Z)
+    int b = per_cu[a.st.Z];
+    if (b <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, surrogate_kernel<W>, kBlock, dyn) != hipSuccess || b <= 0)
+            b = 2;
+        per_cu[a.st.Z] = b;
+    }
     const int64_t need = (n + kBlock - 1) / kBlock;
     const int64_t cap = (int64_t)num_cus() * b;
     const int grid = (int)(need < cap ? need : cap);
