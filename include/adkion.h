@@ -181,18 +181,29 @@ int adk_subcycle_step(const adk_gas *gas, const void *E, int64_t ncells, double 
  */
 #define ADK_PLAN_MAX_GAS 8
 #define ADK_PLAN_MAX_W 6
+/* A window width with at least this many cells gets a launch of its own,
+ * compiled for that width; runs of smaller widths share one launch compiled
+ * for the widest of them. */
+#define ADK_PLAN_SOLO_CELLS (1 << 19)
 
 typedef struct adk_plan adk_plan; /* opaque: grouping of the cells, tiles, tuning */
 
 typedef struct {
-    int32_t ngas;            /* gases of the plan                                   */
-    int32_t nbuckets;        /* non-empty (gas, w) groups                           */
-    int32_t ntiles;          /* tiles of cells_per_lane * 256 cells of one group    */
-    int32_t cells_per_lane;  /* 1, 2 or 4 (autotuned, cached, or fixed by caller)   */
-    int32_t grid;            /* workgroups of the persistent launch                 */
-    int32_t rows;            /* population rows of the plan layout: max w + 1       */
-    int32_t from_cache;      /* 1 when cells_per_lane came from ADK_TUNE_CACHE      */
-    double tuned_us;         /* best trial launch time of the autotuner (0 if none) */
+    int32_t ngas;            /* gases of the plan                                     */
+    int32_t nbuckets;        /* non-empty (gas, w) groups                             */
+    int32_t ntiles;          /* tiles of cells_per_lane * 256 cells of one group      */
+    int32_t cells_per_lane;  /* of the launch with the most cells (1, 2 or 4)         */
+    int32_t grid;            /* workgroups of the launch with the most cells (= tiles) */
+    int32_t rows;            /* population rows of the plan layout: max w + 1         */
+    int32_t from_cache;      /* 1 when every tuned launch's choice came from the cache */
+    double tuned_us;         /* sum of the best trial times of the tuned launches     */
+    int32_t nlaunches;       /* kernel launches per step (launch groups)              */
+    /* per launch, in launch order (widest windows first): */
+    int32_t launch_wmax[ADK_PLAN_MAX_W];   /* widest window it serves              */
+    int32_t launch_cpl[ADK_PLAN_MAX_W];    /* cells per lane (1, 2 or 4)            */
+    int32_t launch_grid[ADK_PLAN_MAX_W];   /* workgroups (one per tile)             */
+    int32_t launch_tiles[ADK_PLAN_MAX_W];  /* tiles                                 */
+    int64_t launch_cells[ADK_PLAN_MAX_W];  /* cells                                 */
 } adk_plan_info;
 
 /* Create a plan over ncells cells: cell c uses gases[cell_gas[c]] with window
@@ -200,18 +211,21 @@ typedef struct {
  * ngas handles, which must outlive the plan), cell_gas and cell_w are host
  * arrays read during the call.  Populations use the compact layout with
  * info.rows rows: pops[rows][ncells], slot s of cell c = level lo[c] + s for
- * s <= cell_w[c] (other rows are not touched).  cells_per_lane = 0 runs the
- * autotuner (timed trials on scratch device buffers of the plan's size;
- * result cached in the file named by ADK_TUNE_CACHE when set), 1, 2 or 4 fixes
- * it.  Synchronous; allocates device memory.  Errors: ADK_EINVAL (null
- * pointers, bad prec, eps < 0 or non-finite, cells_per_lane not in
- * {0,1,2,4}), ADK_ERANGE (ngas outside [1, ADK_PLAN_MAX_GAS], a cell's gas
- * index or width out of range, ncells >= 2^31 - 256), ADK_EDEVICE/ADK_ENOMEM. */
+ * s <= cell_w[c] (other rows are not touched).  The widths are split into
+ * launch groups (ADK_PLAN_SOLO_CELLS).  cells_per_lane = 0 runs the
+ * autotuner for each launch group (timed trials on scratch device buffers of
+ * the plan's size; result cached in the file named by ADK_TUNE_CACHE when
+ * set), 1, 2 or 4 fixes it for every launch.  Synchronous; allocates device
+ * memory.  Errors: ADK_EINVAL (null pointers, bad prec, eps < 0 or
+ * non-finite, cells_per_lane not in {0,1,2,4}), ADK_ERANGE (ngas outside
+ * [1, ADK_PLAN_MAX_GAS], a cell's gas index or width out of range,
+ * ncells >= 2^31 - 256), ADK_EDEVICE/ADK_ENOMEM. */
 int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *cell_gas, const uint8_t *cell_w,
                     int64_t ncells, adk_prec prec, double eps, int32_t cells_per_lane, adk_plan **out);
 
 /* One ionization step of every cell of the plan (same semantics per cell as
- * ionize_step with the cell's gas and width): one persistent launch on stream.
+ * ionize_step with the cell's gas and width): one launch per launch group
+ * (one workgroup per tile), in order, on stream.
  * E[ncells], pops[rows][ncells], lo[ncells] are device arrays of the plan's
  * precision.  Allocates nothing and never synchronises, so it may be captured
  * into a hipGraph; consecutive launches of one plan must be ordered (one

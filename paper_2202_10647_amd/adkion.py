@@ -46,10 +46,16 @@ class _GasDesc(ctypes.Structure):
                 ("l", ctypes.POINTER(ctypes.c_int8)), ("m", ctypes.POINTER(ctypes.c_int8))]
 
 
+PLAN_MAX_W = 6
+
+
 class _PlanInfo(ctypes.Structure):
     _fields_ = [("ngas", ctypes.c_int32), ("nbuckets", ctypes.c_int32), ("ntiles", ctypes.c_int32),
                 ("cells_per_lane", ctypes.c_int32), ("grid", ctypes.c_int32), ("rows", ctypes.c_int32),
-                ("from_cache", ctypes.c_int32), ("tuned_us", ctypes.c_double)]
+                ("from_cache", ctypes.c_int32), ("tuned_us", ctypes.c_double), ("nlaunches", ctypes.c_int32),
+                ("launch_wmax", ctypes.c_int32 * PLAN_MAX_W), ("launch_cpl", ctypes.c_int32 * PLAN_MAX_W),
+                ("launch_grid", ctypes.c_int32 * PLAN_MAX_W), ("launch_tiles", ctypes.c_int32 * PLAN_MAX_W),
+                ("launch_cells", ctypes.c_int64 * PLAN_MAX_W)]
 
 
 class _MlpRange(ctypes.Structure):
@@ -334,7 +340,11 @@ class Plan:
     def get_info(self) -> dict:
         inf = _PlanInfo()
         _check(lib().adk_plan_get_info(self._h, ctypes.byref(inf)), "adk_plan_get_info")
-        return {k: getattr(inf, k) for k, _ in _PlanInfo._fields_}
+        out = {}
+        for k, _ in _PlanInfo._fields_:
+            v = getattr(inf, k)
+            out[k] = list(v)[: inf.nlaunches] if k.startswith("launch_") else v
+        return out
 
     def step(self, E, dt: float, pops, lo, stream=None):
         import torch

@@ -20,6 +20,7 @@ HIP_FLAGS = [
 ]
 PRECS = ("f64", "mixed")
 WIDTHS = range(1, 9)
+PLAN_WMAX = range(1, 7)
 
 
 def _jobs(objdir):
@@ -39,9 +40,9 @@ def _jobs(objdir):
         extra = ["-mllvm", "-amdgpu-mfma-vgpr-form"] if name in ("mlp", "sur") else []
         jobs.append((["hipcc", *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, f"{name}.hip"), "-o", obj], obj))
     for prec in PRECS:
-        for cpl in (1, 2, 4):
-            obj = os.path.join(objdir, f"plan_{prec}_{cpl}.o")
-            jobs.append((["hipcc", *HIP_FLAGS, f"-DADK_PLAN_PREC={prec}", f"-DADK_PLAN_CPL={cpl}", "-c",
+        for wmax in PLAN_WMAX:
+            obj = os.path.join(objdir, f"plan_{prec}_{wmax}.o")
+            jobs.append((["hipcc", *HIP_FLAGS, f"-DADK_PLAN_PREC={prec}", f"-DADK_PLAN_WMAX={wmax}", "-c",
                           os.path.join(CSRC, "plan_inst.hip"), "-o", obj], obj))
     for prec in PRECS:
         for w in WIDTHS:
@@ -57,7 +58,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(objdir, exist_ok=True)
     work = _jobs(objdir)
     # largest instantiations first so the pool stays busy
-    work.sort(key=lambda j: (0 if "plan_" in j[1] else 1, -int(j[1].rsplit("_", 1)[-1][:-2]) if "inst_" in j[1] else 0))
+    work.sort(key=lambda j: (0 if "plan_" in j[1] else 1, -int(j[1].rsplit("_", 1)[-1][:-2])
+                             if ("inst_" in j[1] or "plan_" in j[1]) else 0))
     njobs = jobs or max(1, min(16, os.cpu_count() or 1))
     with ThreadPoolExecutor(njobs) as ex:
         list(ex.map(lambda j: _run(j[0], verbose), work))

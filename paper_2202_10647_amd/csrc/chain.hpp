@@ -27,12 +27,11 @@
 // No formula divides by a small rate difference, so equal, zero and
 // crossing rates need no special case.
 //
-// Scaling (ranges of 3+ points): synthetic gases reach x ~ 1e10 per step,
-// where products of rates and divided differences leave the float range.
-// The sorted table stores ghat[a..b] = g[a..b] prod_{k=a+1..b} m_k with
-// m_k = max(1, s_k); its recurrence is ghat[a..b] = (ghat[a..b-1] m_b -
-// ghat[a+1..b] m_{a+1}) / (s_b - s_a), and the rate product enters as
-// prod (x_k / m_k) <= 1 times a ratio of m's <= 1.
+// Windows of up to three rates run in the policy's type (float for the mixed
+// policy, with its three-point series in double).  Wider windows tabulate in
+// double for either policy: products of up to eight capped rates (x <= 1e15)
+// and the divided differences stay inside the double range, so nothing is
+// rescaled, and the Newton recurrence can run down to small spreads.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -83,10 +82,15 @@ struct PolicyF64 {
     using real = double;
     static constexpr double kDeltaPhi = 0.1;       // 2-point: series below, difference above
     static constexpr int kPhiDegree = 10;          // 0.1^11/12! < 1e-19
-    static constexpr double kDelta3 = 0.5;         // Taylor below this spread (ranges of <= 4 points;
-                                                   // longer ranges: TableDelta)
+    static constexpr double kDelta3 = 0.5;         // Taylor below this spread (three points, windows
+                                                   // of up to three rates)
     static constexpr double kTaylorRelTol = 1e-17;
     static constexpr double kSkipProduct = 1e-18;  // rate products below this: entry is 0
+    // windows of four or more rates (double tables): Newton below this
+    // spread for a table of L points (index L), series tolerance.  Rounding
+    // of the recurrence grows ~ L! / delta^(L-2); these keep it near 1e-13.
+    static constexpr double kGenDelta[9] = {0.0, 0.0, 0.1, 0.5, 0.5, 1.0, 1.0, 1.5, 1.5};
+    static constexpr double kGenTaylorTol = 1e-17;
     __device__ static __forceinline__ double expneg(double x) { return exp(-x); }
     // a / b from the hardware reciprocal estimate refined by Newton steps
     // (no IEEE division sequence; ~1 ulp)
@@ -107,18 +111,16 @@ struct PolicyMixed {
     static constexpr double kDelta3 = 1.0;
     static constexpr double kTaylorRelTol = 1e-9;
     static constexpr double kSkipProduct = 1e-12;
+    // double tables for windows of four or more rates, rounding of the
+    // recurrence kept near 1e-9 (float results)
+    static constexpr double kGenDelta[9] = {0.0, 0.0, 1e-3, 0.01, 0.01, 0.03, 0.1, 0.25, 0.5};
+    static constexpr double kGenTaylorTol = 1e-9;
     __device__ static __forceinline__ float expneg(float x) { return __expf(-x); }
     __device__ static __forceinline__ float quot(float a, float b)
     {
         return a * __builtin_amdgcn_rcpf(b);
     }
 };
-
-template <class R>
-__device__ __forceinline__ R scale_of(R s)
-{
-    return s > R(1) ? s : R(1);
-}
 
 // phi(d) = sum_{k=0}^{K} (-d)^k / (k+1)!  (Horner)
 template <int K, class R>
@@ -194,113 +196,97 @@ __device__ __forceinline__ void sort_points(R (&s)[L], R (&e)[L])
 
 // Taylor branch for sorted points s[A..B] (B > A), in double, summed
 // until the terms are below the tolerance relative to the sum in every
-// active lane: returns ghat[A..B] = g[A..B] * prod_{k=A+1..B} m_k.
-template <class P, int A, int B, class R, int L>
-__device__ __forceinline__ double taylor_scaled(const R (&s)[L], R ea)
+// active lane: returns g[A..B].
+template <class P, int A, int B, int L>
+__device__ __forceinline__ double taylor_dd(const double (&s)[L], double ea)
 {
     constexpr int n = B - A;  // number of variables s_k - s_A, k = A+1..B
-    const double base = (double)s[A];
     double y[n], h[n];
-    double msc = 1.0;
     static_for<0, n>([&](auto vv) {
         constexpr int v = decltype(vv)::value;
-        y[v] = (double)s[A + 1 + v] - base;
+        y[v] = s[A + 1 + v] - s[A];
         h[v] = 1.0;
-        msc *= (double)scale_of(s[A + 1 + v]);
     });
     double acc = kInvFact.v[n];
+    double c_next = kTaylorCoef.v[n][1];
     for (int m = 1; m < 39; ++m) {
+        // the next coefficient's (scalar) load is issued a step ahead
+        const double c = c_next;
+        c_next = kTaylorCoef.v[n][m + 1];
         // h^(1)_m = y_1 h^(1)_{m-1};  h^(k)_m = y_k h^(k)_{m-1} + h^(k-1)_m
         h[0] *= y[0];
         static_for<1, n>([&](auto vv) {
             constexpr int v = decltype(vv)::value;
             h[v] = fma(y[v], h[v], h[v - 1]);
         });
-        const double term = kTaylorCoef.v[n][m] * h[n - 1];
+        const double term = c * h[n - 1];
         acc += term;
-        if (__all(!(fabs(term) > P::kTaylorRelTol * acc))) break;
+        if (__all(!(fabs(term) > P::kGenTaylorTol * acc))) break;
     }
-    return (double)ea * acc * msc;
+    return ea * acc;
 }
 
-// Newton/Taylor switch for a table over L points.  Rounding errors of the
-// Newton recurrence grow by a factor ~ (entries' points)/spread per level, so
-// longer ranges switch to the series at larger spreads.
+// Newton table of L >= 2 sorted points (double): tab[a][b] = g[s_a..s_b]
+// for a < b; an entry of three or more points whose spread is below the
+// policy's threshold for tables of L points is taken from the Taylor series
+// instead.
 template <class P, int L>
-struct TableDelta {
-    static constexpr double v = P::kDelta3 * (L <= 4 ? 1.0 : (L <= 6 ? 2.0 : 3.0));
-};
-
-// Scaled sorted table over L >= 3 points: returns ghat[0..L-1].
-template <class P, int L>
-__device__ __forceinline__ typename P::real dd_top(const typename P::real (&s)[L],
-                                                   const typename P::real (&e)[L])
+__device__ __forceinline__ void dd_table(const double (&s)[L], const double (&e)[L], double (&tab)[L][L])
 {
-    using R = typename P::real;
-    constexpr R delta = R(TableDelta<P, L>::v);
-    R tab[L][L];
-    R msc[L];
-    static_for<0, L>([&](auto aa) {
-        constexpr int a = decltype(aa)::value;
-        msc[a] = scale_of(s[a]);
-    });
+    constexpr double delta = P::kGenDelta[L];
+    // pairs: difference quotient, or the phi series below 0.1 (branch-free)
     static_for<0, L - 1>([&](auto aa) {
         constexpr int a = decltype(aa)::value;
-        if constexpr (L <= 4) {
-            tab[a][a + 1] = g2_sorted<P>(s[a], s[a + 1], e[a], e[a + 1]) * msc[a + 1];
-        } else {
-            const R d = s[a + 1] - s[a];
-            R t;
-            if (d >= delta)
-                t = P::quot(e[a] - e[a + 1], d) * msc[a + 1];
-            else
-                t = (R)taylor_scaled<P, a, a + 1>(s, e[a]);
-            tab[a][a + 1] = t;
-        }
+        tab[a][a + 1] = g2_sorted<PolicyF64>(s[a], s[a + 1], e[a], e[a + 1]);
     });
     static_for<2, L>([&](auto ll) {
         constexpr int len = decltype(ll)::value;
         static_for<0, L - len>([&](auto aa) {
             constexpr int a = decltype(aa)::value;
             constexpr int b = a + len;
-            const R spread = s[b] - s[a];
-            R t;
-            if (spread >= delta) {
-                t = P::quot(tab[a][b - 1] * msc[b] - tab[a + 1][b] * msc[a + 1], spread);
-            } else {
-                t = (R)taylor_scaled<P, a, b>(s, e[a]);
-            }
+            const double spread = s[b] - s[a];
+            double t;
+            if (spread >= delta)
+                t = PolicyF64::quot(tab[a][b - 1] - tab[a + 1][b], spread);
+            else
+                t = taylor_dd<P, a, b>(s, e[a]);
             tab[a][b] = t;
         });
     });
+}
+
+// g over L >= 2 sorted points (double).
+template <class P, int L>
+__device__ __forceinline__ double dd_sorted(const double (&s)[L], const double (&e)[L])
+{
+    double tab[L][L];
+    dd_table<P, L>(s, e, tab);
     return tab[0][L - 1];
 }
 
 // T[J][I] for the chain range [I..J] of rate points (J - I >= 2), 0 when the
 // rate product is negligible in every lane of the wavefront.
 template <class P, int W, int I, int J>
-__device__ __forceinline__ double range_entry(const typename P::real (&x)[W], const typename P::real (&ex)[W])
+__device__ __forceinline__ double range_entry(const double (&x)[W], const double (&ex)[W])
 {
-    using R = typename P::real;
     constexpr int L = J - I + 1;
     double prod = 1.0;
-    R rho = R(1);  // prod x_k / max(1, x_k) = prod min(x_k, 1)
-    static_for<I, J>([&](auto kk) {
-        constexpr int k = decltype(kk)::value;
-        prod *= (double)x[k];
-        rho *= x[k] < R(1) ? x[k] : R(1);
-    });
+    static_for<I, J>([&](auto kk) { prod *= x[decltype(kk)::value]; });
     if (!__any(prod >= P::kSkipProduct)) return 0.0;
-    R s[L], e[L];
+    double s[L], e[L];
     static_for<0, L>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
         s[k] = x[I + k];
         e[k] = ex[I + k];
     });
     sort_points<L>(s, e);
-    const R top = dd_top<P, L>(s, e);
-    const R ratio = P::quot(scale_of(s[0]), scale_of(x[J]));
-    return (double)rho * (double)top * (double)ratio;
+    // a range clustered as a whole needs its top entry only: one series
+    double g;
+    if (s[L - 1] - s[0] < P::kGenDelta[L])
+        g = taylor_dd<P, 0, L - 1>(s, e[0]);
+    else
+        g = dd_sorted<P, L>(s, e);
+    return prod * g;
 }
 
 // g of two points in any order.
@@ -422,40 +408,74 @@ __device__ __forceinline__ void chain_apply(const typename P::real (&x)[W], cons
     }
 }
 
-// Windows of four or more rates: every range of three or more points is
-// sorted and tabulated on its own.
+// Windows of four or more rates, in double for either policy.  Double range
+// holds every product of up to eight capped rates and every divided
+// difference, so no scaling is needed, and double rounding lets the Newton
+// recurrence run down to much smaller spreads than float would (the series
+// then converges in a few terms).
 template <class P, int W>
 __device__ __forceinline__ void chain_apply_general(const typename P::real (&x)[W], const double (&N)[W + 1],
                                                     double (&out)[W + 1])
 {
-    using R = typename P::real;
-    R ex[W];
-    double om[W];
+    double xd[W], ex[W], om[W];
     static_for<0, W>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
-        ex[k] = P::expneg(x[k]);
-        om[k] = (double)one_minus_exp<P>(x[k], ex[k]);
+        xd[k] = (double)x[k];
+        ex[k] = exp(-xd[k]);
+        om[k] = one_minus_exp<PolicyF64>(xd[k], ex[k]);
     });
     // T[j][i] for i <= j < W
     double T[W][W];
     static_for<0, W>([&](auto ii) {
         constexpr int i = decltype(ii)::value;
-        T[i][i] = (double)ex[i];
+        T[i][i] = ex[i];
         if constexpr (i + 1 < W) {
-            const R a = x[i], b = x[i + 1];
+            const double a = xd[i], b = xd[i + 1];
             const bool sw = a > b;
-            const R lo = sw ? b : a, hi = sw ? a : b;
-            const R elo = sw ? ex[i + 1] : ex[i], ehi = sw ? ex[i] : ex[i + 1];
-            T[i + 1][i] = (double)(x[i] * g2_sorted<P>(lo, hi, elo, ehi));
+            const double lo = sw ? b : a, hi = sw ? a : b;
+            const double elo = sw ? ex[i + 1] : ex[i], ehi = sw ? ex[i] : ex[i + 1];
+            T[i + 1][i] = xd[i] * g2_sorted<PolicyF64>(lo, hi, elo, ehi);
         }
     });
-    static_for<2, W>([&](auto dd) {
-        constexpr int d = decltype(dd)::value;
-        static_for<0, W - d>([&](auto ii) {
-            constexpr int i = decltype(ii)::value;
-            T[i + d][i] = range_entry<P, W, i, i + d>(x, ex);
-        });
+    // Rates monotone along the window (the usual case: deeper levels ionize
+    // more slowly) in every lane: the chain order is the sorted order,
+    // reversed where the rates fall, and one table over the W points gives
+    // every range.  Otherwise each range is sorted and tabulated on its own.
+    bool inc = true, dec = true;
+    static_for<0, W - 1>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        inc = inc && xd[k] <= xd[k + 1];
+        dec = dec && xd[k] >= xd[k + 1];
     });
+    if (__all(inc || dec)) {
+        double s[W], e[W], tab[W][W];
+        static_for<0, W>([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            s[k] = dec ? xd[W - 1 - k] : xd[k];
+            e[k] = dec ? ex[W - 1 - k] : ex[k];
+        });
+        dd_table<P, W>(s, e, tab);
+        static_for<2, W>([&](auto dd) {
+            constexpr int d = decltype(dd)::value;
+            static_for<0, W - d>([&](auto ii) {
+                constexpr int i = decltype(ii)::value;
+                double prod = 1.0;
+                static_for<i, i + d>([&](auto kk) { prod *= xd[decltype(kk)::value]; });
+                // chain range [i..i+d] = sorted positions [i..i+d], or
+                // [W-1-i-d..W-1-i] where the rates fall
+                const double g = dec ? tab[W - 1 - i - d][W - 1 - i] : tab[i][i + d];
+                T[i + d][i] = prod * g;
+            });
+        });
+    } else {
+        static_for<2, W>([&](auto dd) {
+            constexpr int d = decltype(dd)::value;
+            static_for<0, W - d>([&](auto ii) {
+                constexpr int i = decltype(ii)::value;
+                T[i + d][i] = range_entry<P, W, i, i + d>(xd, ex);
+            });
+        });
+    }
     static_for<0, W>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
         double acc = T[j][j] * N[j];

@@ -570,10 +570,13 @@ ADK_DECLARE_PREC(mixed)
 // ---------------------------------------------------------------------------
 // Batched step over cells of several gases and window widths (plan).
 // Cells are grouped by (gas, w) on the host; a tile is up to CPL*kBlock cells
-// of one group, listed through a permutation of the cell index.  One
-// persistent launch: every resident workgroup takes tiles from an atomic
-// counter until the list is exhausted; the last workgroup to finish resets
-// the counters, so consecutive launches (and graph replays) need no memset.
+// of one group, listed through a permutation of the cell index.  The widths
+// of a plan are split into launch groups, each served by one launch of the
+// kernel compiled for the group's widest window (its register budget, and so
+// the waves a SIMD can hold, is that of the widest solver it contains).  One
+// workgroup per tile, tiles in the host's order (heaviest first): the
+// hardware dispatcher balances the load, with no device-wide counter (an
+// atomic on one address from every workgroup serialises across the chip).
 namespace adk {
 
 constexpr int kPlanMaxGas = 8;
@@ -590,7 +593,8 @@ struct PlanArgs {
     PlanGasArgs gas[kPlanMaxGas];
     double ln_dt;
     double eps;
-    int ntiles;
+    int t0;      // first tile of the launch group
+    int ntiles;  // tiles of the launch group
 };
 
 struct PlanTile {
@@ -630,85 +634,65 @@ __device__ __forceinline__ void plan_tile(const PlanTile &tile, const PlanGasArg
     });
 }
 
-template <class P, int CPL>
+// Tiles of widths 1..WMAX (the host never hands a wider tile to it);
+// workgroup b takes tile t0 + b.
+template <class P, int WMAX, int CPL>
 __global__ __launch_bounds__(kBlock) void plan_kernel(PlanArgs a, const typename P::real *__restrict__ E,
                                                       typename P::real *__restrict__ pops,
                                                       uint8_t *__restrict__ lo, int64_t n,
                                                       const int32_t *__restrict__ perm,
-                                                      const PlanTile *__restrict__ tiles, unsigned *ctr)
+                                                      const PlanTile *__restrict__ tiles)
 {
     __shared__ double sc[kDevTableLen];
-    __shared__ int s_tile;
-    int staged = -1;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = (int)atomicAdd(&ctr[0], 1u);
-        __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(s_tile);
-        __syncthreads();
-        if (t >= a.ntiles) break;
-        const PlanTile tile = tiles[t];
-        // uniform selection (a dynamic index into the argument block would
-        // put it in scratch memory)
-        PlanGasArgs g = a.gas[0];
-        static_for<1, kPlanMaxGas>([&](auto kk) {
-            if (tile.gas == decltype(kk)::value) g = a.gas[decltype(kk)::value];
+    if ((int)blockIdx.x >= a.ntiles) return;
+    const PlanTile tile = tiles[a.t0 + (int)blockIdx.x];
+    // uniform selection (a dynamic index into the argument block would put
+    // it in scratch memory)
+    PlanGasArgs g = a.gas[0];
+    static_for<1, kPlanMaxGas>([&](auto kk) {
+        if (tile.gas == decltype(kk)::value) g = a.gas[decltype(kk)::value];
+    });
+    stage_coefficients(sc, g.tab, a.ln_dt);
+    if constexpr (WMAX == 1) {
+        plan_tile<P, 1, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm);
+    } else {
+        static_for<1, WMAX + 1>([&](auto ww) {
+            constexpr int w = decltype(ww)::value;
+            if (tile.w == w) plan_tile<P, w, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm);
         });
-        if (tile.gas != staged) {
-            stage_coefficients(sc, g.tab, a.ln_dt);
-            staged = tile.gas;
-        }
-        switch (tile.w) {
-        case 1: plan_tile<P, 1, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
-        case 2: plan_tile<P, 2, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
-        case 3: plan_tile<P, 3, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
-        case 4: plan_tile<P, 4, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
-        case 5: plan_tile<P, 5, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
-        default: plan_tile<P, 6, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm); break;
-        }
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned done = atomicAdd(&ctr[1], 1u);
-        if (done == gridDim.x - 1) {
-            atomicExch(&ctr[0], 0u);
-            atomicExch(&ctr[1], 0u);
-        }
     }
 }
 
-template <class P, int CPL>
-hipError_t launch_plan(const PlanArgs &a, int grid, const void *E, void *pops, uint8_t *lo, int64_t n,
-                       const int32_t *perm, const PlanTile *tiles, unsigned *ctr, hipStream_t st)
+template <class P, int WMAX, int CPL>
+hipError_t launch_plan(const PlanArgs &a, const void *E, void *pops, uint8_t *lo, int64_t n, const int32_t *perm,
+                       const PlanTile *tiles, hipStream_t st)
 {
     using R = typename P::real;
-    hipLaunchKernelGGL((plan_kernel<P, CPL>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E, (R *)pops, lo, n,
-                       perm, tiles, ctr);
+    hipLaunchKernelGGL((plan_kernel<P, WMAX, CPL>), dim3(a.ntiles), dim3(kBlock), 0, st, a, (const R *)E,
+                       (R *)pops, lo, n, perm, tiles);
     return hipGetLastError();
 }
 
-template <class P, int CPL>
-int plan_occupancy()
-{
-    int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, plan_kernel<P, CPL>, kBlock, 0) != hipSuccess || b <= 0)
-        b = 2;
-    return b;
-}
-
-using PlanLaunchFn = hipError_t (*)(const PlanArgs &, int, const void *, void *, uint8_t *, int64_t,
-                                    const int32_t *, const PlanTile *, unsigned *, hipStream_t);
-using PlanOccFn = int (*)();
+using PlanLaunchFn = hipError_t (*)(const PlanArgs &, const void *, void *, uint8_t *, int64_t, const int32_t *,
+                                    const PlanTile *, hipStream_t);
 
 }  // namespace adk
 
-#define ADK_DECLARE_PLAN(PREC, CPL)                                                                        \
-    hipError_t adk_plan_launch_##PREC##_##CPL(const adk::PlanArgs &, int, const void *, void *, uint8_t *, \
-                                              int64_t, const int32_t *, const adk::PlanTile *, unsigned *, \
-                                              hipStream_t);                                                \
-    int adk_plan_occupancy_##PREC##_##CPL();
-ADK_DECLARE_PLAN(f64, 1)
-ADK_DECLARE_PLAN(f64, 2)
-ADK_DECLARE_PLAN(f64, 4)
-ADK_DECLARE_PLAN(mixed, 1)
-ADK_DECLARE_PLAN(mixed, 2)
-ADK_DECLARE_PLAN(mixed, 4)
+// adk_plan_launch_<prec>_<wmax>_<cpl>
+#define ADK_DECLARE_PLAN_CPL(PREC, WMAX, CPL)                                                              \
+    hipError_t adk_plan_launch_##PREC##_##WMAX##_##CPL(const adk::PlanArgs &, const void *, void *,        \
+                                                       uint8_t *, int64_t, const int32_t *,                \
+                                                       const adk::PlanTile *, hipStream_t);
+#define ADK_DECLARE_PLAN(PREC, WMAX)      \
+    ADK_DECLARE_PLAN_CPL(PREC, WMAX, 1)   \
+    ADK_DECLARE_PLAN_CPL(PREC, WMAX, 2)   \
+    ADK_DECLARE_PLAN_CPL(PREC, WMAX, 4)
+#define ADK_DECLARE_PLAN_PREC(PREC) \
+    ADK_DECLARE_PLAN(PREC, 1)       \
+    ADK_DECLARE_PLAN(PREC, 2)       \
+    ADK_DECLARE_PLAN(PREC, 3)       \
+    ADK_DECLARE_PLAN(PREC, 4)       \
+    ADK_DECLARE_PLAN(PREC, 5)       \
+    ADK_DECLARE_PLAN(PREC, 6)
+ADK_DECLARE_PLAN_PREC(f64)
+ADK_DECLARE_PLAN_PREC(mixed)

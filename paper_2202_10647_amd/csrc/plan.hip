@@ -3,11 +3,15 @@
 //
 // A plan groups the cells by (gas, window width) with a stable counting sort
 // (cells of a group keep their mesh order, so runs of neighbouring cells stay
-// coalesced), orders the groups heaviest first (wider windows and longer
-// chains first, so the persistent launch starts the long tiles early), and
-// cuts them into tiles of cells_per_lane x 256 cells.  cells_per_lane is
-// chosen by timed trials on scratch buffers unless the caller fixes it; the
-// choice is cached per (device, problem) in the file named by the
+// coalesced) and orders the groups heaviest first (wider windows and longer
+// chains first).  The widths are then split into launch groups: a width with
+// at least ADK_PLAN_SOLO_CELLS cells gets a launch of its own, compiled for
+// that width; consecutive smaller widths share one launch compiled for the
+// widest of them (one extra launch costs more than the lower occupancy of a
+// wider kernel on few cells).  Each launch group is cut into tiles of
+// cells_per_lane x 256 cells; cells_per_lane is chosen per launch group by
+// timed trials on scratch buffers unless the caller fixes it, and the choice
+// is cached per (device, problem, launch group) in the file named by the
 // ADK_TUNE_CACHE environment variable, when it is set.
 #include <hip/hip_runtime.h>
 
@@ -23,6 +27,23 @@
 
 #include "kernels.hpp"
 
+namespace adk {
+
+// One persistent launch of a plan step: buckets [b0, b1) of the sorted
+// bucket list, tiles [t0, t0 + ntiles) of the plan's tile list.
+struct PlanGroup {
+    int wmax = 0;
+    int b0 = 0, b1 = 0;
+    int64_t cells = 0;
+    int cpl = 0;
+    int t0 = 0, ntiles = 0;
+    int grid = 0;
+    double tuned_us = 0.0;
+    int from_cache = 0;
+};
+
+}  // namespace adk
+
 struct adk_plan {
     int ngas = 0;
     const adk_gas *gas[adk::kPlanMaxGas] = {};
@@ -32,13 +53,10 @@ struct adk_plan {
     int rows = 0;
     int nbuckets = 0;
     int ntiles = 0;
-    int cpl = 1;
-    int grid = 0;
-    double tuned_us = 0.0;
-    int from_cache = 0;
+    int ngroups = 0;
+    adk::PlanGroup group[adk::kPlanMaxW];
     int32_t *d_perm = nullptr;
     adk::PlanTile *d_tiles = nullptr;
-    unsigned *d_ctr = nullptr;
 };
 
 namespace adk {
@@ -80,14 +98,23 @@ __global__ __launch_bounds__(kBlock) void neutral_fill_kernel(R *__restrict__ po
     }
 }
 
-static const PlanLaunchFn kPlanLaunch[2][3] = {
-    {adk_plan_launch_f64_1, adk_plan_launch_f64_2, adk_plan_launch_f64_4},
-    {adk_plan_launch_mixed_1, adk_plan_launch_mixed_2, adk_plan_launch_mixed_4}};
-static const PlanOccFn kPlanOcc[2][3] = {{adk_plan_occupancy_f64_1, adk_plan_occupancy_f64_2, adk_plan_occupancy_f64_4},
-                                         {adk_plan_occupancy_mixed_1, adk_plan_occupancy_mixed_2,
-                                          adk_plan_occupancy_mixed_4}};
+#define ADK_PLAN_FNS(PREC, WMAX)                                                                     \
+    {adk_plan_launch_##PREC##_##WMAX##_1, adk_plan_launch_##PREC##_##WMAX##_2,                       \
+     adk_plan_launch_##PREC##_##WMAX##_4}
+// [precision: f64, mixed][widest window - 1][cells per lane: 1, 2, 4]
+static const PlanLaunchFn kPlanLaunch[2][kPlanMaxW][3] = {
+    {ADK_PLAN_FNS(f64, 1), ADK_PLAN_FNS(f64, 2), ADK_PLAN_FNS(f64, 3), ADK_PLAN_FNS(f64, 4), ADK_PLAN_FNS(f64, 5),
+     ADK_PLAN_FNS(f64, 6)},
+    {ADK_PLAN_FNS(mixed, 1), ADK_PLAN_FNS(mixed, 2), ADK_PLAN_FNS(mixed, 3), ADK_PLAN_FNS(mixed, 4),
+     ADK_PLAN_FNS(mixed, 5), ADK_PLAN_FNS(mixed, 6)}};
+#undef ADK_PLAN_FNS
 
 static int cpl_slot(int cpl) { return cpl == 1 ? 0 : (cpl == 2 ? 1 : 2); }
+
+static PlanLaunchFn plan_fn(const adk_plan *p, int wmax, int cpl)
+{
+    return kPlanLaunch[p->prec == ADK_MIXED ? 1 : 0][wmax - 1][cpl_slot(cpl)];
+}
 
 static int plan_status(hipError_t e)
 {
@@ -102,12 +129,43 @@ struct Bucket {
     int64_t offset;  // start in the permutation
 };
 
-// Tiles of cpl * kBlock cells over the buckets in permutation order.
-static std::vector<PlanTile> make_tiles(const std::vector<Bucket> &b, int cpl)
+// Launch groups over the buckets (sorted by width, widest first): a width
+// with at least ADK_PLAN_SOLO_CELLS cells stands alone; runs of smaller
+// widths between such widths share one launch.
+static std::vector<PlanGroup> make_groups(const std::vector<Bucket> &b)
 {
-    std::vector<PlanTile> t;
+    std::vector<PlanGroup> g;
+    bool open = false;  // the last group takes further small widths
+    size_t i = 0;
+    while (i < b.size()) {
+        const int w = b[i].w;
+        size_t j = i;
+        int64_t cells = 0;
+        while (j < b.size() && b[j].w == w) cells += b[j++].count;
+        const bool solo = cells >= (int64_t)ADK_PLAN_SOLO_CELLS;
+        if (solo || !open) {
+            PlanGroup x;
+            x.wmax = w;
+            x.b0 = (int)i;
+            x.b1 = (int)j;
+            x.cells = cells;
+            g.push_back(x);
+            open = !solo;
+        } else {
+            g.back().b1 = (int)j;
+            g.back().cells += cells;
+        }
+        i = j;
+    }
+    return g;
+}
+
+// Tiles of cpl * kBlock cells over buckets [b0, b1), appended to t.
+static void make_tiles(const std::vector<Bucket> &b, int b0, int b1, int cpl, std::vector<PlanTile> &t)
+{
     const int64_t T = (int64_t)cpl * kBlock;
-    for (const Bucket &k : b)
+    for (int i = b0; i < b1; ++i) {
+        const Bucket &k = b[(size_t)i];
         for (int64_t s = 0; s < k.count; s += T) {
             PlanTile x;
             x.gas = k.gas;
@@ -116,10 +174,10 @@ static std::vector<PlanTile> make_tiles(const std::vector<Bucket> &b, int cpl)
             x.count = (int32_t)std::min<int64_t>(T, k.count - s);
             t.push_back(x);
         }
-    return t;
+    }
 }
 
-static PlanArgs plan_args(const adk_plan *p, double dt, int ntiles)
+static PlanArgs plan_args(const adk_plan *p, double dt, int t0, int ntiles)
 {
     PlanArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -132,32 +190,27 @@ static PlanArgs plan_args(const adk_plan *p, double dt, int ntiles)
     }
     a.ln_dt = std::log(dt);
     a.eps = p->eps;
+    a.t0 = t0;
     a.ntiles = ntiles;
     return a;
 }
 
-static int plan_grid(const adk_plan *p, int cpl, int ntiles)
-{
-    const int occ = kPlanOcc[p->prec == ADK_MIXED ? 1 : 0][cpl_slot(cpl)]();
-    const int g = num_cus() * occ;
-    return std::max(1, std::min(g, ntiles));
-}
-
-static std::string tune_key(const adk_plan *p, const std::vector<Bucket> &b)
+static std::string tune_key(const adk_plan *p, const std::vector<Bucket> &b, const PlanGroup &grp)
 {
     hipDeviceProp_t prop;
     int dev = 0;
     std::string arch = "unknown";
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
     uint64_t h = 0x84222325cbf29ce4ull;
-    for (const Bucket &k : b) {
+    for (int i = grp.b0; i < grp.b1; ++i) {
+        const Bucket &k = b[(size_t)i];
         h = splitmix64(h ^ (uint64_t)(k.gas * 131 + k.w));
         h = splitmix64(h ^ (uint64_t)k.count);
         h = splitmix64(h ^ (uint64_t)p->gas[k.gas]->Z);
     }
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s|n=%lld|prec=%d|b=%016llx", arch.c_str(), (long long)p->ncells,
-                  (int)p->prec, (unsigned long long)h);
+    std::snprintf(buf, sizeof(buf), "%s|n=%lld|prec=%d|wmax=%d|b=%016llx", arch.c_str(), (long long)p->ncells,
+                  (int)p->prec, grp.wmax, (unsigned long long)h);
     for (char *c = buf; *c; ++c)
         if (*c == ' ') *c = '_';
     return buf;
@@ -187,24 +240,20 @@ static void cache_store(const std::string &key, int cpl)
     std::fclose(f);
 }
 
-// Timed trials of cells_per_lane in {1, 2, 4} on scratch buffers: neutral
-// state, fields log-uniform in [10, 5000] GV/m, dt = 0.1 fs.
-static int autotune(adk_plan *p, const std::vector<Bucket> &b, int *cpl_out, double *best_us)
+// Timed trials of cells_per_lane in {1, 2, 4} for every launch group whose
+// choice is still open (cpl == 0), each group timed alone on scratch buffers:
+// neutral state, fields log-uniform in [10, 500] GV/m, dt = 0.1 fs.
+static int autotune(adk_plan *p, const std::vector<Bucket> &b, std::vector<PlanGroup> &groups)
 {
     const int64_t n = p->ncells;
     const size_t es = p->prec == ADK_MIXED ? 4 : 8;
     void *E = nullptr, *pops = nullptr;
     uint8_t *lo = nullptr;
     PlanTile *tiles = nullptr;
-    unsigned *ctr = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    int best = 1;
-    *best_us = 0.0;
     hipError_t err = hipMalloc(&E, es * (size_t)n);
     if (err == hipSuccess) err = hipMalloc(&pops, es * (size_t)n * (size_t)p->rows);
     if (err == hipSuccess) err = hipMalloc((void **)&lo, (size_t)n);
-    if (err == hipSuccess) err = hipMalloc((void **)&ctr, 2 * sizeof(unsigned));
-    if (err == hipSuccess) err = hipMemset(ctr, 0, 2 * sizeof(unsigned));
     const size_t max_tiles = (size_t)(n / kBlock + b.size() + 1);
     if (err == hipSuccess) err = hipMalloc((void **)&tiles, sizeof(PlanTile) * max_tiles);
     if (err == hipSuccess) err = hipEventCreate(&e0);
@@ -223,29 +272,37 @@ static int autotune(adk_plan *p, const std::vector<Bucket> &b, int *cpl_out, dou
         }
         err = hipGetLastError();
     }
-    double best_t = 1e300;
     const int cands[3] = {1, 2, 4};
-    for (int ci = 0; ci < 3 && err == hipSuccess; ++ci) {
-        const int cpl = cands[ci];
-        const std::vector<PlanTile> t = make_tiles(b, cpl);
-        err = hipMemcpy(tiles, t.data(), sizeof(PlanTile) * t.size(), hipMemcpyHostToDevice);
-        if (err != hipSuccess) break;
-        const PlanArgs a = plan_args(p, 1e-16, (int)t.size());
-        const int grid = plan_grid(p, cpl, (int)t.size());
-        const PlanLaunchFn fn = kPlanLaunch[p->prec == ADK_MIXED ? 1 : 0][ci];
-        double t_min = 1e300;
-        for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
-            err = hipEventRecord(e0, 0);
-            if (err == hipSuccess) err = fn(a, grid, E, pops, lo, n, p->d_perm, tiles, ctr, 0);
-            if (err == hipSuccess) err = hipEventRecord(e1, 0);
-            if (err == hipSuccess) err = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-            if (rep > 0) t_min = std::min(t_min, (double)ms);  // first launch is a warm-up
+    for (PlanGroup &grp : groups) {
+        if (grp.cpl != 0 || err != hipSuccess) continue;
+        double best_t = 1e300;
+        int best = 1;
+        for (int ci = 0; ci < 3 && err == hipSuccess; ++ci) {
+            const int cpl = cands[ci];
+            std::vector<PlanTile> t;
+            make_tiles(b, grp.b0, grp.b1, cpl, t);
+            err = hipMemcpy(tiles, t.data(), sizeof(PlanTile) * t.size(), hipMemcpyHostToDevice);
+            if (err != hipSuccess) break;
+            const PlanArgs a = plan_args(p, 1e-16, 0, (int)t.size());
+            const PlanLaunchFn fn = plan_fn(p, grp.wmax, cpl);
+            double t_min = 1e300;
+            for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+                err = hipEventRecord(e0, 0);
+                if (err == hipSuccess) err = fn(a, E, pops, lo, n, p->d_perm, tiles, 0);
+                if (err == hipSuccess) err = hipEventRecord(e1, 0);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) t_min = std::min(t_min, (double)ms);  // first launch is a warm-up
+            }
+            if (t_min < best_t) {
+                best_t = t_min;
+                best = cpl;
+            }
         }
-        if (t_min < best_t) {
-            best_t = t_min;
-            best = cpl;
+        if (err == hipSuccess) {
+            grp.cpl = best;
+            grp.tuned_us = best_t * 1e3;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -254,11 +311,7 @@ static int autotune(adk_plan *p, const std::vector<Bucket> &b, int *cpl_out, dou
     if (pops) (void)hipFree(pops);
     if (lo) (void)hipFree(lo);
     if (tiles) (void)hipFree(tiles);
-    if (ctr) (void)hipFree(ctr);
-    if (err != hipSuccess) return plan_status(err);
-    *best_us = best_t * 1e3;
-    *cpl_out = best;
-    return ADK_OK;
+    return plan_status(err);
 }
 
 }  // namespace adk
@@ -321,6 +374,7 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
         int64_t &o = offset[(size_t)cell_gas[c] * (kPlanMaxW + 1) + cell_w[c]];
         perm[(size_t)o++] = (int32_t)c;
     }
+    std::vector<PlanGroup> groups = make_groups(b);
     int st = ADK_OK;
     hipError_t e = hipSuccess;
     if (ncells > 0) {
@@ -328,34 +382,42 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
         if (e == hipSuccess)
             e = hipMemcpy(p->d_perm, perm.data(), sizeof(int32_t) * (size_t)ncells, hipMemcpyHostToDevice);
     }
-    if (e == hipSuccess) e = hipMalloc((void **)&p->d_ctr, 2 * sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemset(p->d_ctr, 0, 2 * sizeof(unsigned));
     if (e != hipSuccess) st = plan_status(e);
     if (st == ADK_OK) {
-        int cpl = cells_per_lane;
-        if (cpl == 0 && ncells > 0) {
-            const std::string key = tune_key(p, b);
-            cpl = cache_lookup(key);
-            if (cpl) {
-                p->from_cache = 1;
-            } else {
-                st = autotune(p, b, &cpl, &p->tuned_us);
-                if (st == ADK_OK) cache_store(key, cpl);
+        bool tune = false;
+        for (PlanGroup &grp : groups) {
+            grp.cpl = cells_per_lane;
+            if (grp.cpl == 0) {
+                grp.cpl = cache_lookup(tune_key(p, b, grp));
+                grp.from_cache = grp.cpl != 0;
+                tune = tune || grp.cpl == 0;
             }
         }
-        if (cpl == 0) cpl = 1;
-        p->cpl = cpl;
+        if (tune) {
+            st = autotune(p, b, groups);
+            if (st == ADK_OK)
+                for (const PlanGroup &grp : groups)
+                    if (!grp.from_cache) cache_store(tune_key(p, b, grp), grp.cpl);
+        }
     }
+    std::vector<PlanTile> t;
     if (st == ADK_OK) {
-        const std::vector<PlanTile> t = make_tiles(b, p->cpl);
+        for (PlanGroup &grp : groups) {
+            if (grp.cpl == 0) grp.cpl = 1;
+            grp.t0 = (int)t.size();
+            make_tiles(b, grp.b0, grp.b1, grp.cpl, t);
+            grp.ntiles = (int)t.size() - grp.t0;
+            grp.grid = grp.ntiles;
+        }
         p->ntiles = (int)t.size();
+        p->ngroups = (int)groups.size();
+        for (size_t i = 0; i < groups.size(); ++i) p->group[i] = groups[i];
         if (!t.empty()) {
             e = hipMalloc((void **)&p->d_tiles, sizeof(PlanTile) * t.size());
             if (e == hipSuccess)
                 e = hipMemcpy(p->d_tiles, t.data(), sizeof(PlanTile) * t.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) st = plan_status(e);
         }
-        p->grid = plan_grid(p, p->cpl, std::max(p->ntiles, 1));
     }
     if (st != ADK_OK) {
         adk_plan_destroy(p);
@@ -370,23 +432,41 @@ int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t 
     if (!plan) return ADK_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
     if (plan->ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
-    if (plan->ntiles == 0) return ADK_OK;
-    const PlanArgs a = plan_args(plan, dt, plan->ntiles);
-    const PlanLaunchFn fn = kPlanLaunch[plan->prec == ADK_MIXED ? 1 : 0][cpl_slot(plan->cpl)];
-    return plan_status(fn(a, plan->grid, E, pops, lo, plan->ncells, plan->d_perm, plan->d_tiles, plan->d_ctr, stream));
+    for (int i = 0; i < plan->ngroups; ++i) {
+        const PlanGroup &grp = plan->group[i];
+        const PlanArgs a = plan_args(plan, dt, grp.t0, grp.ntiles);
+        const hipError_t e = plan_fn(plan, grp.wmax, grp.cpl)(a, E, pops, lo, plan->ncells, plan->d_perm,
+                                                              plan->d_tiles, stream);
+        if (e != hipSuccess) return plan_status(e);
+    }
+    return ADK_OK;
 }
 
 int adk_plan_get_info(const adk_plan *plan, adk_plan_info *info)
 {
     if (!plan || !info) return ADK_EINVAL;
+    std::memset(info, 0, sizeof(*info));
     info->ngas = plan->ngas;
     info->nbuckets = plan->nbuckets;
     info->ntiles = plan->ntiles;
-    info->cells_per_lane = plan->cpl;
-    info->grid = plan->grid;
     info->rows = plan->rows;
-    info->from_cache = plan->from_cache;
-    info->tuned_us = plan->tuned_us;
+    info->nlaunches = plan->ngroups;
+    int big = -1, cached = 0, tuned = 0;
+    for (int i = 0; i < plan->ngroups; ++i) {
+        const PlanGroup &grp = plan->group[i];
+        info->launch_wmax[i] = grp.wmax;
+        info->launch_cpl[i] = grp.cpl;
+        info->launch_grid[i] = grp.grid;
+        info->launch_tiles[i] = grp.ntiles;
+        info->launch_cells[i] = grp.cells;
+        info->tuned_us += grp.tuned_us;
+        cached += grp.from_cache;
+        tuned += grp.from_cache || grp.tuned_us > 0.0;
+        if (big < 0 || grp.cells > plan->group[big].cells) big = i;
+    }
+    info->cells_per_lane = big >= 0 ? plan->group[big].cpl : 1;
+    info->grid = big >= 0 ? plan->group[big].grid : 0;
+    info->from_cache = tuned > 0 && cached == tuned;
     return ADK_OK;
 }
 
@@ -397,10 +477,6 @@ int adk_plan_destroy(adk_plan *plan)
     if (plan->d_perm) e = hipFree(plan->d_perm);
     if (plan->d_tiles) {
         const hipError_t e2 = hipFree(plan->d_tiles);
-        if (e == hipSuccess) e = e2;
-    }
-    if (plan->d_ctr) {
-        const hipError_t e2 = hipFree(plan->d_ctr);
         if (e == hipSuccess) e = e2;
     }
     delete plan;

@@ -136,6 +136,31 @@ def test_chain_advance_adversarial(torch_dev, ak, orc, prec, w):
     assert out.astype(np.float64).min() >= -TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("w", [4, 5, 6, 7, 8])
+def test_chain_advance_monotone(torch_dev, ak, orc, prec, w):
+    """The adversarial rate sets sorted along the window (falling in a random
+    half of the cells, rising in the other): every wavefront takes the
+    single-table path for monotone windows."""
+    torch = torch_dev
+    rng = np.random.default_rng(2000 + w)
+    n = 4099
+    x = np.sort(adversarial_rates(rng, w, n), axis=0)
+    fall = rng.random(n) < 0.5
+    x[:, fall] = x[::-1, fall]
+    W = (x / DT).astype(npdt(prec))
+    pops = rng.random((w + 1, n))
+    pops /= pops.sum(axis=0)
+    pops = pops.astype(npdt(prec))
+    Wt = torch.from_numpy(W).cuda()
+    Pt = torch.from_numpy(pops).cuda()
+    ak.chain_advance(Wt, DT, Pt)
+    out = Pt.cpu().numpy()
+    ref = orc.chain_advance(W.astype(np.float64), DT, pops.astype(np.float64))
+    compare(out, ref, prec, f"chain_advance monotone w={w} {prec}")
+    assert out.astype(np.float64).min() >= -TOL[prec]
+
+
 def test_config1_full_chain_f64(torch_dev, ak, orc):
     """4096 cells, 7-level chain, E log-uniform [10, 2000] GV/m, dt = 0.1 fs,
     neutral start, full chain (w = Z = 7), one step."""

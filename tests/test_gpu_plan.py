@@ -1,5 +1,5 @@
-"""Batched plan (cells of several gases with uneven windows, one persistent
-launch) against the oracle, per (gas, window) group, from identical inputs."""
+"""Batched plan (cells of several gases with uneven windows, one launch per
+launch group) against the oracle, per (gas, window) group, from identical inputs."""
 import numpy as np
 import pytest
 
@@ -73,13 +73,58 @@ def test_plan_matches_oracle(env, orc, prec, cpl):
     for w in range(1, 6):
         idx = np.nonzero(cell_w == w)[0]
         assert np.all(out[w + 1:, idx] == np.float64(npdt(0.625)))
-    # a second launch of the same plan (counters were reset by the first)
+    # a second launch of the same plan
     plan.step(torch.from_numpy(E).cuda(), DT, Pt, Lt)
     torch.cuda.synchronize()
     ref2, rlo2 = oracle_plan(orc, specs, cell_gas, cell_w, E.astype(np.float64), out.astype(npdt).astype(np.float64),
                              l2, 1e-8)
     assert np.array_equal(Lt.cpu().numpy(), rlo2)
     assert np.max(np.abs(Pt.cpu().numpy().astype(np.float64) - ref2)) <= TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f64"])
+def test_plan_launch_groups(env, orc, prec):
+    """Widths with many cells get launches of their own (compiled for that
+    width), runs of sparse widths share one: 600k cells w = 1 and 600k cells
+    w = 3 (solo), sparse w = 2 and w = 4..6 (two shared launches), interleaved
+    at random over the mesh.  Sampled cells of every (gas, w) group against
+    the oracle, launch by launch as reported in the plan's info."""
+    torch, ak, gases, specs = env
+    rng = np.random.default_rng(77)
+    na, nb, nc = 600_000, 600_000, 120_000
+    g = np.concatenate([np.zeros(na, np.uint8), np.full(nb, 2, np.uint8), rng.integers(1, 5, nc).astype(np.uint8)])
+    w = np.concatenate([np.ones(na, np.uint8), np.full(nb, 3, np.uint8), rng.integers(2, 7, nc).astype(np.uint8)])
+    order = rng.permutation(g.size)
+    cell_gas, cell_w = g[order], w[order]
+    n = cell_gas.size
+    plan = ak.Plan(gases, cell_gas, cell_w, prec=prec, eps=1e-8, cells_per_lane=0)
+    info = plan.info
+    assert info["nlaunches"] == 4
+    assert info["launch_wmax"] == [6, 3, 2, 1]
+    cells = info["launch_cells"]
+    assert cells[1] == int(np.sum(cell_w == 3)) and cells[3] == int(np.sum(cell_w == 1))
+    assert cells[0] == int(np.sum(cell_w >= 4)) and cells[2] == int(np.sum(cell_w == 2))
+    assert sum(info["launch_tiles"]) == info["ntiles"]
+    assert all(c in (1, 2, 4) for c in info["launch_cpl"])
+    npdt = np.float32 if prec == "mixed" else np.float64
+    pops, lo = plan_state(cell_gas, cell_w, info["rows"], seed=123)
+    pops = pops.astype(npdt)
+    E = wl.hash_field(n, seed=19, step=1, dtype=npdt)
+    Pt = torch.from_numpy(pops).cuda()
+    Lt = torch.from_numpy(lo).cuda()
+    plan.step(torch.from_numpy(E).cuda(), DT, Pt, Lt)
+    torch.cuda.synchronize()
+    samp = np.unique(np.concatenate([rng.choice(np.nonzero((cell_gas == gi) & (cell_w == wi))[0], 400)
+                                     for gi in range(len(ZS)) for wi in range(1, 7)
+                                     if np.any((cell_gas == gi) & (cell_w == wi))]))
+    idx = torch.from_numpy(samp).cuda()
+    out, l2 = Pt[:, idx].cpu().numpy().astype(np.float64), Lt[idx].cpu().numpy()
+    sg, sw = cell_gas[samp], cell_w[samp]
+    ref, rlo = oracle_plan(orc, specs, sg, sw, E[samp].astype(np.float64), pops[:, samp].astype(np.float64),
+                           lo[samp], 1e-8)
+    assert np.array_equal(l2, rlo)
+    assert np.max(np.abs(out - ref)) <= TOL[prec]
     plan.close()
 
 
