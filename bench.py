@@ -571,7 +571,7 @@ def surrogate_measure(ak, orc, gas36, spec36, w, eps, steps, train_iters, nsampl
 
 def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
     """Mixed gases with uneven windows (1-level host gas, 1 % dopants of 7, 18,
-    36 and 54 levels, w in 1..6): one persistent plan launch per step.  Each
+    36 and 54 levels, w in 1..6): one launch per launch group per step.  Each
     step's field is generated on the device by the hash harness; the timed
     graph holds [field, step] x steps and the field-only graph is timed
     separately and subtracted."""

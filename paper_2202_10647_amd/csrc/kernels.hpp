@@ -601,9 +601,13 @@ struct PlanTile {
     int32_t gas, w, start, count;
 };
 
+// A tile of one (gas, w) group: the gas table is staged while the first
+// cells' loads are in flight; each lane then walks its CPL cells with the
+// next cell's loads issued before the current one is computed.  A
+// wavefront whose cells all take T = I stores nothing (as ionize_step).
 template <class P, int W, int CPL>
-__device__ __forceinline__ void plan_tile(const PlanTile &tile, const PlanGasArgs &g, double eps, const double *sc,
-                                          const typename P::real *__restrict__ E,
+__device__ __forceinline__ void plan_tile(const PlanTile &tile, const PlanGasArgs &g, double ln_dt, double eps,
+                                          double *sc, const typename P::real *__restrict__ E,
                                           typename P::real *__restrict__ pops, uint8_t *__restrict__ lo, int64_t n,
                                           const int32_t *__restrict__ perm)
 {
@@ -617,6 +621,7 @@ __device__ __forceinline__ void plan_tile(const PlanTile &tile, const PlanGasArg
         cn = perm[idx];
         load_cell(nxt, E, pops, lo, n, cn);
     }
+    stage_coefficients(sc, g.tab, ln_dt);
     static_for<0, CPL>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
         if (idx < end) {
@@ -628,7 +633,12 @@ __device__ __forceinline__ void plan_tile(const PlanTile &tile, const PlanGasArg
                     load_cell(nxt, E, pops, lo, n, cn);
                 }
             }
-            step_cell<P, W>(cur, sc, slog, g.Z, g.has_poly != 0, eps, g.E_cut, pops, lo, n, c);
+            const int p = cur.lo < g.Z ? cur.lo : g.Z;
+            if (__all(p >= g.Z || (fabs((double)cur.E) < g.E_cut && (double)cur.N[0] >= eps))) {
+                if (p != cur.lo) lo[c] = (uint8_t)p;  // an index past Z is clamped
+            } else {
+                step_cell<P, W>(cur, sc, slog, g.Z, g.has_poly != 0, eps, g.E_cut, pops, lo, n, c);
+            }
         }
         idx += kBlock;
     });
@@ -652,13 +662,12 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(PlanArgs a, const typename
     static_for<1, kPlanMaxGas>([&](auto kk) {
         if (tile.gas == decltype(kk)::value) g = a.gas[decltype(kk)::value];
     });
-    stage_coefficients(sc, g.tab, a.ln_dt);
     if constexpr (WMAX == 1) {
-        plan_tile<P, 1, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm);
+        plan_tile<P, 1, CPL>(tile, g, a.ln_dt, a.eps, sc, E, pops, lo, n, perm);
     } else {
         static_for<1, WMAX + 1>([&](auto ww) {
             constexpr int w = decltype(ww)::value;
-            if (tile.w == w) plan_tile<P, w, CPL>(tile, g, a.eps, sc, E, pops, lo, n, perm);
+            if (tile.w == w) plan_tile<P, w, CPL>(tile, g, a.ln_dt, a.eps, sc, E, pops, lo, n, perm);
         });
     }
 }

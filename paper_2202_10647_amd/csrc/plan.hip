@@ -29,7 +29,7 @@
 
 namespace adk {
 
-// One persistent launch of a plan step: buckets [b0, b1) of the sorted
+// One launch of a plan step: buckets [b0, b1) of the sorted
 // bucket list, tiles [t0, t0 + ntiles) of the plan's tile list.
 struct PlanGroup {
     int wmax = 0;
