@@ -358,17 +358,18 @@ def _to_full(P, L, w, Z):
     return full
 
 
-def window_study(ak, mesh, eps, widths=(2, 3, 4), ref_w=8, ref_eps=1e-12, every=10):
+def window_study(ak, mesh, eps, widths=(2, 3, 4, 8), every=10):
     """Full-vs-reduced study on the whole 2D mesh over the whole pulse (the
-    synthetic stand-in for Fig. 2b/2c): FP64 windows of w = 2, 3, 4 rates
-    against a w = 8 window with a 1e-12 shift threshold (which tracks the
-    oracle's full chain to ~1e-12, tests/test_gpu_study.py), sampled every
-    `every` steps: max |dN_k| per level and the relative error of the
-    electron density n_e = sum_k k N_k; then the orbital-number variants of
-    the gas table (Sec. 3 remark on alternative couplings) at w = 3."""
+    synthetic stand-in for Fig. 2b/2c): FP64 windows of w = 2, 3, 4, 8 rates
+    against the full chain (w = Z = 18 on the wide path, no shift; it tracks
+    the oracle's full chain, tests/test_gpu_study.py), sampled every `every`
+    steps: max |dN_k| per level and the relative error of the electron
+    density n_e = sum_k k N_k; then the orbital-number variants of the gas
+    table (Sec. 3 remark on alternative couplings) at w = 3."""
     import torch
     from paper_2202_10647_amd import workloads as wl
     Z = 18
+    ref_w, ref_eps = Z, 0.0
     g = wl.synthetic_gas(Z)
     gas = ak.Gas.from_table(g)
     n = mesh.ncells
@@ -393,10 +394,17 @@ def window_study(ak, mesh, eps, widths=(2, 3, 4), ref_w=8, ref_eps=1e-12, every=
     cell_max = {w: torch.zeros(n, dtype=torch.float64, device="cuda") for w in widths}
     ne_max = {w: torch.zeros(n, dtype=torch.float64, device="cuda") for w in widths}
     t0 = time.perf_counter()
+    ref_s = 0.0
     for t in range(mesh.steps):
         E = mesh.field_torch(t, "cuda", torch.float64)
         for w in ws:
+            if w == ref_w:
+                torch.cuda.synchronize()
+                tr = time.perf_counter()
             ak.ionize_step(gas, E, mesh.dt, *st[w], w=w, eps=ref_eps if w == ref_w else eps)
+            if w == ref_w:
+                torch.cuda.synchronize()
+                ref_s += time.perf_counter() - tr
         if t % every == 0 or t == mesh.steps - 1:
             ref = _to_full(*st[ref_w], ref_w, Z)
             ne_ref = (lev * ref).sum(0)
@@ -412,8 +420,9 @@ def window_study(ak, mesh, eps, widths=(2, 3, 4), ref_w=8, ref_eps=1e-12, every=
     el = time.perf_counter() - t0
     ne_final = (lev * _to_full(*st[ref_w], ref_w, Z)).sum(0)
     res = {"workload": f"laser2d_1024x1024_Z18_full_pulse_{mesh.steps}_steps_f64",
-           "reference": f"w={ref_w} window, shift threshold {ref_eps}", "eps": eps, "sampled_every": every,
-           "seconds": el, "gradual_onset_cells": int(gradual.sum()), "strong_start_cells": int((~gradual).sum()),
+           "reference": f"full chain: w = Z = {ref_w} (one wavefront per cell), no shift", "eps": eps,
+           "sampled_every": every, "seconds": el, "full_chain_seconds": ref_s,
+           "full_chain_us_per_step": ref_s / mesh.steps * 1e6, "gradual_onset_cells": int(gradual.sum()), "strong_start_cells": int((~gradual).sum()),
            "final_mean_charge": {"max": float(ne_final.max()), "mean": float(ne_final.mean())}}
 
     def stats(v):
@@ -450,6 +459,73 @@ def window_study(ak, mesh, eps, widths=(2, 3, 4), ref_w=8, ref_eps=1e-12, every=
                                for name, v in ne_v.items()}
     log("[study] orbital variants, final mesh-mean charge: " +
         ", ".join(f"{k} {v['mesh_mean_charge']:.4f}" for k, v in res["orbital_variants"].items()))
+    gas.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, sample_cells=1 << 20, seed=11):
+    """Full-vs-reduced study on the 3D mesh (256 x 256 x 512 cells, 36 levels,
+    m averaged): FP64 windows of w = 2, 3, 4 rates against the full 36-level
+    chain (w = Z on the wide path, no shift), `steps` steps of the pulse from
+    t = 0; errors on a fixed random sample of cells every `every` steps
+    (max |dN_k| and the relative error of n_e = sum_k k N_k), the full-chain
+    step time on the whole mesh."""
+    import torch
+    from paper_2202_10647_amd import workloads as wl
+    Z = 36
+    gas = ak.Gas.from_table(wl.synthetic_gas(Z))
+    n = mesh.ncells
+    rng = np.random.default_rng(seed)
+    idx = torch.from_numpy(np.sort(rng.choice(n, min(sample_cells, n), replace=False))).cuda()
+    lev = torch.arange(Z + 1, dtype=torch.float64, device="cuda")[:, None]
+    ws = tuple(widths) + (Z,)
+    st = {}
+    for w in ws:
+        P = torch.zeros((w + 1, n), dtype=torch.float64, device="cuda")
+        P[0] = 1.0
+        st[w] = (P, torch.zeros(n, dtype=torch.uint8, device="cuda"))
+    dmax = {w: torch.zeros(idx.numel(), dtype=torch.float64, device="cuda") for w in widths}
+    nemax = {w: torch.zeros(idx.numel(), dtype=torch.float64, device="cuda") for w in widths}
+    ref_s = 0.0
+    t0 = time.perf_counter()
+    for t in range(steps):
+        E = mesh.field_torch(t, "cuda", torch.float64)
+        for w in ws:
+            if w == Z:
+                torch.cuda.synchronize()
+                tr = time.perf_counter()
+            ak.ionize_step(gas, E, mesh.dt, *st[w], w=w, eps=0.0 if w == Z else eps)
+            if w == Z:
+                torch.cuda.synchronize()
+                ref_s += time.perf_counter() - tr
+        if t % every == 0 or t == steps - 1:
+            ref = st[Z][0][:, idx]
+            ne_ref = (lev * ref).sum(0)
+            for w in widths:
+                full = _to_full(st[w][0][:, idx], st[w][1][idx], w, Z)
+                dmax[w] = torch.maximum(dmax[w], (full - ref).abs().amax(dim=0))
+                ne = (lev * full).sum(0)
+                nemax[w] = torch.maximum(nemax[w], torch.where(ne_ref > 1e-3, (ne - ne_ref).abs() / ne_ref,
+                                                               torch.zeros_like(ne)))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ne_final = (lev * st[Z][0][:, idx]).sum(0)
+    res = {"workload": f"laser3d_256x256x512_Z36mavg_{steps}_steps_from_t0_f64",
+           "reference": "full chain: w = Z = 36 (one wavefront per cell), no shift", "eps": eps,
+           "sampled_cells": int(idx.numel()), "sampled_every": every, "seconds": el,
+           "full_chain_seconds": ref_s, "full_chain_us_per_step": ref_s / steps * 1e6,
+           "final_mean_charge_sample": {"max": float(ne_final.max()), "mean": float(ne_final.mean())}}
+    for w in widths:
+        d, e = dmax[w], nemax[w]
+        res[f"w{w}"] = {"max_abs_dN": float(d.max()), "p99_9_abs_dN": float(torch.quantile(d.float(), 0.999)),
+                        "frac_cells_above_1e-4": float((d > 1e-4).double().mean()),
+                        "max_rel_err_ne": float(e.max()), "p99_9_rel_err_ne": float(torch.quantile(e.float(), 0.999))}
+        log(f"[study3d] w={w}: max |dN| {res[f'w{w}']['max_abs_dN']:.2e} (p99.9 {res[f'w{w}']['p99_9_abs_dN']:.1e}),"
+            f" max rel n_e error {res[f'w{w}']['max_rel_err_ne']:.2e}")
+    log(f"[study3d] full 36-level chain: {res['full_chain_us_per_step']:.0f} us/step on {n} cells; "
+        f"final mean charge (sample) {res['final_mean_charge_sample']['mean']:.3f}")
+    del st, dmax, nemax
     gas.close()
     torch.cuda.empty_cache()
     return res
@@ -699,6 +775,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-subcycle", action="store_true")
     ap.add_argument("--no-study", action="store_true")
+    ap.add_argument("--study3d-steps", type=int, default=500, help="0 skips the 3D full-vs-reduced study")
     ap.add_argument("--surrogate-steps", type=int, default=40)
     ap.add_argument("--surrogate-train-iters", type=int, default=24000)
     args = ap.parse_args()
@@ -751,6 +828,9 @@ def main():
     parity = None if args.no_parity else parity_check(adkion, oracle, gas, spec, mesh, w, eps, 1000, 2024)
     subcycle = None if args.no_subcycle else subcycle_measure(adkion, oracle, gas, spec, mesh, w, eps, 1000, 2025)
     study = None if args.no_study else window_study(adkion, mesh, eps)
+    study3d = None
+    if not args.no_study and args.study3d_steps > 0:
+        study3d = window_study_3d(adkion, wl.mesh_3d(), eps, args.study3d_steps)
     mesh3d = surrogate = None
     if not (args.no_mesh3d and args.no_surrogate):
         g36 = wl.synthetic_gas(36)
@@ -807,6 +887,7 @@ def main():
         "surrogate": surrogate,
         "subcycled_baseline": subcycle,
         "window_study": study,
+        "window_study_3d": study3d,
         "cpu_baseline": cpu,
     }
     gas.close()

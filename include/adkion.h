@@ -45,6 +45,7 @@ enum {
 
 #define ADK_MAX_Z 64     /* largest number of ionization levels of a gas        */
 #define ADK_MAX_W 8      /* widest window: active rates per cell (populations w+1) */
+#define ADK_MAX_WIDE_W 63 /* widest window of ionize_step (w > ADK_MAX_W: one wavefront per cell) */
 #define ADK_M_AVERAGE -1 /* projection code: average the rate over m = -l..l     */
 
 /* Physical constants of Eq. (1) (Sec. 2, text after Eq. (1)). */
@@ -83,7 +84,7 @@ typedef enum { ADK_LAYOUT_COMPACT = 0, ADK_LAYOUT_FULL = 1 } adk_layout;
  * step, while lo < Z and N_lo < eps, N_lo is added to N_lo+1, set to 0, and lo
  * is incremented (comparison in double). */
 typedef struct {
-    int32_t w;       /* 1 <= w <= min(Z, ADK_MAX_W)       */
+    int32_t w;       /* 1 <= w <= min(Z, ADK_MAX_WIDE_W)  */
     double eps;      /* >= 0 and finite; 0 disables shifts */
     adk_layout layout;
     adk_prec prec;
@@ -143,9 +144,12 @@ int adk_chain_advance(int32_t w, const void *W, int64_t ncells, double dt, void 
  * E[ncells], pops (see adk_layout) and lo[ncells] (uint8, lowest window level
  * p; values above Z are read as Z) are device arrays; pops and lo are updated
  * in place.  ncells == 0 is a no-op.  Non-finite E gives non-finite
- * populations in that cell only.  Errors: ADK_EINVAL (null pointers with
- * ncells > 0, ncells < 0, dt <= 0 or non-finite, eps < 0 or non-finite, bad
- * enums), ADK_ERANGE (w outside [1, min(Z, ADK_MAX_W)]). */
+ * populations in that cell only.  Windows up to ADK_MAX_W rates run one cell
+ * per lane; wider windows (up to ADK_MAX_WIDE_W, so w = Z with eps = 0 is the
+ * full chain of Sec. 3's comparison for Z <= 63) run one cell per wavefront,
+ * in double arithmetic for either precision.  Errors: ADK_EINVAL (null
+ * pointers with ncells > 0, ncells < 0, dt <= 0 or non-finite, eps < 0 or
+ * non-finite, bad enums), ADK_ERANGE (w outside [1, min(Z, ADK_MAX_WIDE_W)]). */
 int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops,
                 uint8_t *lo, const adk_window *win, hipStream_t stream);
 
@@ -156,8 +160,8 @@ int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, vo
  * the change of the mean charge per atom (lo' and N' after the step, lo read
  * as min(lo, Z)).  dne[ncells] is a device array of the precision's type,
  * computed in double from the same registers as the populations.  Errors: as
- * ionize_step, and ADK_EINVAL for a layout other than ADK_LAYOUT_COMPACT or
- * a null dne with ncells > 0. */
+ * ionize_step (but w at most ADK_MAX_W), and ADK_EINVAL for a layout other
+ * than ADK_LAYOUT_COMPACT or a null dne with ncells > 0. */
 int ionize_step_yield(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops,
                       uint8_t *lo, const adk_window *win, void *dne, hipStream_t stream);
 

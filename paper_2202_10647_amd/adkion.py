@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libadkion.so")
 ADK_OK, ADK_EINVAL, ADK_ERANGE, ADK_EDEVICE, ADK_ENOMEM = 0, -1, -2, -3, -4
 ADK_F64, ADK_MIXED = 0, 1
 ADK_LAYOUT_COMPACT, ADK_LAYOUT_FULL = 0, 1
-ADK_MAX_Z, ADK_MAX_W, ADK_M_AVERAGE = 64, 8, -1
+ADK_MAX_Z, ADK_MAX_W, ADK_MAX_WIDE_W, ADK_M_AVERAGE = 64, 8, 63, -1
 
 #: every function the header declares (checked by the CPU test suite)
 EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "adk_gas_destroy",

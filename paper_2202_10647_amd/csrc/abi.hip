@@ -218,9 +218,10 @@ int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, vo
     if (!(win->eps >= 0.0) || !std::isfinite(win->eps)) return ADK_EINVAL;
     if (!valid_prec(win->prec)) return ADK_EINVAL;
     if (win->layout != ADK_LAYOUT_COMPACT && win->layout != ADK_LAYOUT_FULL) return ADK_EINVAL;
-    if (win->w < 1 || win->w > ADK_MAX_W || win->w > gas->Z) return ADK_ERANGE;
+    if (win->w < 1 || win->w > ADK_MAX_WIDE_W || win->w > gas->Z) return ADK_ERANGE;
     if (ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
     if (ncells == 0) return ADK_OK;
+    if (win->w > ADK_MAX_W) return status_of(adk_step_wide(gas, E, ncells, dt, pops, lo, win, stream));
     const hipError_t e = (win->prec == ADK_F64 ? kStepF64 : kStepMixed)[win->w](gas, E, ncells, dt, pops, lo,
                                                                                win, nullptr, stream);
     return status_of(e);

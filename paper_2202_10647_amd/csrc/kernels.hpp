@@ -567,6 +567,10 @@ using AdvanceFn = hipError_t (*)(const void *, int64_t, double, void *, hipStrea
 ADK_DECLARE_PREC(f64)
 ADK_DECLARE_PREC(mixed)
 
+// ionize_step for windows wider than ADK_MAX_W (wide.hip).
+hipError_t adk_step_wide(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,
+                         const adk_window *win, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Batched step over cells of several gases and window widths (plan).
 // Cells are grouped by (gas, w) on the host; a tile is up to CPL*kBlock cells

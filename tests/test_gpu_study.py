@@ -1,7 +1,8 @@
 """Full-vs-reduced window study on the GPU (the synthetic stand-in for the
 paper's Fig. 2b/2c comparison of the 4-level system with the full system):
-the wide window that bench.py's study uses as its reference tracks the
-oracle's full chain along a pulse trajectory, and the reduced windows order
+the GPU full chain (w = Z, no shift) that bench.py's study uses as its
+reference tracks the oracle's full chain along a pulse trajectory, as does
+a w = 8 window with a 1e-12 shift threshold, and the reduced windows order
 as the paper reports (3 levels clearly worse than 4)."""
 import numpy as np
 import pytest
@@ -11,7 +12,7 @@ from paper_2202_10647_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def test_wide_window_tracks_full_chain_and_reduced_windows_order(orc):
+def test_full_chain_tracks_oracle_and_reduced_windows_order(orc):
     import torch
     from paper_2202_10647_amd import adkion as ak
     Z = 18
@@ -22,7 +23,7 @@ def test_wide_window_tracks_full_chain_and_reduced_windows_order(orc):
     idx = np.array([512 * 1024 + 300, 540 * 1024 + 300])
     steps = 1200
     pf, lf = wl.neutral_state(idx.size, Z + 1)
-    runs = {(8, 1e-12): None, (4, 1e-8): None, (3, 1e-8): None, (2, 1e-8): None}
+    runs = {(Z, 0.0): None, (8, 1e-12): None, (4, 1e-8): None, (3, 1e-8): None, (2, 1e-8): None}
     for key in runs:
         w = key[0]
         P = torch.zeros((w + 1, idx.size), dtype=torch.float64, device="cuda")
@@ -42,6 +43,8 @@ def test_wide_window_tracks_full_chain_and_reduced_windows_order(orc):
                 full[k] = p[k - l[c], c]
                 worst[(w, eps)] = max(worst[(w, eps)], np.max(np.abs(full - pf[:, c])))
     assert lf.max() == 0 and runs[(3, 1e-8)][1].min() >= 8  # the pulse ionized past level 8
+    assert worst[(Z, 0.0)] < 1e-11, worst
+    assert runs[(Z, 0.0)][1].max() == 0  # no shift of the full chain
     assert worst[(8, 1e-12)] < 1e-10, worst
     assert worst[(4, 1e-8)] < 1e-4, worst
     assert worst[(2, 1e-8)] > 10 * worst[(3, 1e-8)] > 10 * worst[(4, 1e-8)], worst

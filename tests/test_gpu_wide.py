@@ -1,0 +1,173 @@
+"""Wide windows (w > 8, up to the whole chain): one wavefront per cell,
+through the C ABI, against the oracle from identical input bits.
+
+The tables of the wide path use the FP64 thresholds of the narrow path's
+windows of up to eight rates; tolerances as for every ionize_step test:
+FP64 <= 1e-12, mixed (float storage, double arithmetic) <= 1e-6, window
+index bit-exact."""
+import numpy as np
+import pytest
+
+from paper_2202_10647_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "mixed": 1e-6}
+DT = 1.334e-16
+
+
+@pytest.fixture(scope="module")
+def env(orc):
+    import torch
+    from paper_2202_10647_amd import adkion
+    assert torch.cuda.is_available()
+    cache = {}
+
+    def gas(Z):
+        if Z not in cache:
+            g = wl.synthetic_gas(Z)
+            cache[Z] = (adkion.Gas.from_table(g), orc.GasSpec(g.U, g.l, g.m))
+        return cache[Z]
+    return torch, adkion, gas
+
+
+def npdt(prec):
+    return np.float64 if prec == "f64" else np.float32
+
+
+def to_full(comp, lo, Z, w):
+    pops = np.zeros((Z + 1, comp.shape[1]))
+    for s in range(w + 1):
+        lev = lo.astype(np.int64) + s
+        ok = lev <= Z
+        pops[lev[ok], np.nonzero(ok)[0]] = comp[s, ok]
+    return pops
+
+
+def run(torch, ak, gas, E, pops, lo, w, eps, layout):
+    Pt = torch.from_numpy(np.ascontiguousarray(pops)).cuda()
+    Lt = torch.from_numpy(np.ascontiguousarray(lo)).cuda()
+    ak.ionize_step(gas, torch.from_numpy(np.ascontiguousarray(E)).cuda(), DT, Pt, Lt, w=w, eps=eps, layout=layout)
+    torch.cuda.synchronize()
+    return Pt.cpu().numpy().astype(np.float64), Lt.cpu().numpy()
+
+
+def check(out, ref, prec, what):
+    finite = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(out), finite), f"{what}: non-finite pattern differs"
+    err = float(np.max(np.abs(out[finite] - ref[finite]))) if finite.any() else 0.0
+    assert err <= TOL[prec], f"{what}: max |dN| = {err:.3e} > {TOL[prec]:.0e}"
+    return err
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("layout", ["compact", "full"])
+@pytest.mark.parametrize("Z,w", [(18, 9), (18, 13), (18, 18), (36, 20), (36, 36), (54, 54)])
+def test_wide_random_window_states(env, orc, prec, layout, Z, w):
+    """Random states at every window position (shifts, exact zeros, slots
+    past Z), E over 0, negative and [1, 2e4] GV/m, a non-finite field."""
+    torch, ak, gas_of = env
+    gas, spec = gas_of(Z)
+    n = 2 * 64 + 45
+    comp, lo = wl.random_window_state(n, Z, w, seed=7 * Z + w)
+    E = wl.loguniform_field(n, 1.0, 20000.0, seed=Z + 3 * w)
+    E[::13] *= -1
+    E[::23] = 0.0
+    E[5] = np.inf
+    pops = comp if layout == "compact" else to_full(comp, lo, Z, w)
+    pops = pops.astype(npdt(prec))
+    E = E.astype(npdt(prec))
+    out, lo2 = run(torch, ak, gas, E, pops, lo, w, 1e-8, layout)
+    ref, rlo = orc.ionize_step(spec, E.astype(np.float64), DT, pops.astype(np.float64), lo, w, 1e-8,
+                               layout=0 if layout == "compact" else 1)
+    assert np.array_equal(lo2, rlo)
+    check(out, ref, prec, f"Z={Z} w={w} {layout} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("Z", [18, 36])
+def test_full_chain_from_neutral_and_mixed_states(env, orc, prec, Z):
+    """w = Z, eps = 0: the full chain (no window, no shift) over several
+    steps of strong fields, from neutral cells and from states spread over
+    many charge states, full layout; populations sum to one."""
+    torch, ak, gas_of = env
+    gas, spec = gas_of(Z)
+    n = 3 * 64 + 11
+    rng = np.random.default_rng(Z)
+    pops = np.zeros((Z + 1, n))
+    pops[0, : n // 2] = 1.0
+    spread = rng.exponential(size=(Z + 1, n - n // 2))
+    spread[rng.random(spread.shape) < 0.3] = 0.0
+    spread[0] += 1e-3
+    pops[:, n // 2:] = spread / spread.sum(axis=0)
+    pops = pops.astype(npdt(prec))
+    lo = np.zeros(n, np.uint8)
+    Pt = torch.from_numpy(pops).cuda()
+    Lt = torch.from_numpy(lo).cuda()
+    ref, rlo = pops.astype(np.float64), lo.copy()
+    for step in range(3):
+        E = wl.loguniform_field(n, 100.0, 10000.0, seed=100 * Z + step).astype(npdt(prec))
+        ak.ionize_step(gas, torch.from_numpy(E).cuda(), DT, Pt, Lt, w=Z, eps=0.0, layout="full")
+        ref, rlo = orc.ionize_step(spec, E.astype(np.float64), DT, ref, rlo, Z, 0.0, layout=1)
+        torch.cuda.synchronize()
+        out = Pt.cpu().numpy().astype(np.float64)
+        assert np.array_equal(Lt.cpu().numpy(), rlo)
+        check(out, ref, prec, f"full chain Z={Z} step {step}")
+        if prec == "mixed":
+            # keep both sides on the same float inputs
+            ref = out.copy()
+    out = Pt.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(out.sum(axis=0) - 1.0)) < (1e-12 if prec == "f64" else 1e-5)
+    assert out.min() >= 0.0
+
+
+def test_wide_errors(env, orc):
+    """w beyond the gas or the limit, and the yield form past w = 8, are
+    rejected with ADK_ERANGE before any launch."""
+    torch, ak, gas_of = env
+    gas, spec = gas_of(54)
+    n = 64
+    E = torch.ones(n, dtype=torch.float64, device="cuda") * 1000.0
+    P = torch.zeros((65, n), dtype=torch.float64, device="cuda")
+    L = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ak.AdkError) as e:
+        ak.ionize_step(gas, E, DT, P, L, w=64)
+    assert e.value.status == ak.ADK_ERANGE
+    g7, _ = gas_of(7)
+    with pytest.raises(ak.AdkError) as e:
+        ak.ionize_step(g7, E, DT, torch.zeros((10, n), dtype=torch.float64, device="cuda"), L, w=9)
+    assert e.value.status == ak.ADK_ERANGE
+    with pytest.raises(ak.AdkError) as e:
+        ak.ionize_step(gas, E, DT, torch.zeros((10, n), dtype=torch.float64, device="cuda"), L, w=9,
+                       dne=torch.zeros(n, dtype=torch.float64, device="cuda"))
+    assert e.value.status == ak.ADK_ERANGE
+
+
+def test_wide_graph_replay(env, orc):
+    """Five w = 18 steps captured in a HIP graph, replayed three times with
+    eager work between replays: bitwise equal to eager launches."""
+    torch, ak, gas_of = env
+    gas, spec = gas_of(18)
+    n = 1000
+    comp, lo = wl.random_window_state(n, 18, 18, seed=3)
+    P0 = torch.from_numpy(comp).cuda()
+    L0 = torch.from_numpy(lo).cuda()
+    fields = torch.stack([torch.from_numpy(wl.loguniform_field(n, 10.0, 5000.0, seed=s)) for s in range(5)]).cuda()
+    P, L = P0.clone(), L0.clone()
+    for s in range(5):
+        ak.ionize_step(gas, fields[s], DT, P, L, w=18, eps=1e-8)
+    torch.cuda.synchronize()
+    want_p, want_l = P.clone(), L.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for s in range(5):
+            ak.ionize_step(gas, fields[s], DT, P, L, w=18, eps=1e-8)
+    for rep in range(3):
+        P.copy_(P0)
+        L.copy_(L0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(P, want_p) and torch.equal(L, want_l), rep
+        _ = float(P.sum().item())
+    del g
