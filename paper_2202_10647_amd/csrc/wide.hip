@@ -151,6 +151,7 @@ __device__ __forceinline__ double wave_sum(double v)
 __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, double *mm, double *Nb, int *cid,
                             int *pos, double *D, double *V)
 {
+    double *ls = (double *)(pos + 64);  // log of the sorted rates
     const int lane = threadIdx.x;
     // rank of x_k among the window's rates (ties by chain index)
     int rank = 0;
@@ -162,6 +163,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
         s[rank] = x;
         e[rank] = exp(-x);
         mm[rank] = fmax(1.0, x);
+        ls[rank] = log(x);
         cid[rank] = lane;
         pos[lane] = rank;
     }
@@ -201,7 +203,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
                 const double xi = s[pi];
                 Rp *= fmin(xi, 1.0);
                 if (Rp == 0.0) break;  // every lower source reaches row j through a zero rate
-                lb += log(xi) - log((double)(j - i));
+                lb += ls[pi] - kLogFact.v[j - i] + kLogFact.v[j - i - 1];  // log x_i - log (j-i)
             }
             A = min(A, pi);
             B = max(B, pi);
@@ -339,8 +341,8 @@ __global__ __launch_bounds__(kWideBlock) void wide_step_kernel(StepArgs a, int W
     extern __shared__ __align__(16) double wl[];
     double *s = wl, *e = wl + 64, *mm = wl + 128, *Nb = wl + 192;
     int *cid = (int *)(wl + 256);
-    int *pos = cid + 64;
-    double *D = wl + 320;
+    int *pos = cid + 64;  // followed by 64 doubles of log rates (chain_sub)
+    double *D = wl + 384;
     double *V = D + W * (W + 1) / 2;
     stage_coefficients(sc, a.tab, a.ln_dt);
     const double *slog = sc + kCoefRows * kCoefStride;
@@ -376,7 +378,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_step_kernel(StepArgs a, int W
 template <class R>
 size_t wide_lds_bytes(int W)
 {
-    return sizeof(double) * (320 + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * kWideBlock);
+    return sizeof(double) * (384 + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * kWideBlock);
 }
 
 template <class R>
