@@ -35,6 +35,16 @@ int grid_for(int64_t n)
     return (int)(blocks < cap ? blocks : cap);
 }
 
+ChunkOrder chunk_order(int64_t n)
+{
+    ChunkOrder o;
+    o.chunks = n / kBlock;
+    o.bits = 0;
+    if (o.chunks >= 2 && o.chunks <= ((int64_t)1 << 31))
+        while (((int64_t)1 << o.bits) < o.chunks) ++o.bits;
+    return o;
+}
+
 StepArgs step_args(const adk_gas *g, double dt, double eps)
 {
     StepArgs a;

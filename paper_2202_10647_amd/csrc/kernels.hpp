@@ -49,10 +49,45 @@ struct StepArgs {
     double E_cut;        // below this |E| every rate of the gas is < 1e-30 per step
 };
 
+// Order in which a grid-stride kernel visits the chunks of kBlock cells: a
+// permutation of the full chunks [0, chunks) (the last, partial chunk stays
+// in place).  Chunk v goes to the first value below `chunks` on the orbit of
+// v under Q = (odd multiply, xor-shift, odd multiply, xor-shift, bit
+// reversal) on k bits, 2^k >= chunks: each step is a permutation of
+// [0, 2^k), and the orbit is walked until it is back in range (cycle
+// walking).  The dispatcher deals consecutive workgroups out to the XCDs and
+// their CUs in turn; in cell order a field that is strong in one slab of the
+// mesh (a laser pulse, whose z range falls on the same chunk residues in
+// every row) lands on the few XCDs and CUs whose workgroups hold that slab,
+// while the scattered order loads them alike.  Measured on the laser meshes
+// (1M and 33.5M cells, mixed precision): 14.5 -> 10.8 us and 330 -> 275 us
+// per step.
+struct ChunkOrder {
+    int64_t chunks;
+    int bits;
+};
+
+__device__ __forceinline__ int64_t chunk_place(int64_t v, const ChunkOrder &o)
+{
+    if (v >= o.chunks || o.bits == 0) return v;
+    const uint32_t mask = o.bits >= 32 ? 0xffffffffu : ((1u << o.bits) - 1u);
+    const int sh = (o.bits + 1) / 2;
+    uint32_t x = (uint32_t)v;
+    do {
+        x = (x * 0x9E3779B9u) & mask;
+        x ^= x >> sh;
+        x = (x * 0x85EBCA6Bu) & mask;
+        x ^= x >> sh;
+        x = __builtin_bitreverse32(x) >> (32 - o.bits);
+    } while ((int64_t)x >= o.chunks);
+    return (int64_t)x;
+}
+
 // Host helpers (abi.hip).
 int num_cus();
 int grid_for(int64_t n);
 StepArgs step_args(const adk_gas *g, double dt, double eps);
+ChunkOrder chunk_order(int64_t n);
 
 // log2 of a positive finite double v: v = m 2^k with m in [1/2, 1); the top
 // six fraction bits of m select c_j ~ 1/m from the table, r = m c_j - 1 is
@@ -266,7 +301,8 @@ __device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &c
 // dne[c] = sum_s (lo' + s) N'_s - sum_s (lo + s) N_s: the change of the mean
 // charge (electrons released per atom), from the same registers.
 template <class P, int W, bool YIELD>
-__global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const typename P::real *__restrict__ E,
+__global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, ChunkOrder ord,
+                                                              const typename P::real *__restrict__ E,
                                                               typename P::real *__restrict__ pops,
                                                               uint8_t *__restrict__ lo, int64_t n,
                                                               typename P::real *__restrict__ dne)
@@ -275,18 +311,26 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const 
     __shared__ double sc[kDevTableLen];
     const double *slog = sc + kCoefRows * kCoefStride;
     const int Z = a.Z;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // workgroup b takes chunks b, b + grid, ... of kBlock cells, each mapped
+    // to a scattered place of the mesh (ChunkOrder)
+    const int64_t nv = (n + kBlock - 1) / kBlock;
+    int64_t v = blockIdx.x;
+    int64_t c = chunk_place(v, ord) * kBlock + threadIdx.x;
     CellLoad<R, W> nxt;
-    if (c < n) load_cell(nxt, E, pops, lo, n, c);  // in flight while the table is staged
+    if (v < nv && c < n) load_cell(nxt, E, pops, lo, n, c);  // in flight while the table is staged
     stage_coefficients(sc, a.tab, a.ln_dt);
-    for (; c < n; c += stride) {
+    for (; v < nv; v += gridDim.x) {
+        const int64_t vn = v + gridDim.x;
+        const int64_t cn = vn < nv ? chunk_place(vn, ord) * kBlock + threadIdx.x : n;
         const CellLoad<R, W> cur = nxt;
-        if (c + stride < n) load_cell(nxt, E, pops, lo, n, c + stride);
+        if (cn < n) load_cell(nxt, E, pops, lo, n, cn);
+        const int64_t cc = c;
+        c = cn;
+        if (cc >= n) continue;
         const int p = cur.lo < Z ? cur.lo : Z;
         if (__all(p >= Z || (fabs((double)cur.E) < a.E_cut && (double)cur.N[0] >= a.eps))) {
-            if (p != cur.lo) lo[c] = (uint8_t)p;  // an index past Z is clamped
-            if (YIELD) dne[c] = R(0);
+            if (p != cur.lo) lo[cc] = (uint8_t)p;  // an index past Z is clamped
+            if (YIELD) dne[cc] = R(0);
             continue;
         }
         R o[W + 1];
@@ -294,9 +338,9 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const 
         step_cell_out<P, W>(cur, sc, slog, Z, a.has_poly != 0, a.eps, a.E_cut, o, l);
         static_for<0, W + 1>([&](auto ss) {
             constexpr int s = decltype(ss)::value;
-            pops[(int64_t)s * n + c] = o[s];
+            pops[(int64_t)s * n + cc] = o[s];
         });
-        lo[c] = (uint8_t)l;
+        lo[cc] = (uint8_t)l;
         if (YIELD) {
             double q0 = 0.0, q1 = 0.0;
             static_for<0, W + 1>([&](auto ss) {
@@ -304,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, const 
                 q0 = fma((double)(p + s), (double)cur.N[s], q0);
                 q1 = fma((double)(l + s), (double)o[s], q1);
             });
-            dne[c] = (R)(q1 - q0);
+            dne[cc] = (R)(q1 - q0);
         }
     }
 }
@@ -521,11 +565,11 @@ hipError_t launch_step(const adk_gas *g, const void *E, int64_t n, double dt, vo
         if (dne) {
             const int grid = resident_grid<step_compact_kernel<P, W, true>>(n);
             hipLaunchKernelGGL((step_compact_kernel<P, W, true>), dim3(grid), dim3(kBlock), 0, st, a,
-                               (const R *)E, (R *)pops, lo, n, (R *)dne);
+                               chunk_order(n), (const R *)E, (R *)pops, lo, n, (R *)dne);
         } else {
             const int grid = resident_grid<step_compact_kernel<P, W, false>>(n);
             hipLaunchKernelGGL((step_compact_kernel<P, W, false>), dim3(grid), dim3(kBlock), 0, st, a,
-                               (const R *)E, (R *)pops, lo, n, (R *)nullptr);
+                               chunk_order(n), (const R *)E, (R *)pops, lo, n, (R *)nullptr);
         }
     } else {
         const int grid = resident_grid<step_full_kernel<P, W>>(n);
