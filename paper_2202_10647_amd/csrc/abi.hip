@@ -35,10 +35,10 @@ int grid_for(int64_t n)
     return (int)(blocks < cap ? blocks : cap);
 }
 
-ChunkOrder chunk_order(int64_t n)
+ChunkOrder chunk_order(int64_t n, int64_t chunk)
 {
     ChunkOrder o;
-    o.chunks = n / kBlock;
+    o.chunks = n / chunk;
     o.bits = 0;
     if (o.chunks >= 2 && o.chunks <= ((int64_t)1 << 31))
         while (((int64_t)1 << o.bits) < o.chunks) ++o.bits;

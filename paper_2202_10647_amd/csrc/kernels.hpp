@@ -49,8 +49,9 @@ struct StepArgs {
     double E_cut;        // below this |E| every rate of the gas is < 1e-30 per step
 };
 
-// Order in which a grid-stride kernel visits the chunks of kBlock cells: a
-// permutation of the full chunks [0, chunks) (the last, partial chunk stays
+// Order in which a grid-stride kernel visits the chunks of its cells (kBlock
+// cells per chunk for the step kernel, one wavefront's 64 for the surrogate):
+// a permutation of the full chunks [0, chunks) (the last, partial chunk stays
 // in place).  Chunk v goes to the first value below `chunks` on the orbit of
 // v under Q = (odd multiply, xor-shift, odd multiply, xor-shift, bit
 // reversal) on k bits, 2^k >= chunks: each step is a permutation of
@@ -87,7 +88,7 @@ __device__ __forceinline__ int64_t chunk_place(int64_t v, const ChunkOrder &o)
 int num_cus();
 int grid_for(int64_t n);
 StepArgs step_args(const adk_gas *g, double dt, double eps);
-ChunkOrder chunk_order(int64_t n);
+ChunkOrder chunk_order(int64_t n, int64_t chunk = kBlock);
 
 // log2 of a positive finite double v: v = m 2^k with m in [1/2, 1); the top
 // six fraction bits of m select c_j ~ 1/m from the table, r = m c_j - 1 is
@@ -541,8 +542,14 @@ StepArgs step_args(const adk_gas *g, double dt, double eps);
 // from the compiled resource usage), no more groups than cells need.
 // (The occupancy is cached per kernel: the template parameter is the kernel
 // itself, so kernels of one signature do not share the cache.)
+//
+// With chunks_per_group > 0 the grid grows beyond the resident slots to about
+// that many kBlock-cell chunks per workgroup: the surplus workgroups start as
+// earlier ones retire, so a CU whose chunks happened to hold the expensive
+// (ionizing) cells takes fewer of them, while each workgroup still loops over
+// several chunks (one-ahead prefetch, table staged once per chunk run).
 template <auto Kernel>
-int resident_grid(int64_t n)
+int resident_grid(int64_t n, int64_t chunks_per_group = 0)
 {
     static int per_cu = 0;
     if (per_cu <= 0) {
@@ -551,9 +558,21 @@ int resident_grid(int64_t n)
         per_cu = b;
     }
     const int64_t need = (n + kBlock - 1) / kBlock;
-    const int64_t cap = (int64_t)num_cus() * per_cu;
-    return (int)(need < cap ? need : cap);
+    int64_t grid = (int64_t)num_cus() * per_cu;
+    if (chunks_per_group > 0) {
+        const int64_t spread = (need + chunks_per_group - 1) / chunks_per_group;
+        grid = spread > grid ? spread : grid;
+    }
+    return (int)(need < grid ? need : grid);
 }
+
+// Chunks per workgroup of the compact step kernel.  Measured on the 3D laser
+// mesh (33.5M cells = 131,072 chunks, 2048 resident workgroups): all resident
+// (64 chunks each) 273 us per step (mixed) / 566 us (FP64); 32 chunks 266 /
+// 521; 16 chunks 249 / 525; 8 chunks 244 / 517; 4 chunks 250 / 533; one chunk
+// per workgroup 318 / 648.  Meshes of up to 8 x resident chunks (the 1M-cell
+// 2D mesh) keep the resident grid.
+constexpr int64_t kStepChunksPerGroup = 8;
 
 template <class P, int W>
 hipError_t launch_step(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,
@@ -563,11 +582,11 @@ hipError_t launch_step(const adk_gas *g, const void *E, int64_t n, double dt, vo
     const StepArgs a = step_args(g, dt, win->eps);
     if (win->layout == ADK_LAYOUT_COMPACT) {
         if (dne) {
-            const int grid = resident_grid<step_compact_kernel<P, W, true>>(n);
+            const int grid = resident_grid<step_compact_kernel<P, W, true>>(n, kStepChunksPerGroup);
             hipLaunchKernelGGL((step_compact_kernel<P, W, true>), dim3(grid), dim3(kBlock), 0, st, a,
                                chunk_order(n), (const R *)E, (R *)pops, lo, n, (R *)dne);
         } else {
-            const int grid = resident_grid<step_compact_kernel<P, W, false>>(n);
+            const int grid = resident_grid<step_compact_kernel<P, W, false>>(n, kStepChunksPerGroup);
             hipLaunchKernelGGL((step_compact_kernel<P, W, false>), dim3(grid), dim3(kBlock), 0, st, a,
                                chunk_order(n), (const R *)E, (R *)pops, lo, n, (R *)nullptr);
         }
