@@ -229,11 +229,18 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
 
 /* One ionization step of every cell of the plan (same semantics per cell as
  * ionize_step with the cell's gas and width): one launch per launch group
- * (one workgroup per tile), in order, on stream.
+ * (one workgroup per tile).  The launch group with the most cells runs on
+ * stream; the others run on a stream of the plan that is forked from stream
+ * (an event recorded on stream) and joined back into it (stream waits on an
+ * event recorded after them), so the sparse groups overlap the dense one and
+ * the step as a whole is ordered on stream like a single launch.
  * E[ncells], pops[rows][ncells], lo[ncells] are device arrays of the plan's
  * precision.  Allocates nothing and never synchronises, so it may be captured
- * into a hipGraph; consecutive launches of one plan must be ordered (one
- * stream).  Errors: ADK_EINVAL (null plan or arrays, dt <= 0 or non-finite). */
+ * into a hipGraph (the fork and join become parallel branches); consecutive
+ * steps of one plan must be ordered (one stream), and one plan must not be
+ * stepped from several host threads at once (its side stream and events are
+ * shared).  Errors: ADK_EINVAL (null plan or arrays, dt <= 0 or non-finite),
+ * ADK_EDEVICE. */
 int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t *lo, hipStream_t stream);
 
 /* Host query of the plan's grouping and tuning.  ADK_EINVAL for NULL. */

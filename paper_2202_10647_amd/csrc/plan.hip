@@ -13,6 +13,14 @@
 // timed trials on scratch buffers unless the caller fixes it, and the choice
 // is cached per (device, problem, launch group) in the file named by the
 // ADK_TUNE_CACHE environment variable, when it is set.
+//
+// A step launches the largest launch group on the caller's stream and the
+// others on a side stream of the plan, forked from and joined back into the
+// caller's stream with events: the launch groups touch disjoint cells, and
+// the few, expensive cells of the sparse widths (a dopant with wide windows
+// and long chains leaves a launch of a few hundred workgroups, latency bound)
+// then run while the dense launch streams the bulk of the mesh through HBM.
+// Captured into a hipGraph the fork and join become parallel branches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,8 +63,11 @@ struct adk_plan {
     int ntiles = 0;
     int ngroups = 0;
     adk::PlanGroup group[adk::kPlanMaxW];
+    int main_group = 0;  // the launch group with the most cells (caller's stream)
     int32_t *d_perm = nullptr;
     adk::PlanTile *d_tiles = nullptr;
+    hipStream_t side = nullptr;  // the other launch groups (ngroups > 1)
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace adk {
@@ -411,8 +422,17 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
         }
         p->ntiles = (int)t.size();
         p->ngroups = (int)groups.size();
-        for (size_t i = 0; i < groups.size(); ++i) p->group[i] = groups[i];
-        if (!t.empty()) {
+        for (size_t i = 0; i < groups.size(); ++i) {
+            p->group[i] = groups[i];
+            if (groups[i].cells > groups[p->main_group].cells) p->main_group = (int)i;
+        }
+        if (p->ngroups > 1) {
+            e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+            if (e != hipSuccess) st = plan_status(e);
+        }
+        if (st == ADK_OK && !t.empty()) {
             e = hipMalloc((void **)&p->d_tiles, sizeof(PlanTile) * t.size());
             if (e == hipSuccess)
                 e = hipMemcpy(p->d_tiles, t.data(), sizeof(PlanTile) * t.size(), hipMemcpyHostToDevice);
@@ -432,14 +452,27 @@ int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t 
     if (!plan) return ADK_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
     if (plan->ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
-    for (int i = 0; i < plan->ngroups; ++i) {
+    auto launch = [&](int i, hipStream_t s) {
         const PlanGroup &grp = plan->group[i];
         const PlanArgs a = plan_args(plan, dt, grp.t0, grp.ntiles);
-        const hipError_t e = plan_fn(plan, grp.wmax, grp.cpl)(a, E, pops, lo, plan->ncells, plan->d_perm,
-                                                              plan->d_tiles, stream);
-        if (e != hipSuccess) return plan_status(e);
-    }
-    return ADK_OK;
+        return plan_fn(plan, grp.wmax, grp.cpl)(a, E, pops, lo, plan->ncells, plan->d_perm, plan->d_tiles, s);
+    };
+    if (plan->ngroups == 1) return plan_status(launch(0, stream));
+    if (plan->ngroups == 0) return ADK_OK;
+    // fork: the side stream starts after everything already on `stream`
+    hipError_t e = hipEventRecord(plan->fork, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->side, plan->fork, 0);
+    if (e != hipSuccess) return plan_status(e);
+    for (int i = 0; i < plan->ngroups && e == hipSuccess; ++i)
+        if (i != plan->main_group) e = launch(i, plan->side);
+    const hipError_t em = e == hipSuccess ? launch(plan->main_group, stream) : hipSuccess;
+    // join (also after a failed launch, so that `stream` never runs ahead of
+    // work already enqueued on the side stream)
+    hipError_t ej = hipEventRecord(plan->join, plan->side);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, plan->join, 0);
+    if (e != hipSuccess) return plan_status(e);
+    if (em != hipSuccess) return plan_status(em);
+    return plan_status(ej);
 }
 
 int adk_plan_get_info(const adk_plan *plan, adk_plan_info *info)
@@ -477,6 +510,18 @@ int adk_plan_destroy(adk_plan *plan)
     if (plan->d_perm) e = hipFree(plan->d_perm);
     if (plan->d_tiles) {
         const hipError_t e2 = hipFree(plan->d_tiles);
+        if (e == hipSuccess) e = e2;
+    }
+    if (plan->fork) {
+        const hipError_t e2 = hipEventDestroy(plan->fork);
+        if (e == hipSuccess) e = e2;
+    }
+    if (plan->join) {
+        const hipError_t e2 = hipEventDestroy(plan->join);
+        if (e == hipSuccess) e = e2;
+    }
+    if (plan->side) {
+        const hipError_t e2 = hipStreamDestroy(plan->side);
         if (e == hipSuccess) e = e2;
     }
     delete plan;

@@ -128,13 +128,17 @@ def test_plan_launch_groups(env, orc, prec):
     plan.close()
 
 
-def test_plan_graph_replay(env, orc):
+@pytest.mark.parametrize("n,nlaunches", [(30000, 1), (600000, 2)])
+def test_plan_graph_replay(env, orc, n, nlaunches):
     """Eight plan steps captured in one HIP graph, replayed three times with
-    eager work in between: bitwise equal to eager launches."""
+    eager work in between: bitwise equal to eager launches.  With two launch
+    groups (a solo w = 1 group of the host gas and one shared group of the
+    dopants) each step forks the dopant launch onto the plan's side stream and
+    joins it back, captured as parallel branches."""
     torch, ak, gases, specs = env
-    n = 30000
-    cell_gas, cell_w = wl.batched_cells(n, seed=3, dopant_fraction=0.2)
+    cell_gas, cell_w = wl.batched_cells(n, seed=3, dopant_fraction=0.2 if n < 100000 else 0.05)
     plan = ak.Plan(gases, cell_gas, cell_w, prec="mixed", cells_per_lane=2)
+    assert plan.info["nlaunches"] == nlaunches
     rows = plan.info["rows"]
     pops, lo = plan_state(cell_gas, cell_w, rows, seed=5)
     P0 = torch.from_numpy(pops.astype(np.float32)).cuda()
