@@ -560,7 +560,8 @@ int resident_grid(int64_t n, int64_t chunks_per_group = 0)
     const int64_t need = (n + kBlock - 1) / kBlock;
     int64_t grid = (int64_t)num_cus() * per_cu;
     if (chunks_per_group > 0) {
-        const int64_t spread = (need + chunks_per_group - 1) / chunks_per_group;
+        int64_t spread = (need + chunks_per_group - 1) / chunks_per_group;
+        spread = spread < ((int64_t)1 << 30) ? spread : ((int64_t)1 << 30);  // grid-stride covers the rest
         grid = spread > grid ? spread : grid;
     }
     return (int)(need < grid ? need : grid);

@@ -482,6 +482,44 @@ def test_electron_yield_matches_oracle(torch_dev, ak, orc, prec, Z, w):
     assert e.value.status == ak.ADK_EINVAL
 
 
+@pytest.mark.parametrize("prec", ["mixed", "f64"])
+@pytest.mark.parametrize("n", [5_000_003, 1_048_573, 300])
+def test_every_cell_stepped_exactly_once(torch_dev, ak, orc, prec, n):
+    """The same inputs in every cell of a ragged mesh: above eight 256-cell
+    chunks per resident workgroup (5M cells: the grid then exceeds the
+    resident workgroups), at the 1M-cell mesh's resident grid, and a single
+    partial chunk.  After one step (plain and with the electron yield) every
+    cell holds the same bits, and they match the oracle: a chunk that the
+    scattered visiting order or the grid skipped, or stepped twice, would
+    leave columns that differ."""
+    torch = torch_dev
+    Z, w = 18, 3
+    gas, spec = gas_pair(ak, orc, Z)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    cell = np.array([0.4, 0.3, 0.2, 0.1])
+    E0, lo0 = 250.0, 2
+    Et = torch.full((n,), E0, dtype=tdt, device="cuda")
+    for with_yield in (False, True):
+        P = torch.from_numpy(cell.astype(npdt(prec))).cuda()[:, None].repeat(1, n).contiguous()
+        L = torch.full((n,), lo0, dtype=torch.uint8, device="cuda")
+        dne = torch.full((n,), 7.0, dtype=tdt, device="cuda") if with_yield else None
+        ak.ionize_step(gas, Et, DT, P, L, w=w, eps=1e-8, dne=dne)
+        torch.cuda.synchronize()
+        assert bool(torch.all(P == P[:, :1])) and bool(torch.all(L == L[0])), f"cells differ ({prec}, n={n})"
+        ref, rlo = orc.ionize_step(spec, np.array([E0]), DT, cell.astype(npdt(prec)).astype(np.float64)[:, None],
+                                   np.array([lo0], np.uint8), w, 1e-8)
+        assert int(L[0]) == int(rlo[0])
+        compare(P[:, :1].cpu().numpy(), ref, prec, f"uniform mesh {prec} n={n}")
+        assert float(ref[0, 0]) < 0.4  # the field ionizes: a second step would change the bits
+        if with_yield:
+            assert bool(torch.all(dne == dne[0]))
+            y_ref = orc.electron_yield(cell.astype(npdt(prec)).astype(np.float64)[:, None], np.array([lo0], np.uint8),
+                                       ref, rlo, Z)
+            assert abs(float(dne[0]) - float(y_ref[0])) <= TOL[prec] * (w + 1) * (lo0 + w + 1)
+        del P, L, dne
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("Z,w,nsub", [(7, 1, 5), (18, 3, 64), (36, 3, 200), (54, 6, 32)])
 def test_subcycle_baseline_matches_oracle(torch_dev, ak, orc, Z, w, nsub):
     """The sub-cycled RK4 comparison baseline against its CPU reference on
