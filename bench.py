@@ -792,6 +792,64 @@ def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
     return res
 
 
+def measure_ceilings(ak):
+    """The device's own ceilings (best of 3 launches each): streaming copies
+    of 1, 2 and 4 GiB with the library's harness kernel and with the runtime's
+    device-to-device copy (HBM: the best of both), 50 passes of a 32 MiB copy
+    (resident in the 256 MB Infinity Cache), and chains of float FMA, double
+    FMA and float exp2 on every wavefront slot of the chip."""
+    import torch
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = float("inf")
+        for _ in range(3):
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            t = min(t, a.elapsed_time(b))
+        return t
+
+    res = {}
+    own, rt = 0.0, 0.0
+    for nb in (1 << 30, 2 << 30, 4 << 30):
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        own = max(own, 2 * nb / (best_ms(lambda: ak.ceiling_copy(dst, src)) * 1e-3) / 1e9)
+        rt = max(rt, 2 * nb / (best_ms(lambda: dst.copy_(src)) * 1e-3) / 1e9)
+        del src, dst
+    res["hbm_copy_gbps"] = max(own, rt)
+    res["hbm_copy_own_kernel_gbps"] = own
+    res["hbm_copy_runtime_gbps"] = rt
+    nb, reps = 32 << 20, 50
+    src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    t = best_ms(lambda: ak.ceiling_copy(dst, src, reps))
+    res["cache_copy_gbps"] = 2 * nb * reps / (t * 1e-3) / 1e9
+    del src, dst
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    lanes = cus * 32 * 64  # 32 wavefront slots per CU
+    iters = 4096
+    for kind, key, tdt, per in ((0, "valu_fp32_fma_tflops", torch.float32, 16), (1, "valu_fp64_fma_tflops",
+                                torch.float64, 16), (2, "valu_exp2_f32_tops", torch.float32, 8)):
+        out = torch.empty(lanes, dtype=tdt, device="cuda")
+        t = best_ms(lambda: ak.ceiling_valu(kind, iters, out))
+        assert bool(torch.all(out == 8)), key
+        res[key] = per * iters * lanes / (t * 1e-3) / 1e12
+    res["method"] = ("HBM: best of the library's 16-byte streaming copy and the runtime's device-to-device copy "
+                     "over 1, 2 and 4 GiB; cache: the library's copy of 32 MiB x 50 passes; VALU: "
+                     "8 dependent chains per lane of fma(x, 1, 0) or exp2(fma(x, 0, 0)) on every wavefront slot; "
+                     "best of 3 launches")
+    log(f"[ceilings] HBM copy {res['hbm_copy_gbps']:.0f} GB/s, cache copy {res['cache_copy_gbps']:.0f} GB/s, "
+        f"FP32 FMA {res['valu_fp32_fma_tflops']:.1f} TFLOP/s, FP64 FMA {res['valu_fp64_fma_tflops']:.1f} TFLOP/s, "
+        f"exp2 {res['valu_exp2_f32_tops']:.2f} T/s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -811,6 +869,7 @@ def main():
                     help="first copy this many MiB device to device three times (a kernel of known traffic "
                          "for calibrating profiler byte counters)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--no-subcycle", action="store_true")
     ap.add_argument("--no-study", action="store_true")
     ap.add_argument("--study3d-steps", type=int, default=500, help="0 skips the 3D full-vs-reduced study")
@@ -887,6 +946,11 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, spec, mesh, w, eps, 1000, 7,
                                                          args.cpu_seconds)
 
+    ceil = None if args.no_ceilings else measure_ceilings(adkion)
+    if ceil and mesh3d:
+        for prec in ("mixed", "f64"):
+            mesh3d[prec]["frac_of_measured_hbm_copy"] = mesh3d[prec]["achieved_gbps"] / ceil["hbm_copy_gbps"]
+
     m = res["mixed"]
     line = {
         "metric": METRIC,
@@ -912,7 +976,10 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_cell(w, "mixed") * n,
                      "kernel": f"step_compact_kernel<PolicyMixed,{w}>",
                      "bytes_per_cell": bytes_per_cell(w, "mixed"), "kernel_avg_us": m["kernel_ms"] * 1e3,
-                     "timing": "HIP events around one graph replay of the timed steps / steps"},
+                     "timing": "HIP events around one graph replay of the timed steps / steps",
+                     "frac_of_measured_hbm_copy": m["achieved_gbps"] / ceil["hbm_copy_gbps"] if ceil else None,
+                     "frac_of_measured_cache_copy": m["achieved_gbps"] / ceil["cache_copy_gbps"] if ceil else None},
+        "ceilings": ceil,
         "launch": "timed steps captured in one HIP graph; eager per-call launches reported as eager_ms_per_step",
         "eager_ms_per_step": m["eager_ms_per_step"],
         "fp64": {"value": res["f64"]["value"], "ms_per_step": res["f64"]["ms_per_step"],

@@ -260,6 +260,25 @@ int adk_field_hash(void *E, int64_t n, uint64_t seed, int64_t step, double E_lo,
                    hipStream_t stream);
 
 
+/* Hardware ceilings for the measurement harness (not part of the method).
+ * adk_ceiling_copy: reps passes of a 16-byte-per-lane streaming copy of
+ * `bytes` bytes from src to dst (device buffers, not overlapping; bytes a
+ * multiple of 16).  One pass over a large buffer measures the HBM bandwidth,
+ * several passes over a buffer that fits the 256 MB Infinity Cache its
+ * bandwidth; bytes moved = 2 x bytes x reps.
+ * adk_ceiling_valu: nlanes lanes (a multiple of 256) each run 8 independent
+ * chains of `iters` steps: kind 0 x <- fma(x, 1, 0) in float, kind 1 the
+ * same in double, kind 2 x <- exp2(fma(x, 0, 0)) in float; out[nlanes] (float
+ * for kinds 0 and 2, double for kind 1) receives 8 per lane.  Work per launch:
+ * 16 x iters x nlanes flops (kinds 0, 1) or 8 x iters x nlanes exp2 (kind 2).
+ * Both are asynchronous on stream.  Errors: ADK_EINVAL (null buffers, bytes
+ * not a multiple of 16 or negative, reps < 1, kind not 0..2, iters < 0,
+ * nlanes not a positive multiple of 256), ADK_ERANGE (more than 2^30
+ * workgroups), ADK_EDEVICE. */
+int adk_ceiling_copy(void *dst, const void *src, int64_t bytes, int64_t reps, hipStream_t stream);
+int adk_ceiling_valu(int32_t kind, int64_t iters, void *out, int64_t nlanes, hipStream_t stream);
+
+
 /* ---------------------------------------------------------------------------
  * Band-column surrogate.  The exact step (Eqs. (2)-(5)) moves the population
  * of a source level k to k, k+1, k+2, ...; within the reduced window of

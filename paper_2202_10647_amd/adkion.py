@@ -27,7 +27,8 @@ EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "a
            "adk_subcycle_step", "adk_plan_create",
            "adk_plan_step", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash", "adk_mlp_nparams",
            "adk_mlp_create", "adk_mlp_destroy", "adk_mlp_get_state", "adk_band_columns", "adk_mlp_forward",
-           "adk_mlp_loss_grad", "adk_mlp_train", "adk_mlp_save", "adk_mlp_load", "adk_surrogate_step")
+           "adk_mlp_loss_grad", "adk_mlp_train", "adk_mlp_save", "adk_mlp_load", "adk_surrogate_step",
+           "adk_ceiling_copy", "adk_ceiling_valu")
 ADK_PLAN_MAX_GAS, ADK_PLAN_MAX_W = 8, 6
 
 
@@ -120,6 +121,10 @@ def lib():
     L.adk_plan_destroy.argtypes = [vp]
     L.adk_field_hash.restype = ctypes.c_int
     L.adk_field_hash.argtypes = [vp, i64, ctypes.c_uint64, i64, dbl, dbl, ctypes.c_int, vp]
+    L.adk_ceiling_copy.restype = ctypes.c_int
+    L.adk_ceiling_copy.argtypes = [vp, vp, i64, i64, vp]
+    L.adk_ceiling_valu.restype = ctypes.c_int
+    L.adk_ceiling_valu.argtypes = [i32, i64, vp, i64, vp]
     L.adk_mlp_nparams.restype = i64
     L.adk_mlp_nparams.argtypes = [i32]
     L.adk_mlp_create.restype = ctypes.c_int
@@ -376,6 +381,29 @@ def field_hash(E, seed: int, step: int, E_lo: float = 10.0, E_hi: float = 5000.0
                               float(E_hi), _prec_of(E), _stream(stream))
     _check(st, "adk_field_hash")
     return E
+
+
+def ceiling_copy(dst, src, reps: int = 1, stream=None):
+    """Measurement harness: reps passes of a streaming copy src -> dst (device
+    tensors of equal byte size, a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise AdkError(ADK_EINVAL, "ceiling_copy: dst and src differ in size")
+    _check(lib().adk_ceiling_copy(_dev(dst, "dst"), _dev(src, "src"), nbytes, int(reps), _stream(stream)),
+           "adk_ceiling_copy")
+    return dst
+
+
+def ceiling_valu(kind: int, iters: int, out, stream=None):
+    """Measurement harness: 8 dependency chains of `iters` float FMAs (kind 0),
+    double FMAs (kind 1) or float exp2 (kind 2) per lane of out (one lane per
+    element; float32 for kinds 0 and 2, float64 for kind 1)."""
+    want = "float64" if kind == 1 else "float32"
+    if str(out.dtype).split(".")[-1] != want:
+        raise AdkError(ADK_EINVAL, f"ceiling_valu: kind {kind} writes {want}")
+    _check(lib().adk_ceiling_valu(int(kind), int(iters), _dev(out, "out"), out.numel(), _stream(stream)),
+           "adk_ceiling_valu")
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -216,3 +216,20 @@ def test_yield_host_validation(L):
     win = adkion._Window(3, 1e-8, adkion.ADK_LAYOUT_COMPACT, adkion.ADK_MIXED)
     assert L.ionize_step_yield(None, None, 4, 1e-16, None, None, ctypes.byref(win), None, None) == adkion.ADK_EINVAL
     assert L.ionize_step_yield(None, None, 0, 1e-16, None, None, None, None, None) == adkion.ADK_EINVAL
+
+
+def test_ceiling_host_validation(L):
+    """The measurement harness entry points reject bad arguments on the host
+    (no device call is made for any of these)."""
+    E = adkion.ADK_EINVAL
+    assert L.adk_ceiling_copy(None, None, 40, 1, None) == E      # not a multiple of 16
+    assert L.adk_ceiling_copy(None, None, 32, 1, None) == E      # null buffers
+    assert L.adk_ceiling_copy(None, None, 32, 0, None) == E      # reps < 1
+    assert L.adk_ceiling_copy(None, None, -16, 1, None) == E
+    assert L.adk_ceiling_copy(None, None, 0, 1, None) == adkion.ADK_OK  # nothing to copy
+    assert L.adk_ceiling_valu(3, 10, None, 256, None) == E       # kind
+    assert L.adk_ceiling_valu(0, 10, None, 256, None) == E       # null out
+    buf = ctypes.c_void_p(1)
+    assert L.adk_ceiling_valu(0, -1, buf, 256, None) == E        # iters < 0
+    assert L.adk_ceiling_valu(0, 10, buf, 100, None) == E        # lanes not a multiple of 256
+    assert L.adk_ceiling_valu(0, 10, buf, 0, None) == E
