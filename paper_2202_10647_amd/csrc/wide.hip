@@ -27,12 +27,21 @@
 //   * lane j accumulates row j, N'_j = sum_i T[j][i] N_i; the top slot takes
 //     what the rows leave (conservation).
 // All arithmetic is double; populations are stored in the precision's type.
+//
+// LDS bounds how many of these latency-bound wavefronts a CU holds, so it
+// goes to the cells only: each wavefront (one per workgroup) has its region
+// (sorted rates, the triangular table, and the per-lane columns of the hole
+// recurrence, W - 1 entries for each of the W lanes that use them), and the
+// rate coefficients and the log2 table, read once per cell, come from the
+// gas's device table through the caches instead of being staged.
 #include "kernels.hpp"
 
 namespace adk {
 namespace {
 
 constexpr int kWideBlock = 64;  // one wavefront per workgroup
+
+__device__ __forceinline__ int wide_lane() { return threadIdx.x; }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -107,11 +116,11 @@ constexpr double kWideClusterSpread = 2.0;  // largest spread any order's thresh
 // The partial sums accumulate in D[a][a+k] (written by this lane only), the
 // h values in this lane's column of hv; on return D holds ghat.
 __device__ void taylor_row(const double *s, const double *e, const double *mm, double *D, int a, int nmax,
-                           double *hv, int lane)
+                           double *hv, int lane, int vs)
 {
     const double sa = s[a];
     for (int k = 1; k <= nmax; ++k) {
-        hv[(k - 1) * kWideBlock + lane] = 1.0;
+        hv[(k - 1) * vs + lane] = 1.0;
         D[tri(a, a + k)] = kInvFactL.v[k];
     }
     double sgn = 1.0;
@@ -120,8 +129,8 @@ __device__ void taylor_row(const double *s, const double *e, const double *mm, d
         double prev = 0.0;  // h_m() of no variables is 0 for m >= 1
         bool conv = true;
         for (int k = 1; k <= nmax; ++k) {
-            const double hk = fma(s[a + k] - sa, hv[(k - 1) * kWideBlock + lane], prev);
-            hv[(k - 1) * kWideBlock + lane] = hk;
+            const double hk = fma(s[a + k] - sa, hv[(k - 1) * vs + lane], prev);
+            hv[(k - 1) * vs + lane] = hk;
             prev = hk;
             const double term = sgn * hk * kInvFactL.v[k + m];
             const double acc = D[tri(a, a + k)] + term;
@@ -147,12 +156,13 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // The exact update of a window of Wp rates held one per lane (x_k in lane k
 // for k < Wp, N_k in lane k for k <= Wp; zero elsewhere): returns N'_k in
-// lane k.  All 64 lanes call it together.
+// lane k.  All 64 lanes call it together.  V: per-lane columns of the hole
+// recurrence, entry t of lane k at V[t vs + k] (vs >= Wp, t <= Wp - 2).
 __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, double *mm, double *Nb, int *cid,
-                            int *pos, double *D, double *V)
+                            int *pos, double *D, double *V, int vs)
 {
     double *ls = (double *)(pos + 64);  // log of the sorted rates
-    const int lane = threadIdx.x;
+    const int lane = wide_lane();
     // rank of x_k among the window's rates (ties by chain index)
     int rank = 0;
     for (int k = 0; k < Wp; ++k) {
@@ -176,7 +186,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
         D[tri(lane, lane)] = e[lane];
         int nmax = 0;
         while (lane + nmax + 1 < Wp && s[lane + nmax + 1] - s[lane] < kWideClusterSpread) ++nmax;
-        if (nmax > 0) taylor_row(s, e, mm, D, lane, nmax, V, lane);
+        if (nmax > 0) taylor_row(s, e, mm, D, lane, nmax, V, lane, vs);
     }
     wave_sync();
     for (int ord = 1; ord < Wp; ++ord) {
@@ -216,7 +226,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
             if (holes == 0) {
                 G = D[tri(A, B)];
             } else {
-                for (int t = 0; t <= holes; ++t) V[t * kWideBlock + lane] = D[tri(A + t, B)];
+                for (int t = 0; t <= holes; ++t) V[t * vs + lane] = D[tri(A + t, B)];
                 int cnt = holes;
                 for (int q = B; q > A && cnt > 0; --q) {
                     const int ci = cid[q];
@@ -226,8 +236,8 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
                     const double sq = s[q];
                     double cur = V[lane];
                     for (int t = 0; t <= cnt; ++t) {
-                        const double nxt = V[(t + 1) * kWideBlock + lane];
-                        V[t * kWideBlock + lane] = fma(nxt, mm[A + t + 1], (sq - s[A + t]) * cur) * rh;
+                        const double nxt = V[(t + 1) * vs + lane];
+                        V[t * vs + lane] = fma(nxt, mm[A + t + 1], (sq - s[A + t]) * cur) * rh;
                         cur = nxt;
                     }
                 }
@@ -248,13 +258,13 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
 // Nb (window populations), cid (chain index of a sorted position), pos (sorted
 // position of a chain index), D (triangular table), V (one column per lane).
 template <class R>
-__device__ void wide_cell(const StepArgs &a, const double *sc, const double *slog, int W, bool full, int64_t c,
+__device__ void wide_cell(const StepArgs &a, int W, bool full, int64_t c,
                           double EL, int p0, const R *__restrict__ E, R *__restrict__ pops,
                           uint8_t *__restrict__ lo, int64_t n, double *s, double *e, double *mm, double *Nb,
                           int *cid, int *pos, double *D, double *V)
 {
     (void)E;
-    const int lane = threadIdx.x;
+    const int lane = wide_lane();
     const int Z = a.Z;
     wave_sync();  // the previous cell's reads of LDS are done
     double Ns = 0.0;
@@ -276,10 +286,15 @@ __device__ void wide_cell(const StepArgs &a, const double *sc, const double *slo
     const bool finite = EL <= 1.7976931348623157e308 || p >= Z;
     double out = Ns;
     if (finite && p < Z) {
-        const Field f = field_terms<RateEval<PolicyF64>::kLogTerms>(EL, slog);
+        const Field f = field_terms<RateEval<PolicyF64>::kLogTerms>(EL, a.tab + kCoefRows * kCoefStride);
         double x = 0.0;
         const int lev = p + lane;
-        if (lane < W && lev < Z) x = RateEval<PolicyF64>::x_of(sc + lev * kCoefStride, f, a.has_poly != 0);
+        if (lane < W && lev < Z) {
+            double row[kCoefStride];
+            for (int k = 0; k < kCoefStride; ++k) row[k] = a.tab[lev * kCoefStride + k];
+            row[0] += a.ln_dt * kLog2e;  // the fold of ln dt that staging applies
+            x = RateEval<PolicyF64>::x_of(row, f, a.has_poly != 0);
+        }
         // Only slots [q_lo, top] change by more than 1e-30.  q_lo, q_hi: the
         // lowest and highest slot holding at least 1e-30; slot j can receive
         // at most sum_i N_i prod_{k=i}^{j-1} x_k / (j-i)! (g <= 1/n!), so the
@@ -290,9 +305,11 @@ __device__ void wide_cell(const StepArgs &a, const double *sc, const double *slo
         if (pop) {
             const int q_lo = __ffsll((long long)pop) - 1;
             const int q_hi = 63 - __clzll((long long)pop);
-            double *lx = V, *lnN = V + kWideBlock;  // scratch before the solve
-            lx[lane] = lane < W ? log(x) : -INFINITY;
-            lnN[lane] = sig ? log(fabs(Ns)) : -INFINITY;
+            double *lx = V, *lnN = V + (W + 1);  // scratch before the solve (slots 0..W)
+            if (lane <= W) {
+                lx[lane] = lane < W ? log(x) : -INFINITY;
+                lnN[lane] = sig ? log(fabs(Ns)) : -INFINITY;
+            }
             wave_sync();
             bool reach = false;
             if (lane >= q_lo && lane <= W) {
@@ -312,7 +329,7 @@ __device__ void wide_cell(const StepArgs &a, const double *sc, const double *slo
                 const int src = lane + q_lo < 64 ? lane + q_lo : 63;
                 const double xs = __shfl(x, src), Nsub = __shfl(Ns, src);
                 const double r = chain_sub(Wp, lane < Wp ? xs : 0.0, lane <= Wp ? Nsub : 0.0, s, e, mm, Nb, cid,
-                                           pos, D, V);
+                                           pos, D, V, W);
                 const double back = __shfl(r, lane - q_lo >= 0 ? lane - q_lo : 0);
                 if (lane >= q_lo && lane <= top) out = back;
             }
@@ -332,21 +349,25 @@ __device__ void wide_cell(const StepArgs &a, const double *sc, const double *slo
     if (lane == 0) lo[c] = (uint8_t)p;
 }
 
+// Doubles of one wavefront's LDS region for width W: s, e, mm, Nb, cid and
+// pos, log rates (384), the triangular table, and the per-lane columns
+// ((W - 1) W >= 2 (W + 1), which also holds the scratch of the reach test).
+constexpr size_t wide_wave_doubles(int W)
+{
+    return 384 + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * W;
+}
+
 template <class R>
 __global__ __launch_bounds__(kWideBlock) void wide_step_kernel(StepArgs a, int W, int full, const R *__restrict__ E,
                                                                R *__restrict__ pops, uint8_t *__restrict__ lo,
                                                                int64_t n)
 {
-    __shared__ double sc[kDevTableLen];
     extern __shared__ __align__(16) double wl[];
-    double *s = wl, *e = wl + 64, *mm = wl + 128, *Nb = wl + 192;
     int *cid = (int *)(wl + 256);
     int *pos = cid + 64;  // followed by 64 doubles of log rates (chain_sub)
     double *D = wl + 384;
     double *V = D + W * (W + 1) / 2;
-    stage_coefficients(sc, a.tab, a.ln_dt);
-    const double *slog = sc + kCoefRows * kCoefStride;
-    const int lane = threadIdx.x;
+    const int lane = wide_lane();
     const int Z = a.Z;
     for (int64_t base = (int64_t)blockIdx.x * kWideBlock; base < n; base += (int64_t)gridDim.x * kWideBlock) {
         // lane-per-cell test: fully stripped, or below the field cutoff with
@@ -369,16 +390,10 @@ __global__ __launch_bounds__(kWideBlock) void wide_step_kernel(StepArgs a, int W
             todo &= todo - 1;
             const double EL = __shfl(EL0, src);
             const int p = __shfl(p0, src);
-            wide_cell<R>(a, sc, slog, W, full != 0, base + src, EL, p, E, pops, lo, n, wl, wl + 64, wl + 128,
-                         wl + 192, cid, pos, D, V);
+            wide_cell<R>(a, W, full != 0, base + src, EL, p, E, pops, lo, n, wl, wl + 64, wl + 128, wl + 192, cid,
+                         pos, D, V);
         }
     }
-}
-
-template <class R>
-size_t wide_lds_bytes(int W)
-{
-    return sizeof(double) * (384 + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * kWideBlock);
 }
 
 template <class R>
@@ -387,7 +402,7 @@ hipError_t launch_wide(const adk_gas *g, const void *E, int64_t n, double dt, vo
 {
     const StepArgs a = step_args(g, dt, win->eps);
     const int W = win->w;
-    const size_t dyn = wide_lds_bytes<R>(W);
+    const size_t dyn = sizeof(double) * wide_wave_doubles(W);
     static int per_cu[ADK_MAX_WIDE_W + 1] = {};  // occupancy per width (LDS grows with W)
     int b = per_cu[W];
     if (b <= 0) {
