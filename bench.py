@@ -577,7 +577,7 @@ def surrogate_measure(ak, orc, gas36, spec36, w, eps, steps, train_iters, nsampl
     """Surrogate form on the 3D mesh: train the band-column network on the
     device (analytic FP64 targets), check its columns on held-out samples
     against the oracle, time surrogate steps over the mesh like mesh3d, and
-    judge one full-size call against the FP64 oracle (sampled cells) and
+    check one full-size call against the FP64 oracle (sampled cells) and
     against the FP64 analytic step on the GPU (all cells)."""
     import torch
     from oracle import mlp as omlp
@@ -878,8 +878,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the ionization step has no "
-              "cross-cell coupling and this build measures one GPU's share; see DESIGN.md for sharding.",
-              file=sys.stderr)
+              "cross-cell coupling, so a mesh shards into slabs of cells, one per GPU, with no exchange "
+              "in the step; the figure measured here is one GPU's share.", file=sys.stderr)
         sys.exit(2)
 
     import torch
