@@ -243,6 +243,19 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
  * ADK_EDEVICE. */
 int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t *lo, hipStream_t stream);
 
+/* hipGraph path of the batched step: nsteps more steps of the plan with the
+ * arguments of its last adk_plan_step (same E, dt, pops, lo: a field held
+ * constant over nsteps steps, e.g. an ionization sub-cycle inside one field
+ * step), launched as one graph on stream.  The graph (every launch group of
+ * every step, the side-stream fork and join as parallel branches) is captured
+ * on the plan's own stream on first use and cached; it is captured again when
+ * nsteps or the last step's arguments change.  When stream is itself being
+ * captured, the steps are enqueued on it directly (they join the caller's
+ * graph).  Results equal nsteps calls of adk_plan_step bit for bit.
+ * nsteps == 0 is a no-op.  Errors: ADK_EINVAL (null plan, nsteps < 0, no
+ * adk_plan_step before), ADK_EDEVICE. */
+int adk_plan_graph_replay(adk_plan *plan, int32_t nsteps, hipStream_t stream);
+
 /* Host query of the plan's grouping and tuning.  ADK_EINVAL for NULL. */
 int adk_plan_get_info(const adk_plan *plan, adk_plan_info *info);
 

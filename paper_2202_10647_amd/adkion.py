@@ -25,7 +25,7 @@ ADK_MAX_Z, ADK_MAX_W, ADK_MAX_WIDE_W, ADK_M_AVERAGE = 64, 8, 63, -1
 EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "adk_gas_destroy",
            "adk_gas_levels", "adk_rates", "adk_chain_advance", "ionize_step", "ionize_step_yield",
            "adk_subcycle_step", "adk_plan_create",
-           "adk_plan_step", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash", "adk_mlp_nparams",
+           "adk_plan_step", "adk_plan_graph_replay", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash", "adk_mlp_nparams",
            "adk_mlp_create", "adk_mlp_destroy", "adk_mlp_get_state", "adk_band_columns", "adk_mlp_forward",
            "adk_mlp_loss_grad", "adk_mlp_train", "adk_mlp_save", "adk_mlp_load", "adk_surrogate_step",
            "adk_ceiling_copy", "adk_ceiling_valu")
@@ -115,6 +115,8 @@ def lib():
                                   ctypes.POINTER(vp)]
     L.adk_plan_step.restype = ctypes.c_int
     L.adk_plan_step.argtypes = [vp, vp, dbl, vp, vp, vp]
+    L.adk_plan_graph_replay.restype = ctypes.c_int
+    L.adk_plan_graph_replay.argtypes = [vp, i32, vp]
     L.adk_plan_get_info.restype = ctypes.c_int
     L.adk_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
     L.adk_plan_destroy.restype = ctypes.c_int
@@ -361,6 +363,11 @@ class Plan:
         st = lib().adk_plan_step(self._h, _dev(E, "E"), float(dt), _dev(pops, "pops"), _dev(lo, "lo"),
                                  _stream(stream))
         _check(st, "adk_plan_step")
+
+    def graph_replay(self, nsteps: int, stream=None):
+        """nsteps more steps with the arguments of the last step(), replayed
+        as one captured hipGraph (captured on first use, cached)."""
+        _check(lib().adk_plan_graph_replay(self._h, int(nsteps), _stream(stream)), "adk_plan_graph_replay")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

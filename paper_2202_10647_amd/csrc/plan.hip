@@ -68,6 +68,21 @@ struct adk_plan {
     adk::PlanTile *d_tiles = nullptr;
     hipStream_t side = nullptr;  // the other launch groups (ngroups > 1)
     hipEvent_t fork = nullptr, join = nullptr;
+    // arguments of the last adk_plan_step, replayed by adk_plan_graph_replay
+    bool has_last = false;
+    const void *last_E = nullptr;
+    double last_dt = 0.0;
+    void *last_pops = nullptr;
+    uint8_t *last_lo = nullptr;
+    // the captured replay graph and what it was captured with
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t graph_steps = 0;
+    const void *graph_E = nullptr;
+    double graph_dt = 0.0;
+    void *graph_pops = nullptr;
+    uint8_t *graph_lo = nullptr;
 };
 
 namespace adk {
@@ -447,11 +462,9 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
     return ADK_OK;
 }
 
-int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t *lo, hipStream_t stream)
+// The launches of one step (arguments already validated).
+static int plan_launch(adk_plan *plan, const void *E, double dt, void *pops, uint8_t *lo, hipStream_t stream)
 {
-    if (!plan) return ADK_EINVAL;
-    if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
-    if (plan->ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
     auto launch = [&](int i, hipStream_t s) {
         const PlanGroup &grp = plan->group[i];
         const PlanArgs a = plan_args(plan, dt, grp.t0, grp.ntiles);
@@ -473,6 +486,80 @@ int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t 
     if (e != hipSuccess) return plan_status(e);
     if (em != hipSuccess) return plan_status(em);
     return plan_status(ej);
+}
+
+int adk_plan_step(adk_plan *plan, const void *E, double dt, void *pops, uint8_t *lo, hipStream_t stream)
+{
+    if (!plan) return ADK_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
+    if (plan->ncells > 0 && (!E || !pops || !lo)) return ADK_EINVAL;
+    plan->has_last = true;
+    plan->last_E = E;
+    plan->last_dt = dt;
+    plan->last_pops = pops;
+    plan->last_lo = lo;
+    return plan_launch(plan, E, dt, pops, lo, stream);
+}
+
+static void drop_graph(adk_plan *plan)
+{
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->exec = nullptr;
+    plan->graph = nullptr;
+    plan->graph_steps = 0;
+}
+
+int adk_plan_graph_replay(adk_plan *plan, int32_t nsteps, hipStream_t stream)
+{
+    if (!plan || nsteps < 0) return ADK_EINVAL;
+    if (nsteps == 0 || plan->ncells == 0 || plan->ngroups == 0) return ADK_OK;
+    if (!plan->has_last) return ADK_EINVAL;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(stream, &cs);
+    if (e != hipSuccess) return plan_status(e);
+    if (cs != hipStreamCaptureStatusNone) {
+        // the caller is capturing stream: the steps go into the caller's graph
+        for (int32_t k = 0; k < nsteps; ++k) {
+            const int st = plan_launch(plan, plan->last_E, plan->last_dt, plan->last_pops, plan->last_lo, stream);
+            if (st != ADK_OK) return st;
+        }
+        return ADK_OK;
+    }
+    const bool cached = plan->exec && plan->graph_steps == nsteps && plan->graph_E == plan->last_E &&
+                        plan->graph_dt == plan->last_dt && plan->graph_pops == plan->last_pops &&
+                        plan->graph_lo == plan->last_lo;
+    if (!cached) {
+        drop_graph(plan);
+        if (!plan->cap) {
+            e = hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking);
+            if (e != hipSuccess) return plan_status(e);
+        }
+        e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return plan_status(e);
+        int st = ADK_OK;
+        for (int32_t k = 0; k < nsteps && st == ADK_OK; ++k)
+            st = plan_launch(plan, plan->last_E, plan->last_dt, plan->last_pops, plan->last_lo, plan->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(plan->cap, &g);  // ended whatever happened inside
+        if (st != ADK_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != ADK_OK ? st : plan_status(e);
+        }
+        e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            plan->exec = nullptr;
+            (void)hipGraphDestroy(g);
+            return plan_status(e);
+        }
+        plan->graph = g;
+        plan->graph_steps = nsteps;
+        plan->graph_E = plan->last_E;
+        plan->graph_dt = plan->last_dt;
+        plan->graph_pops = plan->last_pops;
+        plan->graph_lo = plan->last_lo;
+    }
+    return plan_status(hipGraphLaunch(plan->exec, stream));
 }
 
 int adk_plan_get_info(const adk_plan *plan, adk_plan_info *info)
@@ -522,6 +609,11 @@ int adk_plan_destroy(adk_plan *plan)
     }
     if (plan->side) {
         const hipError_t e2 = hipStreamDestroy(plan->side);
+        if (e == hipSuccess) e = e2;
+    }
+    drop_graph(plan);
+    if (plan->cap) {
+        const hipError_t e2 = hipStreamDestroy(plan->cap);
         if (e == hipSuccess) e = e2;
     }
     delete plan;

@@ -233,3 +233,8 @@ def test_ceiling_host_validation(L):
     assert L.adk_ceiling_valu(0, -1, buf, 256, None) == E        # iters < 0
     assert L.adk_ceiling_valu(0, 10, buf, 100, None) == E        # lanes not a multiple of 256
     assert L.adk_ceiling_valu(0, 10, buf, 0, None) == E
+
+
+def test_plan_graph_replay_host_validation(L):
+    assert L.adk_plan_graph_replay(None, 1, None) == adkion.ADK_EINVAL
+    assert L.adk_plan_graph_replay(None, -1, None) == adkion.ADK_EINVAL

@@ -194,3 +194,55 @@ def test_plan_errors(env):
     p = ak.Plan(gases, np.zeros(0, np.uint8), np.zeros(0, np.uint8))
     assert p.info["ntiles"] == 0
     p.close()
+
+
+def test_plan_graph_replay_entry_point(env, orc):
+    """adk_plan_graph_replay: one step, then seven more replayed as the plan's
+    own captured graph (two launch groups: fork and join inside the graph),
+    bitwise equal to eight eager steps; the cached graph is replayed again,
+    captured anew for new arrays, and inside a caller's capture the steps join
+    the caller's graph.  Errors before any step and for nsteps < 0."""
+    torch, ak, gases, specs = env
+    n = 600000
+    cell_gas, cell_w = wl.batched_cells(n, seed=8, dopant_fraction=0.05)
+    plan = ak.Plan(gases, cell_gas, cell_w, prec="mixed", cells_per_lane=2)
+    assert plan.info["nlaunches"] == 2
+    with pytest.raises(ak.AdkError) as e:
+        plan.graph_replay(3)  # no step yet
+    assert e.value.status == ak.ADK_EINVAL
+    rows = plan.info["rows"]
+    pops, lo = plan_state(cell_gas, cell_w, rows, seed=9)
+    P0 = torch.from_numpy(pops.astype(np.float32)).cuda()
+    L0 = torch.from_numpy(lo).cuda()
+    E = torch.from_numpy(wl.hash_field(n, 21, 1, dtype=np.float32)).cuda()
+    P, L = P0.clone(), L0.clone()
+    for _ in range(8):
+        plan.step(E, DT, P, L)
+    torch.cuda.synchronize()
+    want_p, want_l = P.clone(), L.clone()
+    for rep in range(2):  # captured on the first pass, cached on the second
+        P.copy_(P0)
+        L.copy_(L0)
+        plan.step(E, DT, P, L)
+        plan.graph_replay(7)
+        torch.cuda.synchronize()
+        assert torch.equal(P, want_p) and torch.equal(L, want_l), rep
+    P2, L2 = P0.clone(), L0.clone()  # new arrays: captured again
+    plan.step(E, DT, P2, L2)
+    plan.graph_replay(7)
+    torch.cuda.synchronize()
+    assert torch.equal(P2, want_p) and torch.equal(L2, want_l)
+    P2.copy_(P0)
+    L2.copy_(L0)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.step(E, DT, P2, L2)
+        plan.graph_replay(7)
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(P2, want_p) and torch.equal(L2, want_l)
+    del g
+    with pytest.raises(ak.AdkError) as e:
+        plan.graph_replay(-1)
+    assert e.value.status == ak.ADK_EINVAL
+    plan.close()
