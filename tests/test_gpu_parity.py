@@ -379,6 +379,48 @@ def test_mesh3d_full_size_sampled(torch_dev, ak, orc, prec, state):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("mesh_name,prec", [("2d", "mixed"), ("2d", "f64"), ("3d", "mixed"), ("3d", "f64")])
+def test_full_run_parity_protocol(torch_dev, ak, orc, mesh_name, prec):
+    """The benchmark's run at full size (2D: 1M cells, 18 levels, 2000 steps;
+    3D: 33.5M cells, 36 levels m averaged, 500 steps; w = 3, eps = 1e-8, from
+    neutral cells), stepped on the GPU in the launch configuration the
+    benchmark times.  At steps 0, 1, every 50th and the last, a fixed random
+    sample of 65,536 cells is copied back with its field and pre-step state,
+    the oracle recomputes that step from those exact bits, and the GPU's
+    post-step state must match it per call."""
+    torch = torch_dev
+    mesh = wl.mesh_2d() if mesh_name == "2d" else wl.mesh_3d()
+    Z = 18 if mesh_name == "2d" else 36
+    gas, spec = gas_pair(ak, orc, Z)
+    n, w, eps = mesh.ncells, 3, 1e-8
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    rng = np.random.default_rng(2202)
+    sample = np.sort(rng.choice(n, 65536, replace=False))
+    idx = torch.from_numpy(sample).cuda()
+    P = torch.zeros((w + 1, n), dtype=tdt, device="cuda")
+    P[0] = 1.0
+    L = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    last = mesh.steps - 1
+    checks = 0
+    for t in range(mesh.steps):
+        E = mesh.field_torch(t, "cuda", tdt)
+        check = t in (0, 1, last) or t % 50 == 0
+        if check:
+            e0, p0, l0 = E[idx].cpu().numpy(), P[:, idx].cpu().numpy(), L[idx].cpu().numpy()
+        ak.ionize_step(gas, E, mesh.dt, P, L, w=w, eps=eps)
+        if check:
+            out, l2 = P[:, idx].cpu().numpy(), L[idx].cpu().numpy()
+            ref, rlo = orc.ionize_step(spec, e0.astype(np.float64), mesh.dt, p0.astype(np.float64), l0, w, eps)
+            assert np.array_equal(l2, rlo), f"step {t}: window index differs"
+            compare(out, ref, prec, f"{mesh_name} {prec} step {t}")
+            checks += 1
+    assert checks == (mesh.steps - 1) // 50 + 2 + (1 if last % 50 else 0)
+    # the run ionizes: the pulse has pushed windows up by the end
+    assert int(L.max()) >= 3
+    del P, L, idx
+    torch.cuda.empty_cache()
+
+
 def test_graph_replay_matches_eager(torch_dev, ak, orc):
     """Thirty steps captured in one HIP graph and replayed three times, with
     eager work and synchronisations between replays: every replay equals the
