@@ -246,3 +246,42 @@ def test_plan_graph_replay_entry_point(env, orc):
         plan.graph_replay(-1)
     assert e.value.status == ak.ADK_EINVAL
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f64"])
+def test_plan_full_size_sampled(env, orc, prec):
+    """The benchmark's batched mix at full size: 16,777,216 cells, 1 %
+    dopants of 7, 18, 36 and 54 levels with w = 1..6, the launch groups and
+    cells per lane the autotuner picks (the launch configuration the
+    benchmark times).  One step from a seeded window state in a host-made
+    log-uniform field; 10,000 host cells and 10,000 dopant cells are
+    recomputed by the oracle."""
+    torch, ak, gases, specs = env
+    n = 1 << 24
+    cell_gas, cell_w = wl.batched_cells(n, seed=4)
+    plan = ak.Plan(gases, cell_gas, cell_w, prec=prec, eps=1e-8, cells_per_lane=0)
+    rows = plan.info["rows"]
+    npdt = np.float32 if prec == "mixed" else np.float64
+    pops, lo = plan_state(cell_gas, cell_w, rows, seed=31)
+    pops = pops.astype(npdt)
+    E = wl.hash_field(n, seed=19, step=3, dtype=npdt)
+    Pt = torch.from_numpy(pops).cuda()
+    Lt = torch.from_numpy(lo).cuda()
+    plan.step(torch.from_numpy(E).cuda(), DT, Pt, Lt)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6)
+    dop = np.nonzero(cell_gas > 0)[0]
+    host = np.nonzero(cell_gas == 0)[0]
+    samp = np.unique(np.concatenate([rng.choice(host, 10000, replace=False), rng.choice(dop, 10000, replace=False)]))
+    idx = torch.from_numpy(samp).cuda()
+    out, l2 = Pt[:, idx].cpu().numpy().astype(np.float64), Lt[idx].cpu().numpy()
+    ref, rlo = oracle_plan(orc, specs, cell_gas[samp], cell_w[samp], E[samp].astype(np.float64),
+                           pops[:, samp].astype(np.float64), lo[samp], 1e-8)
+    assert np.array_equal(l2, rlo)
+    assert np.max(np.abs(out - ref)) <= TOL[prec]
+    # rows above a cell's window are left as they were
+    above = np.arange(rows)[:, None] > cell_w[samp][None, :]
+    assert np.array_equal(out[above], pops[:, samp].astype(np.float64)[above])
+    del Pt, Lt, idx
+    plan.close()
+    torch.cuda.empty_cache()
