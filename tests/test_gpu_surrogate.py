@@ -342,3 +342,43 @@ def test_trained_network_gain(env, orc):
     assert err["trained"].mean() <= 0.2 * err["identity"].mean()
     net.close()
     init.close()
+
+
+def test_surrogate_full_size_sampled(env, orc):
+    """The surrogate form at the 3D mesh's full size (33,554,432 cells, 36
+    levels m averaged, w = 3) in the pulse (t = 210 dt), from a seeded window
+    state, in the launch configuration the benchmark times; 65,536 sampled
+    cells against the CPU reference of the same network (tolerances as in the
+    small-mesh comparison above)."""
+    torch, ak, gases = env
+    Z, w, eps = 36, 3, 1e-8
+    gas, spec = gases[Z]
+    params = wl.mlp_init(Z, 12)
+    net = ak.Mlp(gas, params)
+    mesh = wl.mesh_3d()
+    n = mesh.ncells
+    N, lo = wl.random_window_state(n, Z, w, seed=77, dtype=np.float32)
+    E = mesh.field(210, dtype=np.float32)
+    Pt = torch.from_numpy(N).cuda()
+    Lt = torch.from_numpy(lo).cuda()
+    ak.surrogate_step(gas, net, torch.from_numpy(E).cuda(), mesh.dt, Pt, Lt, w=w, eps=eps)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(210)
+    samp = np.sort(rng.choice(n, 65536, replace=False))
+    idx = torch.from_numpy(samp).cuda()
+    got, glo = Pt[:, idx].cpu().numpy().astype(np.float64), Lt[idx].cpu().numpy()
+    ref, rlo, use, x = mlp.surrogate_step(orc, spec, Z, params.astype(np.float64), RNG, E[samp].astype(np.float64),
+                                          mesh.dt, N[:, samp].astype(np.float64), lo[samp], w, eps)
+    assert np.array_equal(glo, rlo)
+    assert use.sum() > 10000  # the pulse puts many sampled cells in the network's range
+    ana = ~use
+    assert np.max(np.abs(got[:, ana] - ref[:, ana])) <= 1e-6
+    th = mlp.NEGLIGIBLE_XDT
+    clear = ~np.any((x > th / 3) & (x < 3 * th), axis=0)
+    sel = use & clear
+    d = np.abs(got[:, sel] - ref[:, sel]).max(axis=0)
+    assert np.quantile(d, 0.9) <= 1e-5 and d.max() <= 1e-2, np.quantile(d, [0.5, 0.9, 0.99, 1.0])
+    assert np.allclose(got[:, use].sum(axis=0), N[:, samp][:, use].astype(np.float64).sum(axis=0), atol=3e-6)
+    del Pt, Lt, idx
+    net.close()
+    torch.cuda.empty_cache()
