@@ -171,3 +171,43 @@ def test_wide_graph_replay(env, orc):
         assert torch.equal(P, want_p) and torch.equal(L, want_l), rep
         _ = float(P.sum().item())
     del g
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("mesh_name", ["2d", "3d_box"])
+def test_full_chain_full_size_sampled(env, orc, prec, mesh_name):
+    """The studies' reference solver at the size they run it: the full chain
+    (w = Z, eps = 0, full layout) over the whole 2D mesh (1M cells, 18
+    levels) or the 3D mesh's central 64 x 64 x 512 box (2M cells, 36 levels
+    m averaged), one step in the pulse from seeded states spread over many
+    charge states; sampled cells against the oracle's binary128 exponential."""
+    torch, ak, gas_of = env
+    if mesh_name == "2d":
+        mesh, Z, t, ns = wl.mesh_2d(), 18, 1000, 4096
+        cells = np.arange(mesh.ncells)
+    else:
+        mesh, Z, t, ns = wl.mesh_3d(), 36, 250, 1024
+        nx, ny, nz = mesh.shape
+        ix, iy = np.arange(nx // 2 - 32, nx // 2 + 32), np.arange(ny // 2 - 32, ny // 2 + 32)
+        cells = ((ix[:, None, None] * ny + iy[None, :, None]) * nz + np.arange(nz)[None, None, :]).ravel()
+    gas, spec = gas_of(Z)
+    n = cells.size
+    rng = np.random.default_rng(Z + t)
+    spread = rng.exponential(size=(Z + 1, n))
+    spread[rng.random(spread.shape) < 0.3] = 0.0
+    spread[0] += 1e-3
+    pops = (spread / spread.sum(axis=0)).astype(npdt(prec))
+    lo = np.zeros(n, np.uint8)
+    E = mesh.field_at(t, cells).astype(npdt(prec))
+    out_t, lo_t = torch.from_numpy(pops).cuda(), torch.from_numpy(lo).cuda()
+    ak.ionize_step(gas, torch.from_numpy(E).cuda(), mesh.dt, out_t, lo_t, w=Z, eps=0.0, layout="full")
+    torch.cuda.synchronize()
+    samp = np.sort(rng.choice(n, ns, replace=False))
+    idx = torch.from_numpy(samp).cuda()
+    out, l2 = out_t[:, idx].cpu().numpy().astype(np.float64), lo_t[idx].cpu().numpy()
+    ref, rlo = orc.ionize_step(spec, E[samp].astype(np.float64), mesh.dt, pops[:, samp].astype(np.float64), lo[samp],
+                               Z, 0.0, layout=1)
+    assert np.array_equal(l2, rlo) and not l2.any()
+    check(out, ref, prec, f"full chain {mesh_name} {prec}")
+    del out_t, lo_t, idx
+    torch.cuda.empty_cache()
