@@ -593,3 +593,38 @@ def test_subcycle_baseline_matches_oracle(torch_dev, ak, orc, Z, w, nsub):
     assert np.max(rel[ok], initial=0.0) <= 1e-9
     with pytest.raises(ak.AdkError):
         ak.subcycle_step(gas, Et, DT, Pt, Lt, w, 0)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f64"])
+def test_electron_yield_full_size_sampled(torch_dev, ak, orc, prec):
+    """The fused electron yield at the 3D mesh's full size (33.5M cells, the
+    benchmark's launch configuration), one step in the pulse from a seeded
+    window state: 65,536 sampled cells' yields against the oracle's yield of
+    its own step, and the populations equal to ionize_step's bit for bit."""
+    torch = torch_dev
+    Z, w = 36, 3
+    gas, spec = gas_pair(ak, orc, Z)
+    mesh = wl.mesh_3d()
+    n = mesh.ncells
+    comp, lo = wl.random_window_state(n, Z, w, seed=36, dtype=npdt(prec))
+    E = mesh.field(230, dtype=npdt(prec))
+    Et = torch.from_numpy(E).cuda()
+    P1, L1 = torch.from_numpy(comp).cuda(), torch.from_numpy(lo).cuda()
+    P2, L2 = P1.clone(), L1.clone()
+    dne = torch.empty(n, dtype=Et.dtype, device="cuda")
+    ak.ionize_step(gas, Et, mesh.dt, P1, L1, w=w, eps=1e-8, dne=dne)
+    ak.ionize_step(gas, Et, mesh.dt, P2, L2, w=w, eps=1e-8)
+    torch.cuda.synchronize()
+    assert torch.equal(P1, P2) and torch.equal(L1, L2)
+    rng = np.random.default_rng(230)
+    samp = np.sort(rng.choice(n, 65536, replace=False))
+    idx = torch.from_numpy(samp).cuda()
+    y = dne[idx].cpu().numpy().astype(np.float64)
+    pin, lin = comp[:, samp].astype(np.float64), lo[samp]
+    ref, rlo = orc.ionize_step(spec, E[samp].astype(np.float64), mesh.dt, pin, lin, w, 1e-8)
+    y_ref = orc.electron_yield(pin, lin, ref, rlo, Z)
+    bound = TOL[prec] * (w + 1) * (Z + 1)
+    assert np.max(np.abs(y - y_ref)) <= bound
+    assert np.max(y_ref) > 0.1  # the pulse ionizes sampled cells this step
+    del P1, L1, P2, L2, dne, idx, Et
+    torch.cuda.empty_cache()
