@@ -157,7 +157,7 @@ struct RateEval<PolicyF64> {
     {
         double x = exp2(rate_exponent2(row, f));
         if (has_poly) x *= mavg_poly(row, f);
-        return fmin(x, kXMax<double>);
+        return x < kXMax<double> ? x : kXMax<double>;  // the cap (x is never NaN here)
     }
 };
 
@@ -168,13 +168,17 @@ struct RateEval<PolicyMixed> {
     {
         // 2^t with t split exactly in double: the integer part goes to the
         // exponent and only |fr| <= 1/2 passes through the float exp2, so the
-        // relative error stays a few float ulps whatever the size of t.
-        const double t = fmax(fmin(rate_exponent2(row, f), 45.0), -160.0);
+        // relative error stays a few float ulps whatever the size of t.  The
+        // lower bound keeps the integer part in range of the conversion (2^-160
+        // is 0 in float; the field terms bound t above by |alpha| log2(1e300)
+        // + a, far inside int); a t above 128 gives +inf, which the cap below
+        // turns into kXMax (the m-average polynomial is at least 1, never 0).
+        const double t = fmax(rate_exponent2(row, f), -160.0);
         const double ti = rint(t);
         // |t - ti| <= 1/2: the hardware exp2 (no range reduction needed)
         float x = ldexpf(__builtin_amdgcn_exp2f((float)(t - ti)), (int)ti);
         if (has_poly) x *= (float)mavg_poly(row, f);
-        return fminf(x, kXMax<float>);
+        return __builtin_amdgcn_fmed3f(x, 0.0f, kXMax<float>);  // the cap (x >= 0, never NaN here)
     }
 };
 
