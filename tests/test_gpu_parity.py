@@ -628,3 +628,37 @@ def test_electron_yield_full_size_sampled(torch_dev, ak, orc, prec):
     assert np.max(y_ref) > 0.1  # the pulse ionizes sampled cells this step
     del P1, L1, P2, L2, dne, idx, Et
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("Z,w", [(18, 3), (36, 3), (54, 6), (7, 1)])
+def test_weak_rate_series_matches_oracle(torch_dev, ak, orc, prec, Z, w):
+    """Fields picked so that every rate of every cell's window lies in
+    [1e-9, 1e-3] per step (the Taylor-series branch in every wavefront), and a
+    set that straddles the 1e-3 threshold (wavefronts of both branches), all
+    cells against the oracle; populations stay conserved."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, Z)
+    n = 3 * 256 + 17
+    comp, lo = wl.random_window_state(n, Z, w, seed=Z + 5 * w)
+    lo = np.minimum(lo, Z - w).astype(np.uint8)  # full windows below the last level
+    grid = np.logspace(0, 4.5, 3000)
+    rates = orc.rates(spec, grid) * DT  # [Z][grid]
+    rng = np.random.default_rng(Z * w)
+    for lo_x, hi_x in ((1e-9, 1e-3), (1e-5, 1e-1)):
+        E = np.empty(n)
+        for c in range(n):
+            xmax = rates[lo[c]: lo[c] + w].max(axis=0)
+            xmin = rates[lo[c]: lo[c] + w].min(axis=0)
+            ok = np.nonzero((xmax <= hi_x) & (xmin >= lo_x))[0]
+            if ok.size == 0:
+                ok = np.nonzero(xmax <= hi_x)[0]
+            E[c] = grid[rng.choice(ok)]
+        pops = comp.astype(npdt(prec))
+        Ep = E.astype(npdt(prec))
+        out, l2 = run_step(torch, ak, gas, Ep, pops, lo, w, 1e-8, "compact")
+        ref, rlo = orc.ionize_step(spec, Ep.astype(np.float64), DT, pops.astype(np.float64), lo, w, 1e-8)
+        assert np.array_equal(l2, rlo)
+        compare(out, ref, prec, f"weak rates [{lo_x:g}, {hi_x:g}] Z={Z} w={w} {prec}")
+        tot = out.astype(np.float64).sum(axis=0) - pops.astype(np.float64).sum(axis=0)
+        assert np.max(np.abs(tot)) <= (1e-14 if prec == "f64" else 1e-6)
