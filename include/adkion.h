@@ -147,9 +147,12 @@ int adk_chain_advance(int32_t w, const void *W, int64_t ncells, double dt, void 
  * populations in that cell only.  Windows up to ADK_MAX_W rates run one cell
  * per lane; wider windows (up to ADK_MAX_WIDE_W, so w = Z with eps = 0 is the
  * full chain of Sec. 3's comparison for Z <= 63) run one cell per wavefront,
- * in double arithmetic for either precision.  Errors: ADK_EINVAL (null
- * pointers with ncells > 0, ncells < 0, dt <= 0 or non-finite, eps < 0 or
- * non-finite, bad enums), ADK_ERANGE (w outside [1, min(Z, ADK_MAX_WIDE_W)]). */
+ * in double arithmetic for either precision.  A cell with no shift due whose
+ * window rates are all below 1e-16 per step (windows up to ADK_MAX_W) keeps
+ * its populations: the exact step would change them by less than 3e-16.
+ * Errors: ADK_EINVAL (null pointers with ncells > 0, ncells < 0, dt <= 0 or
+ * non-finite, eps < 0 or non-finite, bad enums), ADK_ERANGE (w outside
+ * [1, min(Z, ADK_MAX_WIDE_W)]). */
 int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops,
                 uint8_t *lo, const adk_window *win, hipStream_t stream);
 

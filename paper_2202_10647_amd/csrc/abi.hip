@@ -45,6 +45,29 @@ ChunkOrder chunk_order(int64_t n, int64_t chunk)
     return o;
 }
 
+WinCut window_cutoffs(const adk_gas *g, double dt, int w)
+{
+    adk_gas *mg = const_cast<adk_gas *>(g);
+    std::lock_guard<std::mutex> lock(mg->cut_mu);
+    if (mg->wcut_dt != dt || mg->wcut_w != w) {
+        float lvl[ADK_MAX_Z];
+        level_thresholds(*g, dt, kIdentityRate, lvl);  // rounded down per level
+        for (int p = 0; p <= ADK_MAX_Z; ++p) {
+            float e = 0.0f;  // p >= Z: fully stripped, never compared
+            if (p < g->Z) {
+                e = INFINITY;
+                for (int k = p; k < p + w && k < g->Z; ++k) e = std::fmin(e, lvl[k]);
+            }
+            mg->wcut[p] = e;
+        }
+        mg->wcut_dt = dt;
+        mg->wcut_w = w;
+    }
+    WinCut c;
+    for (int p = 0; p <= ADK_MAX_Z; ++p) c.e[p] = mg->wcut[p];
+    return c;
+}
+
 StepArgs step_args(const adk_gas *g, double dt, double eps)
 {
     StepArgs a;

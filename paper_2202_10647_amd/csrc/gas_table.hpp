@@ -21,6 +21,10 @@ struct adk_gas {
     // per-level negligible-rate fields of the last step used by the surrogate
     double thr_dt = -1.0;
     float thr_E[ADK_MAX_Z] = {};
+    // per-window identity fields of the last (step, width) of ionize_step
+    double wcut_dt = -1.0;
+    int wcut_w = 0;
+    float wcut[ADK_MAX_Z + 1] = {};
 };
 
 namespace adk {

@@ -84,7 +84,18 @@ __device__ __forceinline__ int64_t chunk_place(int64_t v, const ChunkOrder &o)
     return (int64_t)x;
 }
 
+// Identity windows.  For each window start p < Z, the field below which
+// every rate of the window p .. min(p + w, Z) - 1 is below kIdentityRate per
+// step (the smallest of the levels' thresholds, rounded down): a cell under
+// it with no shift due keeps its populations, which the exact step would
+// change by less than w kIdentityRate of them (below FP64 rounding).
+constexpr double kIdentityRate = 1e-16;
+struct WinCut {
+    float e[ADK_MAX_Z + 1];
+};
+
 // Host helpers (abi.hip).
+WinCut window_cutoffs(const adk_gas *g, double dt, int w);
 int num_cus();
 int grid_for(int64_t n);
 StepArgs step_args(const adk_gas *g, double dt, double eps);
@@ -306,7 +317,7 @@ __device__ __forceinline__ void step_cell(const CellLoad<typename P::real, W> &c
 // dne[c] = sum_s (lo' + s) N'_s - sum_s (lo + s) N_s: the change of the mean
 // charge (electrons released per atom), from the same registers.
 template <class P, int W, bool YIELD>
-__global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, ChunkOrder ord,
+__global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, WinCut wc, ChunkOrder ord,
                                                               const typename P::real *__restrict__ E,
                                                               typename P::real *__restrict__ pops,
                                                               uint8_t *__restrict__ lo, int64_t n,
@@ -314,8 +325,10 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, ChunkO
 {
     using R = typename P::real;
     __shared__ double sc[kDevTableLen];
+    __shared__ float scut[ADK_MAX_Z + 1];
     const double *slog = sc + kCoefRows * kCoefStride;
     const int Z = a.Z;
+    for (int t = threadIdx.x; t <= ADK_MAX_Z; t += kBlock) scut[t] = wc.e[t];  // visible after the staging barrier
     // workgroup b takes chunks b, b + grid, ... of kBlock cells, each mapped
     // to a scattered place of the mesh (ChunkOrder)
     const int64_t nv = (n + kBlock - 1) / kBlock;
@@ -333,14 +346,15 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, ChunkO
         c = cn;
         if (cc >= n) continue;
         const int p = cur.lo < Z ? cur.lo : Z;
-        if (__all(p >= Z || (fabs((double)cur.E) < a.E_cut && (double)cur.N[0] >= a.eps))) {
+        const double ecut = p < Z ? (double)scut[p] : 0.0;
+        if (__all(p >= Z || (fabs((double)cur.E) < ecut && (double)cur.N[0] >= a.eps))) {
             if (p != cur.lo) lo[cc] = (uint8_t)p;  // an index past Z is clamped
             if (YIELD) dne[cc] = R(0);
             continue;
         }
         R o[W + 1];
         int l;
-        step_cell_out<P, W>(cur, sc, slog, Z, a.has_poly != 0, a.eps, a.E_cut, o, l);
+        step_cell_out<P, W>(cur, sc, slog, Z, a.has_poly != 0, a.eps, ecut, o, l);
         static_for<0, W + 1>([&](auto ss) {
             constexpr int s = decltype(ss)::value;
             pops[(int64_t)s * n + cc] = o[s];
@@ -360,13 +374,15 @@ __global__ __launch_bounds__(kBlock) void step_compact_kernel(StepArgs a, ChunkO
 
 // ionize_step, full layout: pops[(Z+1)][n], row k = level k.
 template <class P, int W>
-__global__ __launch_bounds__(kBlock) void step_full_kernel(StepArgs a, const typename P::real *__restrict__ E,
+__global__ __launch_bounds__(kBlock) void step_full_kernel(StepArgs a, WinCut wc, const typename P::real *__restrict__ E,
                                                            typename P::real *__restrict__ pops,
                                                            uint8_t *__restrict__ lo, int64_t n)
 {
     using R = typename P::real;
     __shared__ double sc[kDevTableLen];
+    __shared__ float scut[ADK_MAX_Z + 1];
     const double *slog = sc + kCoefRows * kCoefStride;
+    for (int t = threadIdx.x; t <= ADK_MAX_Z; t += kBlock) scut[t] = wc.e[t];  // visible after the staging barrier
     stage_coefficients(sc, a.tab, a.ln_dt);
     const int Z = a.Z;
     const bool has_poly = a.has_poly != 0;
@@ -387,7 +403,9 @@ __global__ __launch_bounds__(kBlock) void step_full_kernel(StepArgs a, const typ
             N[s] = (p + s <= Z) ? (double)pops[(int64_t)(p + s) * n + c] : 0.0;
         });
         double out[W + 1];
-        if (__all(EL < a.E_cut)) {
+        // the compact kernel's identity test (window under its identity
+        // field, no shift due), so both layouts take the same path
+        if (__all(p0 >= Z || (EL < (double)scut[p0] && p == p0))) {
             static_for<0, W + 1>([&](auto ss) { out[decltype(ss)::value] = N[decltype(ss)::value]; });
         } else {
             const Field f = field_terms<RateEval<P>::kLogTerms>(EL, slog);
@@ -585,19 +603,20 @@ hipError_t launch_step(const adk_gas *g, const void *E, int64_t n, double dt, vo
 {
     using R = typename P::real;
     const StepArgs a = step_args(g, dt, win->eps);
+    const WinCut wc = window_cutoffs(g, dt, W);
     if (win->layout == ADK_LAYOUT_COMPACT) {
         if (dne) {
             const int grid = resident_grid<step_compact_kernel<P, W, true>>(n, kStepChunksPerGroup);
-            hipLaunchKernelGGL((step_compact_kernel<P, W, true>), dim3(grid), dim3(kBlock), 0, st, a,
+            hipLaunchKernelGGL((step_compact_kernel<P, W, true>), dim3(grid), dim3(kBlock), 0, st, a, wc,
                                chunk_order(n), (const R *)E, (R *)pops, lo, n, (R *)dne);
         } else {
             const int grid = resident_grid<step_compact_kernel<P, W, false>>(n, kStepChunksPerGroup);
-            hipLaunchKernelGGL((step_compact_kernel<P, W, false>), dim3(grid), dim3(kBlock), 0, st, a,
+            hipLaunchKernelGGL((step_compact_kernel<P, W, false>), dim3(grid), dim3(kBlock), 0, st, a, wc,
                                chunk_order(n), (const R *)E, (R *)pops, lo, n, (R *)nullptr);
         }
     } else {
         const int grid = resident_grid<step_full_kernel<P, W>>(n);
-        hipLaunchKernelGGL((step_full_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, a, (const R *)E,
+        hipLaunchKernelGGL((step_full_kernel<P, W>), dim3(grid), dim3(kBlock), 0, st, a, wc, (const R *)E,
                            (R *)pops, lo, n);
     }
     return hipGetLastError();
