@@ -99,3 +99,22 @@ def test_rates_array_matches_scalar(orc):
         k = 3 + j
         for i, e in enumerate(E):
             assert W[j, i] == orc.level_rate(g.U[k], k + 1, g.l[k], g.m[k], e)
+
+
+@pytest.mark.parametrize("U,Q,l", [(15.76, 1, 1), (40.74, 3, 1), (422.4, 8, 1), (520.0, 10, 2), (8.0, 1, 0)])
+@pytest.mark.parametrize("E1,E2", [(150.0, 900.0), (400.0, 3000.0)])
+def test_field_dependence_at_noninteger_nstar(orc, U, Q, l, E1, E2):
+    """Eq. (1) depends on the field only through E^(1/2) (the square-root
+    factor), E^-(2n*-|m|-1) (the power factor) and exp(-2 E_a (Q/n*)^3 / (3E))
+    (the tunnelling factor), so the log-ratio of two rates of one level is, at
+    any n*, (1/2 - (2n*-|m|-1)) ln(E2/E1) - (2/3) E_a (Q/n*)^3 (1/E2 - 1/E1).
+    Every n* here is non-integer; a wrong exponent on E or a wrong power of
+    Q/n* in the tunnelling factor changes the ratio by orders of magnitude."""
+    ns = Q * math.sqrt(U_H / U)
+    assert abs(ns - round(ns)) > 0.05
+    for am in range(l + 1):
+        w1 = orc.rate_lm(U, Q, l, am, E1)
+        w2 = orc.rate_lm(U, Q, l, am, E2)
+        assert w1 > 0.0 and w2 > 0.0
+        want = (0.5 - (2 * ns - am - 1)) * math.log(E2 / E1) - (2.0 / 3.0) * E_A * (Q / ns) ** 3 * (1 / E2 - 1 / E1)
+        assert math.log(w2 / w1) == pytest.approx(want, rel=1e-12, abs=1e-11)
