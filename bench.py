@@ -977,6 +977,7 @@ def main():
                      "kernel": f"step_compact_kernel<PolicyMixed,{w}>",
                      "bytes_per_cell": bytes_per_cell(w, "mixed"), "kernel_avg_us": m["kernel_ms"] * 1e3,
                      "timing": "HIP events around one graph replay of the timed steps / steps",
+                     "kernel_trace": "profiles/step_compact_mixed_w3_mesh2d_default_bench_trace.md",
                      "frac_of_measured_hbm_copy": m["achieved_gbps"] / ceil["hbm_copy_gbps"] if ceil else None,
                      "frac_of_measured_cache_copy": m["achieved_gbps"] / ceil["cache_copy_gbps"] if ceil else None},
         "ceilings": ceil,
