@@ -662,3 +662,49 @@ def test_weak_rate_series_matches_oracle(torch_dev, ak, orc, prec, Z, w):
         compare(out, ref, prec, f"weak rates [{lo_x:g}, {hi_x:g}] Z={Z} w={w} {prec}")
         tot = out.astype(np.float64).sum(axis=0) - pops.astype(np.float64).sum(axis=0)
         assert np.max(np.abs(tot)) <= (1e-14 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("Z,w", [(18, 3), (36, 3), (54, 6)])
+def test_identity_field_boundary(torch_dev, ak, orc, prec, Z, w):
+    """Fields at the per-window identity field (every rate of the window at
+    1e-16 per step, located on the oracle's rates): wavefronts held 2 % below
+    it keep their populations bit for bit, wavefronts 2 % above it and cells
+    scattered across it match the oracle, window indices equal."""
+    torch = torch_dev
+    gas, spec = gas_pair(ak, orc, Z)
+    n = 4 * 256 + 37
+    comp, lo = wl.random_window_state(n, Z, w, seed=3 * Z + w)
+    lo = np.minimum(lo, Z - w).astype(np.uint8)
+    comp[0] = np.maximum(comp[0], 1e-4)  # no shift due anywhere
+    comp /= comp.sum(axis=0, keepdims=True)
+    grid = np.geomspace(1.0, 1e6, 40001)
+    rates = orc.rates(spec, grid) * DT  # [Z][grid]
+    E_lo = np.empty(n)
+    E_hi = np.empty(n)
+    for c in range(n):
+        xmax = rates[lo[c]: lo[c] + w].max(axis=0)
+        below = np.nonzero(xmax <= 1e-16)[0]
+        i = below[-1] if below.size else 0
+        assert i + 1 < grid.size and xmax[i + 1] > 1e-16
+        E_lo[c], E_hi[c] = grid[i], grid[i + 1]
+    rng = np.random.default_rng(Z + 7 * w)
+    E = E_lo * rng.uniform(0.95, 1.05, n)
+    E[0:256] = 0.98 * E_lo[0:256]  # four identity wavefronts
+    E[256:512] = 1.02 * E_hi[256:512]  # four wavefronts over the field
+    E[::13] *= -1.0
+    pops = comp.astype(npdt(prec))
+    Ep = E.astype(npdt(prec))
+    out, l2 = run_step(torch, ak, gas, Ep, pops, lo, w, 1e-8, "compact")
+    ref, rlo = orc.ionize_step(spec, Ep.astype(np.float64), DT, pops.astype(np.float64), lo, w, 1e-8)
+    assert np.array_equal(l2, rlo) and np.array_equal(l2, lo)
+    compare(out, ref, prec, f"identity boundary Z={Z} w={w} {prec}")
+    assert np.array_equal(out[:, 0:256], pops[:, 0:256])
+    # the same cells through the full layout take the same decision
+    full = np.zeros((Z + 1, n), dtype=npdt(prec))
+    for s in range(w + 1):
+        full[lo.astype(np.int64) + s, np.arange(n)] = pops[s]
+    fout, fl2 = run_step(torch, ak, gas, Ep, full, lo, w, 1e-8, "full")
+    assert np.array_equal(fl2, l2)
+    for s in range(w + 1):
+        assert np.array_equal(fout[lo.astype(np.int64) + s, np.arange(n)], out[s])
