@@ -118,3 +118,21 @@ def test_field_dependence_at_noninteger_nstar(orc, U, Q, l, E1, E2):
         assert w1 > 0.0 and w2 > 0.0
         want = (0.5 - (2 * ns - am - 1)) * math.log(E2 / E1) - (2.0 / 3.0) * E_A * (Q / ns) ** 3 * (1 / E2 - 1 / E1)
         assert math.log(w2 / w1) == pytest.approx(want, rel=1e-12, abs=1e-11)
+
+
+@pytest.mark.parametrize("E", [30.0, 60.0, 100.0, 200.0])
+def test_hydrogen_step_closed_form(orc, E):
+    """The step driver on a one-level gas (hydrogen: U = U_H, so Q = 1 and
+    n* = 1, l = m = 0): the neutral fraction falls to exp(-W dt) with W the
+    hand-simplified Eq. (1), the rest is ionized (Eq. (3) with one rate).
+    Pins which charge and level the driver evaluates Eq. (1) at, and dt."""
+    dt = 1.334e-16
+    spec = orc.GasSpec([U_H], [0], [0])
+    x = hydrogen_closed_form(E) * dt
+    assert 1e-3 < x < 10.0
+    pops = np.array([[1.0, 0.25], [0.0, 0.75]])
+    out, lo = orc.ionize_step(spec, np.array([E, -E]), dt, pops, np.zeros(2, np.uint8), w=1, eps=1e-8)
+    assert lo.tolist() == [0, 0]
+    for c, n0 in enumerate((1.0, 0.25)):
+        assert out[0, c] == pytest.approx(n0 * math.exp(-x), rel=1e-13)
+        assert out[1, c] == pytest.approx(1.0 - n0 * math.exp(-x), rel=1e-13)
