@@ -106,3 +106,53 @@ def test_planted_mistake_is_caught(tmp_path, name, old, new):
     orc = _mutant_oracle(str(tmp_path), 1, old, new)
     failed = _failing_pins(orc)
     assert failed, f"no pin catches the planted mistake: {name}"
+
+
+# The sub-cycled RK4 baseline's reference (oracle/subcycle.py), same idea:
+# a mutated copy of the module text runs under the baseline's two pins.
+SUBCYCLE_SRC = os.path.join(ROOT, "oracle", "subcycle.py")
+S = _load_path("pins_subcycle", os.path.join(HERE, "test_oracle_subcycle.py"))
+
+SUBCYCLE_MUTANTS = [
+    ("RK4 weights 1, 1, 1, 1", "(h / 6.0) * (k1 + 2.0 * (k2 + k3) + k4)", "(h / 4.0) * (k1 + k2 + k3 + k4)"),
+    ("second stage at the full substep", "y + 0.5 * h * k1", "y + h * k1"),
+    ("top level leaks", "d[w] = x[w - 1] * y[w - 1]", "d[w] = x[w - 1] * y[w - 1] - x[w - 1] * y[w]"),
+    ("rates not scaled by dt", "x[s, ok] = Wall[k[ok], np.nonzero(ok)[0]] * dt",
+     "x[s, ok] = Wall[k[ok], np.nonzero(ok)[0]] * dt * 1.001"),
+]
+
+
+def _subcycle_copy(old, new):
+    import types
+    from oracle import mlp
+    src = open(SUBCYCLE_SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique: {old!r}"
+    src = src.replace("from .mlp import window_shift\n", "").replace(old, new)
+    mod = types.ModuleType("subcycle_mutant")
+    mod.window_shift = mlp.window_shift
+    exec(compile(src, "subcycle_mutant.py", "exec"), mod.__dict__)
+    return mod
+
+
+def _failing_subcycle_pins(orc, mod):
+    saved = S.subcycle
+    S.subcycle = mod
+    failed = []
+    try:
+        for pin in (S.test_single_level_closed_form, S.test_conservation_and_fourth_order_convergence):
+            try:
+                pin(orc)
+            except AssertionError:
+                failed.append(pin.__name__)
+    finally:
+        S.subcycle = saved
+    return failed
+
+
+def test_unmutated_subcycle_copy_passes(orc):
+    assert _failing_subcycle_pins(orc, _subcycle_copy("h = 1.0 / nsub", "h = 1.0 / nsub ")) == []
+
+
+@pytest.mark.parametrize("name,old,new", SUBCYCLE_MUTANTS)
+def test_planted_subcycle_mistake_is_caught(orc, name, old, new):
+    assert _failing_subcycle_pins(orc, _subcycle_copy(old, new)), f"no pin catches: {name}"
