@@ -156,3 +156,58 @@ def test_unmutated_subcycle_copy_passes(orc):
 @pytest.mark.parametrize("name,old,new", SUBCYCLE_MUTANTS)
 def test_planted_subcycle_mistake_is_caught(orc, name, old, new):
     assert _failing_subcycle_pins(orc, _subcycle_copy(old, new)), f"no pin catches: {name}"
+
+
+# The surrogate network's reference (oracle/mlp.py) under its own pins.
+MLP_SRC = os.path.join(ROOT, "oracle", "mlp.py")
+M = _load_path("pins_mlp", os.path.join(HERE, "test_oracle_mlp.py"))
+
+MLP_MUTANTS = [
+    ("bfloat16 with 7 significant bits", "np.rint(m * 256.0) / 256.0", "np.rint(m * 128.0) / 128.0"),
+    ("ReLU mask of the wrong layer", 'dz3 = (dz4 @ c["W4"]) * (c["h3"] > 0)', 'dz3 = (dz4 @ c["W4"]) * (c["h2"] > 0)'),
+    ("weight gradient transposed", 'g["W2"] = dz2.T @ c["h1"]', 'g["W2"] = c["h1"].T @ dz2'),
+    ("Adam without bias correction of m", "mh = m / (1.0 - beta1 ** t)", "mh = m"),
+    ("band update drops the window top", "o[top] = N[top, c]", "o[top] = 0.0"),
+]
+
+
+def _mlp_copy(old, new):
+    import sys
+    import types
+    src = open(MLP_SRC).read()
+    assert src.count(old) == 1, f"mutation site not unique: {old!r}"
+    mod = types.ModuleType("mlp_mutant")
+    sys.modules["mlp_mutant"] = mod  # dataclasses resolve annotations through sys.modules
+    try:
+        exec(compile(src.replace(old, new), "mlp_mutant.py", "exec"), mod.__dict__)
+    finally:
+        del sys.modules["mlp_mutant"]
+    return mod
+
+
+def _failing_mlp_pins(orc, mod):
+    pins = [M.test_bf16_rounding, M.test_backward_matches_finite_differences,
+            M.test_adam_first_step_and_bias_correction, M.test_softmax_invariants,
+            lambda: M.test_weight_layout_out_in(True),
+            lambda: M.test_band_update_with_exact_columns_is_the_step(orc, 3)]
+    saved = M.mlp
+    M.mlp = mod
+    failed = []
+    try:
+        for i, pin in enumerate(pins):
+            try:
+                pin()
+            except AssertionError:
+                failed.append(i)
+    finally:
+        M.mlp = saved
+    return failed
+
+
+def test_unmutated_mlp_copy_passes(orc):
+    assert _failing_mlp_pins(orc, _mlp_copy("mh = m / (1.0 - beta1 ** t)", "mh = m / (1.0 - beta1 ** t) ")) == []
+
+
+@pytest.mark.parametrize("name,old,new", MLP_MUTANTS)
+def test_planted_mlp_mistake_is_caught(orc, name, old, new):
+    assert _failing_mlp_pins(orc, _mlp_copy(old, new)), f"no pin catches: {name}"
