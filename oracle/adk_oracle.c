@@ -58,10 +58,10 @@ static double orc_fact(int n)
  * Eq. (1), literally: W_lm for one electron with orbital number l and
  * projection |m| = am, in s^-1.  U in eV, E in GV/m.
  * consts = {omega_a [s^-1], E_a [GV/m], U_H [eV]} (Sec. 2, text after Eq. (1)).
- * Pinned by the hydrogen closed form, the charge scaling law, the |m| and l
- * factors and, at non-integer n*, the whole field dependence; the
- * field-independent factor's dependence on non-integer n* is parity unpinned
- * beyond n* = 1 and the scaling law (the paper prints no rate values).
+ * Pinned by hand-simplified closed forms at n* = 1, 2 and 3 (which fix the
+ * n* dependence of every factor), the charge scaling law, the |m| and l
+ * factors and, at non-integer n*, the whole field dependence (the paper
+ * prints no rate values).
  */
 double orc_rate_lm(double U, int Q, int l, int am, double E, const double *consts)
 {

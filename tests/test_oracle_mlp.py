@@ -215,3 +215,80 @@ def test_surrogate_samples_definition():
     # log-uniform: log E is uniform
     le = (np.log(E) - np.log(10)) / np.log(500)
     assert abs(le.mean() - 0.5) < 0.01 and abs(le.var() - 1 / 12) < 0.005
+
+
+def test_features_map_the_trained_range_onto_the_unit_interval():
+    """u and v are affine in log10 |E| and log10 dt, with the trained range's
+    ends at -1 and +1 and its geometric centre at 0; the sign of E is dropped."""
+    r = mlp.Range()
+    E = np.array([r.E_lo, r.E_hi, math.sqrt(r.E_lo * r.E_hi), -r.E_hi, r.E_lo * 10.0])
+    u, v = r.features(E, r.dt_lo)
+    want_u = [-1.0, 1.0, 0.0, 1.0, -1.0 + 2.0 / math.log10(r.E_hi / r.E_lo)]
+    assert np.allclose(u, want_u, rtol=0, atol=1e-14)
+    assert v.shape == u.shape and np.allclose(v, -1.0, atol=1e-14)
+    _, v = r.features(E, r.dt_hi)
+    assert np.allclose(v, 1.0, atol=1e-14)
+    _, v = r.features(E[:1], math.sqrt(r.dt_lo * r.dt_hi))
+    assert abs(v[0]) < 1e-14
+    # a range of its own: 1..100 GV/m puts 10 GV/m at the centre
+    r2 = mlp.Range(E_lo=1.0, E_hi=100.0)
+    u, _ = r2.features(np.array([10.0, 1.0, 100.0]), r2.dt_lo)
+    assert np.allclose(u, [0.0, -1.0, 1.0], atol=1e-14)
+
+
+def _constant_network(Z, q):
+    """Every input gives the column q: all weights zero, b4 = log q."""
+    blocks = {name: np.zeros(shape) for name, shape in mlp.block_shapes(Z)}
+    blocks["b4"][:] = np.log(q)
+    return mlp.pack(blocks, Z)
+
+
+def test_surrogate_step_composition(orc):
+    """The surrogate form of the step, pinned case by case with a network whose
+    column is the same constant q for every input: band columns apply after the
+    start-of-step window shift, destinations past the window top (or past level
+    Z) land on the top, sources whose W dt is below NEGLIGIBLE_XDT keep their
+    population, and cells out of the trained field range, fully stripped cells
+    and calls with dt out of range take the analytic oracle step."""
+    Z, w, dt, eps = 7, 2, 1.334e-16, 1e-8
+    t = wl.synthetic_gas(Z)
+    spec = orc.GasSpec(t.U, t.l, t.m)
+    q = np.array([0.5, 0.25, 0.15, 0.1])
+    params = _constant_network(Z, q)
+    r = mlp.Range()
+    cells = [  # (E, lo, N)
+        (3000.0, 2, (0.5, 0.3, 0.2)),         # 0: two network sources
+        (-3000.0, 2, (0.5, 0.3, 0.2)),        # 1: the sign of E is dropped
+        (50.0, 0, (0.7, 0.2, 0.1)),           # 2: level 0 network, level 1 negligible
+        (12.0, 0, (0.6, 0.3, 0.1)),           # 3: every source negligible
+        (3000.0, 6, (0.8, 0.2, 0.0)),         # 4: top clipped at level Z
+        (3000.0, 1, (1e-10, 0.6, 0.4 - 1e-10)),  # 5: shift first, then the band
+        (6000.0, 2, (0.5, 0.3, 0.2)),         # 6: above the field range: analytic
+        (0.0, 2, (0.5, 0.3, 0.2)),            # 7: zero field: analytic
+        (3000.0, 7, (1.0, 0.0, 0.0)),         # 8: fully stripped: analytic
+    ]
+    E = np.array([c[0] for c in cells])
+    lo = np.array([c[1] for c in cells], np.uint8)
+    N = np.array([c[2] for c in cells], np.float64).T.copy()
+    x = orc.rates(spec, np.abs(E)) * dt
+    assert np.all(x[2:4, 0] >= 1e-9) and x[0, 2] >= 1e-9 and x[1, 2] < 1e-9 and np.all(x[:2, 3] < 1e-9)
+    out, olo, use, _ = mlp.surrogate_step(orc, spec, Z, params, r, E, dt, N, lo, w, eps, bf16_ops=False)
+    q0, q1, q23 = q[0], q[1], q[2] + q[3]
+    for c in (0, 1):
+        a, b, top = N[:, c]
+        assert np.allclose(out[:, c], [q0 * a, q1 * a + q0 * b, top + q23 * a + (1 - q0) * b], rtol=1e-14)
+    a, b, top = N[:, 2]
+    assert np.allclose(out[:, 2], [q0 * a, q1 * a + b, top + q23 * a], rtol=1e-14)
+    assert np.array_equal(out[:, 3], N[:, 3])
+    a, b, _ = N[:, 4]
+    assert np.allclose(out[:, 4], [q0 * a, b + (1 - q0) * a, 0.0], rtol=1e-14)
+    a, b = N[1, 5] + N[0, 5], N[2, 5]
+    assert np.allclose(out[:, 5], [q0 * a, q1 * a + q0 * b, q23 * a + (1 - q0) * b], rtol=1e-14)
+    assert olo.tolist()[:6] == [2, 2, 0, 0, 6, 2]
+    assert use.tolist() == [True] * 6 + [False] * 3
+    ana, alo = orc.ionize_step(spec, E[6:], dt, N[:, 6:], lo[6:], w, eps)
+    assert np.array_equal(out[:, 6:], ana) and np.array_equal(olo[6:], alo)
+    # dt outside the trained range: the whole call is the analytic step
+    out, olo, use, _ = mlp.surrogate_step(orc, spec, Z, params, r, E, 5e-16, N, lo, w, eps, bf16_ops=False)
+    ana, alo = orc.ionize_step(spec, E, 5e-16, N, lo, w, eps)
+    assert not use.any() and np.array_equal(out, ana) and np.array_equal(olo, alo)

@@ -37,6 +37,7 @@ PINS = [
     ("projection ratio", lambda o: R.test_projection_ratio_closed_form(o, 2)),
     ("orbital factor", R.test_orbital_factor),
     ("field dependence", lambda o: R.test_field_dependence_at_noninteger_nstar(o, 40.74, 3, 1, 150.0, 900.0)),
+    ("integer n* closed forms", lambda o: R.test_integer_nstar_closed_forms(o, 300.0)),
     ("hydrogen step", lambda o: R.test_hydrogen_step_closed_form(o, 100.0)),
     ("one level", lambda o: C.test_single_level_closed_form(o, 0.7)),
     ("two levels, Eq. (7)", lambda o: C.test_two_level_eq7(o, 0.4, 1.3)),
@@ -51,11 +52,11 @@ PINS = [
 MUTANTS = [
     ("power exponent without |m|", "2.0 * ns - am - 1.0", "2.0 * ns - 1.0"),
     ("tunnelling factor with (Q/n*)^2", "pow((double)Q / ns, 3.0)", "pow((double)Q / ns, 2.0)"),
-    pytest.param("square-root factor without n*^3", "sqrt(3.0 * n3 * EL / (M_PI * Q3 * E_a))",
-                 "sqrt(3.0 * EL / (M_PI * Q3 * E_a))",
-                 marks=pytest.mark.xfail(strict=True, reason="parity unpinned: the field-independent factor's "
-                                         "dependence on non-integer n* (n* = 1 and the charge scaling law at "
-                                         "fixed n* leave it free)")),
+    ("square-root factor without n*^3", "sqrt(3.0 * n3 * EL / (M_PI * Q3 * E_a))",
+     "sqrt(3.0 * EL / (M_PI * Q3 * E_a))"),
+    ("angular factor without n*", "(2.0 * M_PI * ns * pow(2.0, am)", "(2.0 * M_PI * pow(2.0, am)"),
+    ("Q^2/(2 n*) instead of Q^2/(2 n*^2)", "(double)Q * Q / (2.0 * ns * ns)", "(double)Q * Q / (2.0 * ns)"),
+    ("Stirling factor to the power n*", "pow(2.0 * M_E / ns, 2.0 * ns)", "pow(2.0 * M_E / ns, ns)"),
     ("Q instead of Q^2", "(double)Q * Q / (2.0 * ns * ns)", "(double)Q / (2.0 * ns * ns)"),
     ("e/n* instead of 2e/n*", "pow(2.0 * M_E / ns, 2.0 * ns)", "pow(M_E / ns, 2.0 * ns)"),
     ("l + 1 instead of 2l + 1", "(2.0 * l + 1.0) * orc_fact(l + am)", "(l + 1.0) * orc_fact(l + am)"),
@@ -168,6 +169,12 @@ MLP_MUTANTS = [
     ("weight gradient transposed", 'g["W2"] = dz2.T @ c["h1"]', 'g["W2"] = c["h1"].T @ dz2'),
     ("Adam without bias correction of m", "mh = m / (1.0 - beta1 ** t)", "mh = m"),
     ("band update drops the window top", "o[top] = N[top, c]", "o[top] = 0.0"),
+    ("field feature not centred", "- 0.5 * (lE0 + lE1)) / (0.5 * (lE1 - lE0))", "- lE0) / (0.5 * (lE1 - lE0))"),
+    ("stripped cells take the band", "use &= p < Z", "use &= p <= Z"),
+    ("negligible-source test reversed", "Q[:, x[s] < NEGLIGIBLE_XDT]", "Q[:, x[s] > NEGLIGIBLE_XDT]"),
+    ("field range open above", "(E <= rng.E_hi)", "(E <= 2 * rng.E_hi)"),
+    ("band applied before the shift", "band = band_update(N, p, w, Z, cols, use)",
+     "band = band_update(np.asarray(pops, np.float64), p, w, Z, cols, use)"),
 ]
 
 
@@ -189,7 +196,9 @@ def _failing_mlp_pins(orc, mod):
     pins = [M.test_bf16_rounding, M.test_backward_matches_finite_differences,
             M.test_adam_first_step_and_bias_correction, M.test_softmax_invariants,
             lambda: M.test_weight_layout_out_in(True),
-            lambda: M.test_band_update_with_exact_columns_is_the_step(orc, 3)]
+            lambda: M.test_band_update_with_exact_columns_is_the_step(orc, 3),
+            M.test_features_map_the_trained_range_onto_the_unit_interval,
+            lambda: M.test_surrogate_step_composition(orc)]
     saved = M.mlp
     M.mlp = mod
     failed = []

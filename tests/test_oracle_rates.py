@@ -136,3 +136,49 @@ def test_hydrogen_step_closed_form(orc, E):
     for c, n0 in enumerate((1.0, 0.25)):
         assert out[0, c] == pytest.approx(n0 * math.exp(-x), rel=1e-13)
         assert out[1, c] == pytest.approx(1.0 - n0 * math.exp(-x), rel=1e-13)
+
+
+def closed_form_nstar2(E, Q, l, am):
+    """Eq. (1) at n* = 2, simplified by hand for the two charges that give
+    n* = 2 exactly: Q = 1 with U = U_H/4 and Q = 2 with U = U_H.  With n* = 2
+    the factors are sqrt(24 E/(pi Q^3 E_a)), Q^2/8, e^4,
+    exp(-E_a Q^3/(12 E)), (2l+1)(l+|m|)!/(4 pi 2^|m| |m|! (l-|m|)!) and
+    (E_a Q^3/(4 E))^(3-|m|); below they are multiplied out per case."""
+    e = math.e
+    if Q == 1:
+        s = OMEGA_A * e ** 4 / (32 * math.pi) * math.sqrt(24 * E / (math.pi * E_A)) * (E_A / (4 * E)) ** 3 \
+            * math.exp(-E_A / (12 * E))
+        return {(0, 0): s, (1, 0): 3 * s, (1, 1): 3 * s * 4 * E / E_A}[(l, am)]
+    if Q == 2:
+        s = OMEGA_A * e ** 4 / (8 * math.pi) * math.sqrt(3 * E / (math.pi * E_A)) * (2 * E_A / E) ** 3 \
+            * math.exp(-2 * E_A / (3 * E))
+        return {(0, 0): s, (1, 0): 3 * s, (1, 1): 3 * s * E / (2 * E_A)}[(l, am)]
+    raise ValueError(Q)
+
+
+def closed_form_nstar3(E, l, am):
+    """Eq. (1) at n* = 3 (Q = 3, U = U_H), simplified by hand: the square-root
+    factor is sqrt(3E/(pi E_a)), Q^2/(2 n*^2) = 1/2, (2e/3)^6,
+    exp(-2 E_a/(3E)), angular factor (2l+1)(l+|m|)!/(6 pi 2^|m| |m|! (l-|m|)!)
+    and (2 E_a/E)^(5-|m|)."""
+    s = OMEGA_A * (2 * math.e / 3) ** 6 / (12 * math.pi) * math.sqrt(3 * E / (math.pi * E_A)) \
+        * (2 * E_A / E) ** 5 * math.exp(-2 * E_A / (3 * E))
+    r = E / (2 * E_A)
+    return {(0, 0): s, (1, 0): 3 * s, (1, 1): 3 * s * r, (2, 0): 5 * s, (2, 1): 15 * s * r,
+            (2, 2): 15 * s * r * r}[(l, am)]
+
+
+@pytest.mark.parametrize("E", [5.0, 40.0, 300.0, 2000.0])
+def test_integer_nstar_closed_forms(orc, E):
+    """The n* dependence of Eq. (1)'s field-independent factor: at n* = 2
+    (two charges) and n* = 3 every factor is an elementary number, and the
+    oracle must give the hand-simplified value (a factor n*^3 dropped from the
+    square root, a wrong power of 2e/n* or of n* in the angular factor all
+    move these by integer ratios)."""
+    for Q, U in ((1, U_H / 4), (2, U_H)):
+        for l, am in ((0, 0), (1, 0), (1, 1)):
+            assert orc.rate_lm(U, Q, l, am, E) == pytest.approx(closed_form_nstar2(E, Q, l, am), rel=1e-13)
+        want = (closed_form_nstar2(E, Q, 1, 0) + 2 * closed_form_nstar2(E, Q, 1, 1)) / 3
+        assert orc.level_rate(U, Q, 1, -1, E) == pytest.approx(want, rel=1e-13)
+    for l, am in ((0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)):
+        assert orc.rate_lm(U_H, 3, l, am, E) == pytest.approx(closed_form_nstar3(E, l, am), rel=1e-13)
