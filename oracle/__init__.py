@@ -68,6 +68,11 @@ def _load():
     lib.orc_ionize_step.argtypes = [ctypes.c_int, dp, i8p, i8p, dp, ctypes.c_int64, dp,
                                     ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_int, dp, u8p]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.orc_adaptive_step.restype = None
+    lib.orc_adaptive_step.argtypes = [ctypes.c_int, dp, i8p, i8p, dp, ctypes.c_int64, dp, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, u8p, u8p,
+                                      ip, ip, dp, dp]
     lib.orc_max_threads.restype = ctypes.c_int
     lib.orc_max_threads.argtypes = []
     _lib = lib
@@ -162,6 +167,37 @@ def ionize_step(gas: GasSpec, E, dt, pops, lo, w, eps, layout=0, consts=None):
                             float(eps), int(layout), _dp(pops),
                             lo.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
     return pops, lo
+
+
+def adaptive_step(gas: GasSpec, E, dt, pops, lo, wc, wmin, wmax, eps, tol, force_top=None, consts=None):
+    """One step with an adaptive window (see orc_adaptive_step): pops[(wmax+1)][n],
+    lo[n] and wc[n] (rates in each cell's window) in; returns (pops, lo, wc,
+    info) as new arrays, info = dict(top, leak_top, leak_below) per cell.
+    force_top[n] (optional, int): where >= 0, the top slot to take instead of
+    the leak criterion."""
+    E = np.ascontiguousarray(np.asarray(E, dtype=np.float64).ravel())
+    n = E.size
+    pops = np.array(pops, dtype=np.float64, order="C", copy=True)
+    lo = np.array(lo, dtype=np.uint8, order="C", copy=True).ravel()
+    wc = np.array(wc, dtype=np.uint8, order="C", copy=True).ravel()
+    assert pops.shape == (wmax + 1, n), (pops.shape, wmax, n)
+    assert lo.shape == (n,) and wc.shape == (n,)
+    assert 0 <= wmin <= wmax <= 63
+    top = np.zeros(n, np.int32)
+    lt = np.zeros(n)
+    lb = np.zeros(n)
+    ip = ctypes.POINTER(ctypes.c_int)
+    ft = None
+    if force_top is not None:
+        ft = np.ascontiguousarray(np.asarray(force_top, np.int32).ravel())
+        assert ft.shape == (n,)
+    c = _consts(consts)
+    u8 = ctypes.POINTER(ctypes.c_uint8)
+    _load().orc_adaptive_step(gas.Z, *gas._ptrs(), _dp(c), n, _dp(E), float(dt), int(wmin), int(wmax), float(eps),
+                              float(tol), _dp(pops), lo.ctypes.data_as(u8), wc.ctypes.data_as(u8),
+                              ft.ctypes.data_as(ip) if ft is not None else None, top.ctypes.data_as(ip),
+                              _dp(lt), _dp(lb))
+    return pops, lo, wc, dict(top=top, leak_top=lt, leak_below=lb)
 
 
 def max_threads() -> int:

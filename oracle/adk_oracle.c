@@ -237,6 +237,94 @@ void orc_ionize_step(int Z, const double *U, const int8_t *l, const int8_t *m,
     }
 }
 
+/*
+ * Bound on the population that passes slot t of a window during the step in
+ * the full chain (Eq. (3) with every level above the window present):
+ *     leak(t) = sum_{s <= t, N_s != 0} N_s x_s x_{s+1} ... x_t / (t - s + 1)!,
+ * x_k = W_{p+k} dt.  A particle that starts at slot s has passed slot t once
+ * the t - s + 1 exponential waiting times of slots s..t sum to at most dt,
+ * and that probability is at most prod x / (t - s + 1)! (the density of such
+ * a sum is at most prod W u^(n-1)/(n-1)!).  The window with its top at slot t
+ * holds that population back (Sec. 3: the top absorbs), and changes nothing
+ * below slot t, so leak(t) bounds its difference from the full chain.
+ */
+static double orc_leak(const double *N, const double *x, int t)
+{
+    double L = 0.0;
+    for (int s = 0; s <= t; ++s) {
+        if (N[s] == 0.0) continue;
+        double term = N[s];
+        for (int k = s; k <= t; ++k) term *= x[k];
+        L += term / orc_fact(t - s + 1);
+    }
+    return L;
+}
+
+/*
+ * One step with an adaptive window: the reduced system of Sec. 3 ("specified
+ * independently for each computational cell"), here with a top that moves up
+ * per cell and step so that the population the absorbing top holds back
+ * stays below tol.
+ *   pops[(wmax+1)][ncells]: slot s holds level p + s for s <= wc (slots above
+ *     wc are read as zero and written as zero);
+ *   p[ncells]: lowest window level (values above Z read as Z);
+ *   wc[ncells]: rates in the window (its top is slot wc).
+ * Per cell:
+ *   1. window shift at the start of the step (as orc_ionize_step); the top
+ *      level stays, so wc drops by the number of shifts (not below 0);
+ *   2. t0 = min(max(wmin, wc), Z - p);
+ *   3. top = t0, then while top < min(wmax, Z - p) and not leak(top) <= tol:
+ *      top += 1 (a NaN leak widens);
+ *   4. exact solve of the window [p, p + top], top absorbing;
+ *   5. slots 0..wmax stored (zero above top), wc = top.
+ * force_top (may be NULL): a value >= 0 replaces step 3 for that cell.
+ * top_out, leak_top, leak_below (may be NULL): the top taken, leak at it,
+ * and leak one slot lower (-1 when top == t0).
+ */
+void orc_adaptive_step(int Z, const double *U, const int8_t *l, const int8_t *m, const double *consts,
+                       int64_t ncells, const double *E, double dt, int wmin, int wmax, double eps, double tol,
+                       double *pops, uint8_t *p, uint8_t *wc, const int *force_top, int *top_out,
+                       double *leak_top, double *leak_below)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t c = 0; c < ncells; ++c) {
+        double N[ORC_MAXN], x[ORC_MAXN], W[ORC_MAXN];
+        for (int k = 0; k < ORC_MAXN; ++k) N[k] = 0.0;
+        int lo = p[c] > Z ? Z : p[c];
+        int w = wc[c] > wmax ? wmax : wc[c];
+        for (int s = 0; s <= w; ++s)
+            if (lo + s <= Z) N[s] = pops[(int64_t)s * ncells + c];
+        /* window shift at the start of the step, residual folded upward */
+        while (lo < Z && N[0] < eps) {
+            N[1] += N[0];
+            for (int s = 0; s < wmax; ++s) N[s] = N[s + 1];
+            N[wmax] = 0.0;
+            ++lo;
+            w = w > 0 ? w - 1 : 0;
+        }
+        const int room = Z - lo < wmax ? Z - lo : wmax;
+        int t0 = w > wmin ? w : wmin;
+        if (t0 > Z - lo) t0 = Z - lo;
+        for (int k = 0; k <= room && lo + k < Z; ++k) {
+            W[k] = orc_level_rate(U[lo + k], lo + k + 1, l[lo + k], m[lo + k], E[c], consts);
+            x[k] = W[k] * dt;
+        }
+        int top = t0;
+        if (force_top && force_top[c] >= 0) {
+            top = force_top[c];
+        } else {
+            while (top < room && !(orc_leak(N, x, top) <= tol)) ++top;
+        }
+        if (top_out) top_out[c] = top;
+        if (leak_top) leak_top[c] = lo + top < Z ? orc_leak(N, x, top) : 0.0;
+        if (leak_below) leak_below[c] = top > t0 ? orc_leak(N, x, top - 1) : -1.0;
+        orc_advance_window(top + 1, W, dt, N);
+        for (int s = 0; s <= wmax; ++s) pops[(int64_t)s * ncells + c] = s <= top ? N[s] : 0.0;
+        p[c] = (uint8_t)lo;
+        wc[c] = (uint8_t)top;
+    }
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP

@@ -30,6 +30,7 @@ def _load_path(name, path):
 R = _load_path("pins_rates", os.path.join(HERE, "test_oracle_rates.py"))
 C = _load_path("pins_chain", os.path.join(HERE, "test_oracle_chain.py"))
 W = _load_path("pins_window", os.path.join(HERE, "test_oracle_window.py"))
+A = _load_path("pins_adaptive", os.path.join(HERE, "test_oracle_adaptive.py"))
 
 PINS = [
     ("hydrogen closed form", lambda o: R.test_hydrogen_closed_form(o, 100.0)),
@@ -46,6 +47,11 @@ PINS = [
     ("shift with fold", W.test_shift_folds_residual_and_moves_window),
     ("window = full chain", lambda o: W.test_window_equals_full_chain_when_it_covers_the_rest(o, 7, 7)),
     ("conservation over a pulse", W.test_conservation_and_nonnegativity_over_a_pulse),
+    ("adaptive: zero tolerance = full chain", lambda o: A.test_zero_tolerance_is_the_full_chain(o, 7)),
+    ("adaptive: fixed width = fixed window", lambda o: A.test_fixed_width_is_the_fixed_window(o, 3)),
+    ("adaptive: leak bounds the full chain", lambda o: A.test_leak_bounds_what_the_full_chain_moves_past_the_top(o, 1e-6)),
+    ("adaptive: leak closed forms", A.test_leak_closed_forms),
+    ("adaptive: shift lowers the width", A.test_shift_lowers_the_width_and_keeps_the_top_level),
 ]
 
 # (name, original text, planted text); the original must occur exactly once
@@ -68,6 +74,14 @@ MUTANTS = [
     ("level k ionized at charge k", "W[k - lo] = orc_level_rate(U[k], k + 1,", "W[k - lo] = orc_level_rate(U[k], k + 2,"),
     ("window one level short", "const int top = lo + w < Z ? lo + w : Z;",
      "const int top = lo + w - 1 < Z ? lo + w - 1 : Z;"),
+    ("adaptive: leak without the factorial", "L += term / orc_fact(t - s + 1);", "L += term;"),
+    ("adaptive: leak misses the top rate", "for (int k = s; k <= t; ++k) term *= x[k];",
+     "for (int k = s; k < t; ++k) term *= x[k];"),
+    ("adaptive: widening test reversed", "while (top < room && !(orc_leak(N, x, top) <= tol)) ++top;",
+     "while (top < room && (orc_leak(N, x, top) <= tol)) ++top;"),
+    ("adaptive: width kept at a shift", "w = w > 0 ? w - 1 : 0;", "w = w > 0 ? w : 0;"),
+    ("adaptive: top slot dropped", "pops[(int64_t)s * ncells + c] = s <= top ? N[s] : 0.0;",
+     "pops[(int64_t)s * ncells + c] = s < top ? N[s] : 0.0;"),
 ]
 
 
