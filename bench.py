@@ -6,12 +6,15 @@ population of a cell's active window advanced by one step (sum over cells
 of top - lo + 1), for the mixed-precision path, next to the plain FP64 path
 on the same GPU and the CPU oracle on the host.
 
-Headline workload: the 2D laser-pulse mesh (1024 x 1024 cells, 18-level
-synthetic chain, window of 4 populations, w = 3, 2000 steps of 0.05 laser
-periods).  The timed region is K consecutive steps of that run (default: the
-whole run), with the field of every step already resident in device memory.
-A second, HBM-bound workload (the 256 x 256 x 512 3D mesh, 36 levels,
-m-averaged) is measured as well and reported under "mesh3d".
+Headline workload: the 3D laser-pulse mesh (256 x 256 x 512 = 33,554,432
+cells, 36-level synthetic chain with m-averaged rates, window of 4
+populations, w = 3, 500 steps of 0.05 laser periods), the largest
+single-GPU configuration and the one whose state (1.3 GB per step) streams
+from HBM.  The pulse is run in from neutral cells for 200 steps (untimed),
+then K consecutive steps (default 300, the rest of the run) are timed as one
+replay of a HIP graph, with the field of every step already resident in
+device memory.  The 2D mesh (1024 x 1024 cells, 18 levels), whose state
+stays in the 256 MB Infinity Cache, is reported under "mesh2d".
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -37,11 +40,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(key):
-    """HBM bytes per launch of the headline kernel from the committed byte-counter
-    summary, or None when the step kernel's sources changed since it was taken."""
+PROFILE_3D_BYTES = "step_compact_w3_mesh3d_bytes.txt"
+PROFILE_2D_BYTES = "step_compact_mixed_w3_mesh2d_bytes.txt"
+
+
+def measured_traffic(key, profile=PROFILE_3D_BYTES):
+    """HBM bytes per launch of a step kernel from a committed byte-counter
+    summary under profiles/, or None when the step kernel's sources changed
+    since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "step_compact_mixed_w3_mesh2d_bytes.txt")
+    path = os.path.join(ROOT, "profiles", profile)
     csrc = os.path.join(ROOT, "paper_2202_10647_amd", "csrc")
     try:
         vals = {}
@@ -186,68 +194,267 @@ def parity_check(ak, orc, gas, spec, mesh, w, eps, step, seed):
                                    lo[sample], w, eps)
         yref = orc.electron_yield(P[:, sample].astype(np.float64), lo[sample], ref, rlo, spec.Z)
         out[prec] = dict(max_abs_err=float(np.max(np.abs(g - ref))), lo_mismatch=int(np.sum(gl != rlo)),
-                         cells=int(sample.size), electron_yield_max_abs_err=float(np.max(np.abs(gy - yref))))
+                         cells=int(sample.size), electron_yield_max_abs_err=float(np.max(np.abs(gy - yref))),
+                         per_level_max_abs_err=per_level_error(g, gl, ref, rlo, spec.Z))
         log(f"[parity] {prec}: max |dN| = {out[prec]['max_abs_err']:.2e} over {sample.size} cells, "
             f"lo mismatches {out[prec]['lo_mismatch']}, electron yield max err "
             f"{out[prec]['electron_yield_max_abs_err']:.2e}")
     return out
 
 
+def _probe_rate(fn, probe):
+    t = time.perf_counter()
+    fn(probe)
+    return probe / max(time.perf_counter() - t, 1e-6)
+
+
 def cpu_baseline(orc, spec, mesh, w, eps, step, seed, target_s):
-    """The oracle as it stands, on the host cores: one ionize_step over a
-    bounded sample of the mesh cells (sized for about target_s seconds)."""
+    """The oracle as it stands, on the host cores, on the 2D mesh: one
+    ionize_step over a bounded sample of the mesh cells (sized for about
+    target_s seconds) from a seeded random window state."""
     from paper_2202_10647_amd import workloads as wl
     n = mesh.ncells
     E = mesh.field(step)
     comp, lo = wl.random_window_state(n, spec.Z, w, seed=seed)
-    probe = 8192
-    t = time.perf_counter()
-    orc.ionize_step(spec, E[:probe], mesh.dt, comp[:, :probe], lo[:probe], w, eps)
-    rate = probe / max(time.perf_counter() - t, 1e-6)
-    m = int(min(n, max(probe, rate * target_s)))
+    rate = _probe_rate(lambda m: orc.ionize_step(spec, E[:m], mesh.dt, comp[:, :m], lo[:m], w, eps), 8192)
+    m = int(min(n, max(8192, rate * target_s)))
     t = time.perf_counter()
     _, lo2 = orc.ionize_step(spec, E[:m], mesh.dt, comp[:, :m], lo[:m], w, eps)
     el = time.perf_counter() - t
     units = int(np.sum(np.minimum(lo2.astype(np.int64) + w, spec.Z) - lo2.astype(np.int64) + 1))
-    log(f"[cpu] oracle: {m} cells in {el:.2f} s on {orc.max_threads()} threads")
+    log(f"[cpu] oracle, 2D mesh: {m} cells in {el:.2f} s on {orc.max_threads()} threads")
     return dict(value=units / el, unit="cell·level updates/s", cores=orc.max_threads(), kind="oracle",
+                workload=f"laser2d_1024x1024_Z{spec.Z}_w{w}",
                 sample=f"one ionize_step (w={w}, {spec.Z} levels, FP64 rates, binary128 expm) over the first "
                        f"{m} cells of the {mesh.shape[0]}x{mesh.shape[1]} mesh at t={step} dt from a seeded "
                        f"random window state; OpenMP over cells; {el:.1f} s")
 
 
-def mesh3d_measure(ak, gas36, w, eps, steps, warmup):
-    """HBM-bound workload: 33.5M cells, 36 levels, m averaged, mixed and FP64."""
+def cpu_baseline_3d(orc, spec36, mesh, mid_state, w, eps, seed, target_s):
+    """The oracle on the headline workload: one ionize_step of a seeded random
+    sample of the 3D mesh's cells, from the run state the GPU read before the
+    middle timed step (float32 bits widened to double), sized for about
+    target_s seconds of host time."""
+    E, P, lo, step = mid_state
+    n = mesh.ncells
+    perm = np.random.default_rng(seed).permutation(n)
+
+    def run(m):
+        idx = np.sort(perm[:m])
+        return orc.ionize_step(spec36, E[idx], mesh.dt, P[:, idx], lo[idx], w, eps)
+
+    rate = _probe_rate(run, 16384)
+    m = int(min(n, max(16384, rate * target_s)))
+    t = time.perf_counter()
+    _, lo2 = run(m)
+    el = time.perf_counter() - t
+    units = int(np.sum(np.minimum(lo2.astype(np.int64) + w, spec36.Z) - lo2.astype(np.int64) + 1))
+    log(f"[cpu] oracle, 3D mesh: {m} cells in {el:.2f} s on {orc.max_threads()} threads")
+    return dict(value=units / el, unit="cell·level updates/s", cores=orc.max_threads(), kind="oracle",
+                workload=f"laser3d_256x256x512_Z36mavg_w{w}",
+                sample=f"plain oracle (FP64 rates, binary128 expm, OpenMP over cells): one ionize_step (w={w}, 36 "
+                       f"levels m averaged) of {m} randomly sampled cells of the 256x256x512 mesh from the run state "
+                       f"before step {step} (the bits the GPU read); {el:.1f} s")
+
+
+def cpu_baseline_chain7(orc, target_s):
+    """The oracle on the 7-level chain workload: 4096 cells, full chain w = 7,
+    fields log-uniform in [10, 2000] GV/m, dt = 0.1 fs, neutral cells; the
+    4096-cell step repeated for about target_s seconds."""
+    from paper_2202_10647_amd import workloads as wl
+    g = wl.synthetic_gas(7)
+    spec = orc.GasSpec(g.U, g.l, g.m)
+    n, w, dt = 4096, 7, 1e-16
+    E = wl.loguniform_field(n, 10.0, 2000.0, seed=1)
+    P, lo = wl.neutral_state(n, w + 1)
+    reps, el = 0, 0.0
+    t = time.perf_counter()
+    while el < target_s or reps == 0:
+        orc.ionize_step(spec, E, dt, P, lo, w, 0.0)
+        reps += 1
+        el = time.perf_counter() - t
+    units = reps * n * (w + 1)
+    log(f"[cpu] oracle, 7-level chain: {reps} x {n} cells in {el:.2f} s")
+    return dict(value=units / el, unit="cell·level updates/s", cores=orc.max_threads(), kind="oracle",
+                workload="chain7_4096_cells_full_chain",
+                sample=f"plain oracle: {reps} repetitions of one full-chain step (w = 7) of all {n} cells; {el:.1f} s")
+
+
+def cpu_baseline_batched(orc, ncells, target_s, seed=4):
+    """The oracle on the batched mixed-gas workload: one step of a seeded
+    random sample of its cells (host gas and dopants as they occur), from the
+    seeded window states and hashed field of the GPU parity check."""
+    from paper_2202_10647_amd import workloads as wl
+    tables = [wl.synthetic_gas(z) for z in (1,) + wl.DOPANT_Z]
+    specs = [orc.GasSpec(t.U, t.l, t.m) for t in tables]
+    cell_gas, cell_w = wl.batched_cells(ncells, seed=seed)
+    perm = np.random.default_rng(seed + 1).permutation(ncells)
+    dt = 1.334e-16
+    E_all = wl.hash_field(ncells, 99, 7)
+
+    def run(m):
+        idx = np.sort(perm[:m])
+        cg, cw = cell_gas[idx], cell_w[idx]
+        pops, lo = wl.plan_window_state(cg, cw, [t.Z for t in tables], 7, seed=31)
+        E = E_all[idx]
+        t = time.perf_counter()
+        units = 0
+        for gi, spec in enumerate(specs):
+            for w in range(1, 7):
+                sel = np.nonzero((cg == gi) & (cw == w))[0]
+                if sel.size == 0:
+                    continue
+                _, l2 = orc.ionize_step(spec, E[sel], dt, pops[: w + 1, sel], lo[sel], w, 1e-8)
+                units += int(np.sum(np.minimum(l2.astype(np.int64) + w, spec.Z) - l2.astype(np.int64) + 1))
+        return time.perf_counter() - t, units
+
+    el, _ = run(65536)
+    m = int(min(ncells, max(65536, 65536 / max(el, 1e-6) * target_s)))
+    el, units = run(m)
+    log(f"[cpu] oracle, batched mixed gases: {m} cells in {el:.2f} s")
+    return dict(value=units / el, unit="cell·level updates/s", cores=orc.max_threads(), kind="oracle",
+                workload=f"batched_{ncells}_cells_1pct_dopants_Z7_18_36_54_w1to6",
+                sample=f"plain oracle: one step of {m} randomly sampled cells of the {ncells}-cell mixed-gas mesh "
+                       f"(per (gas, w) group), seeded window states; {el:.1f} s")
+
+
+def full_levels_np(P, lo, Z):
+    """Compact windows P[w+1][n] at lo -> populations of every level [Z+1][n]."""
+    w = P.shape[0] - 1
+    n = P.shape[1]
+    full = np.zeros((Z + 1, n))
+    l64 = np.minimum(np.asarray(lo, np.int64), Z)
+    cols = np.arange(n)
+    for s_ in range(w + 1):
+        k = l64 + s_
+        ok = k <= Z
+        np.add.at(full, (k[ok], cols[ok]), np.asarray(P[s_], np.float64)[ok])
+    return full
+
+
+def per_level_error(got, glo, ref, rlo, Z):
+    """max over cells of |dN_k| for every level k = 0..Z (windows mapped to
+    their levels on each side)."""
+    d = np.abs(full_levels_np(got, glo, Z) - full_levels_np(ref, rlo, Z))
+    return [float(v) for v in d.max(axis=1)]
+
+
+def sampled_parity(ak, orc, gas, spec, E_np, P_np, lo_np, dt, w, eps, sample, prec, Z):
+    """One ionize_step call on the device from the given state (all cells),
+    sampled cells recomputed by the oracle from the same input bits; returns
+    the max error, the per-level max error and the window-index mismatches."""
+    import torch
+    npdt = np.float32 if prec == "mixed" else np.float64
+    E = E_np.astype(npdt)
+    P = P_np.astype(npdt)
+    Pt, Lt = torch.from_numpy(P).cuda(), torch.from_numpy(lo_np.copy()).cuda()
+    ak.ionize_step(gas, torch.from_numpy(E).cuda(), dt, Pt, Lt, w=w, eps=eps)
+    idx = torch.from_numpy(sample).cuda()
+    g = Pt[:, idx].cpu().numpy().astype(np.float64)
+    gl = Lt[idx].cpu().numpy()
+    del Pt, Lt
+    ref, rlo = orc.ionize_step(spec, E[sample].astype(np.float64), dt, P[:, sample].astype(np.float64),
+                               lo_np[sample], w, eps)
+    return dict(max_abs_err=float(np.max(np.abs(g - ref))), lo_mismatch=int(np.sum(gl != rlo)),
+                cells=int(sample.size), per_level_max_abs_err=per_level_error(g, gl, ref, rlo, Z))
+
+
+def headline_3d(ak, orc, gas36, spec36, mesh, K, warmup, w, eps, t0=200, parity_cells=65536, seed=2031):
+    """The headline: K consecutive steps of the 3D pulse run (33.5M cells,
+    36 levels, w = 3), mixed precision and FP64.  Per precision: fields of
+    steps t0..t0+K-1 resident on the device; the pulse run in from neutral
+    cells over steps 0..t0-1 (untimed, eager); `warmup` untimed eager steps
+    from that state on a copy; the K steps captured in one HIP graph, replayed
+    once untimed and once timed (HIP events on the replay stream) from the
+    run-in state; an untimed eager pass counts the window populations of
+    every step.  Parity: one call from the run state at the middle of the
+    timed steps and one from a seeded random window state, 65,536 sampled
+    cells recomputed by the oracle from the same bits, per-level errors."""
     import torch
     from paper_2202_10647_amd import workloads as wl
-    mesh = wl.mesh_3d()
     n = mesh.ncells
-    t_first = 200
-    res = {}
+    Z = 36
+    t0 = min(t0, max(0, mesh.steps - K))
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(n, min(n, parity_cells), replace=False))
+    res = {"workload": f"laser3d_256x256x512_Z36mavg_w{w}", "cells": n, "levels": Z, "window_w": w, "eps": eps,
+           "t0": t0, "timed_steps": f"steps {t0}..{t0 + K - 1} of the {mesh.steps}-step run, after {t0} steps "
+                                     f"of run-in from neutral cells"}
+    stream = torch.cuda.current_stream()
     for prec, tdt in (("mixed", torch.float32), ("f64", torch.float64)):
-        fields = torch.empty((steps, n), dtype=tdt, device="cuda")
-        for i in range(steps):
-            fields[i] = mesh.field_torch(t_first + i, "cuda", tdt)
+        fields = torch.empty((K, n), dtype=tdt, device="cuda")
+        for i in range(K):
+            fields[i] = mesh.field_torch(t0 + i, "cuda", tdt)
         p = torch.zeros((w + 1, n), dtype=tdt, device="cuda")
         p[0] = 1.0
         lo = torch.zeros(n, dtype=torch.uint8, device="cuda")
-        for i in range(min(warmup, t_first)):  # run the pulse in (untimed)
-            ak.ionize_step(gas36, mesh.field_torch(i, "cuda", tdt), mesh.dt, p, lo, w=w, eps=eps)
-        total, avg, _ = run_steps(ak, gas36, fields, mesh.dt, p, lo, w, eps, per_launch=True)
-        # the window index only grows, so the final index bounds every step's
-        # window from below (exact while lo <= Z - w, which holds here)
-        units = window_units(lo, w, 36) * steps
-        value = units / (total * 1e-3)
-        gbps = bytes_per_cell(w, prec) * n / (avg * 1e-3) / 1e9
-        res[prec] = dict(value=value, ms_per_step=total / steps, kernel_ms=avg, achieved_gbps=gbps,
-                         frac_hbm=gbps / HBM_PEAK_GBPS)
-        log(f"[mesh3d] {prec}: {total / steps * 1e3:.1f} us/step, kernel {avg * 1e3:.1f} us, {value:.3e} "
-            f"cell-level/s, {gbps:.0f} GB/s ({gbps / HBM_PEAK_GBPS:.2f} of HBM peak)")
-        del fields, p, lo
+        for t in range(t0):
+            ak.ionize_step(gas36, mesh.field_torch(t, "cuda", tdt), mesh.dt, p, lo, w=w, eps=eps)
+        p0, l0 = p.clone(), lo.clone()
+
+        def restore():
+            p.copy_(p0)
+            lo.copy_(l0)
+            torch.cuda.synchronize()
+
+        for i in range(min(warmup, K)):
+            ak.ionize_step(gas36, fields[i], mesh.dt, p, lo, w=w, eps=eps)
+        restore()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for i in range(K):
+                ak.ionize_step(gas36, fields[i], mesh.dt, p, lo, w=w, eps=eps)
+        restore()
+        graph.replay()  # warm replay
+        restore()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        graph.replay()
+        b.record(stream)
+        torch.cuda.synchronize()
+        total_ms = a.elapsed_time(b)
+        del graph
+        # untimed eager pass: window populations advanced per step, and the
+        # run state at the middle of the timed steps for the parity check
+        restore()
+        units = 0
+        mid = K // 2
+        for i in range(K):
+            if i == mid:
+                mid_state = (fields[i].cpu().numpy().astype(np.float64), p.cpu().numpy().astype(np.float64),
+                             lo.cpu().numpy())
+            ak.ionize_step(gas36, fields[i], mesh.dt, p, lo, w=w, eps=eps)
+            units += window_units(lo, w, Z)  # the window after the step's start-of-step shift
+        torch.cuda.synchronize()
+        max_lo = int(lo.max().item())
+        del fields, p, lo, p0, l0
         torch.cuda.empty_cache()
+        ms = total_ms / K
+        gbps = bytes_per_cell(w, prec) * n / (ms * 1e-3) / 1e9
+        r = dict(value=units / (total_ms * 1e-3), ms_per_step=ms, kernel_avg_us=ms * 1e3, units=units,
+                 achieved_gbps=gbps, frac_hbm=gbps / HBM_PEAK_GBPS, max_lo=max_lo,
+                 bytes_per_cell=bytes_per_cell(w, prec))
+        log(f"[mesh3d] {prec}: {ms * 1e3:.1f} us/step (graph of {K} steps), {r['value']:.3e} cell-level/s, "
+            f"{gbps:.0f} GB/s algorithmic ({gbps / HBM_PEAK_GBPS:.2f} of 8 TB/s), max lo {max_lo}")
+        # parity from the run state (the bits the timed steps read) and from a
+        # seeded random window state (every window position, shifts due)
+        E_mid, P_mid, l_mid = mid_state
+        r["parity_run_state"] = sampled_parity(ak, orc, gas36, spec36, E_mid, P_mid, l_mid, mesh.dt, w, eps,
+                                               sample, prec, Z)
+        r["parity_run_state"]["state"] = f"run state before step {t0 + mid}"
+        comp, lr = wl.random_window_state(n, Z, w, seed=seed + 1)
+        r["parity_random_state"] = sampled_parity(ak, orc, gas36, spec36, E_mid, comp, lr, mesh.dt, w, eps,
+                                                  sample, prec, Z)
+        r["parity_random_state"]["state"] = f"seeded random window states, field of step {t0 + mid}"
+        if prec == "mixed":
+            res["_mid_state"] = (E_mid, P_mid, l_mid, t0 + mid)
+        del comp, lr, mid_state
+        for key in ("parity_run_state", "parity_random_state"):
+            q = r[key]
+            log(f"[mesh3d] {prec} parity ({q['state']}): max |dN| {q['max_abs_err']:.2e} over {q['cells']} "
+                f"cells, lo mismatches {q['lo_mismatch']}")
+        res[prec] = r
     res["speedup_mixed_vs_f64"] = res["mixed"]["value"] / res["f64"]["value"]
-    res["workload"] = "laser3d_256x256x512_Z36mavg_w3"
-    res["timed_steps"] = f"{steps} steps from t={t_first} dt"
     return res
 
 
@@ -667,16 +874,25 @@ def surrogate_measure(ak, orc, gas36, spec36, w, eps, steps, train_iters, nsampl
     ref, rlo = orc.ionize_step(spec36, E32[sample].astype(np.float64), mesh.dt, P32[:, sample].astype(np.float64),
                                lo0[sample], w, eps)
     d_or = np.abs(g - ref).max(axis=0)
+    gl = Ls[idx].cpu().numpy()
     res["error_vs_fp64"] = dict(
         oracle_sample=dict(cells=int(sample.size), max_abs=float(d_or.max()), mean_abs=float(d_or.mean()),
                            p99=float(np.quantile(d_or, 0.99)),
-                           lo_mismatch=int(np.sum(Ls[idx].cpu().numpy() != rlo))),
+                           lo_mismatch=int(np.sum(gl != rlo)),
+                           per_level_max_abs_err=per_level_error(g, gl, ref, rlo, 36)),
         gpu_fp64_all_cells=dict(cells=n, max_abs=float(dfull.max()), mean_abs=float(dfull.mean()),
                                 in_range_cells=int(active.sum()),
                                 max_abs_in_range=float(dfull[active].max()) if bool(active.any()) else 0.0),
         state="seeded random window states, field of step %d" % step)
     log(f"[surrogate] one call vs FP64: oracle sample max {d_or.max():.2e} mean {d_or.mean():.2e}; "
         f"GPU FP64 all cells max {float(dfull.max()):.2e} mean {float(dfull.mean()):.2e}")
+    # the method without the network on the same cells: the mixed analytic step
+    Pm, Lm = torch.from_numpy(P32.copy()).cuda(), torch.from_numpy(lo0.copy()).cuda()
+    ak.ionize_step(gas36, torch.from_numpy(E32).cuda(), mesh.dt, Pm, Lm, w=w, eps=eps)
+    gm, glm = Pm[:, idx].cpu().numpy().astype(np.float64), Lm[idx].cpu().numpy()
+    res["error_vs_fp64"]["mixed_analytic_same_cells"] = dict(
+        max_abs=float(np.abs(gm - ref).max()), per_level_max_abs_err=per_level_error(gm, glm, ref, rlo, 36))
+    del Pm, Lm
     del Ps, Ls, Pf, Lf, p, lo
     net.close()
     torch.cuda.empty_cache()
@@ -769,8 +985,10 @@ def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
         pre_p, pre_l, e_s = pops0[:, samp], lo0[samp], E0[samp]
         del pops0
         err, mism = 0.0, 0
+        per_level = {}
         for gi, t in enumerate(tables):
             spec = orc.GasSpec(t.U, t.l, t.m)
+            lv = np.zeros(t.Z + 1)
             for w in range(1, 7):
                 sel = np.nonzero((cell_gas[samp] == gi) & (cell_w[samp] == w))[0]
                 if sel.size == 0:
@@ -779,8 +997,11 @@ def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
                                            pre_p[: w + 1, sel].astype(np.float64), pre_l[sel], w, 1e-8)
                 err = max(err, float(np.max(np.abs(out[: w + 1, sel] - ref))))
                 mism += int(np.sum(l2[sel] != rlo))
+                lv = np.maximum(lv, per_level_error(out[: w + 1, sel], l2[sel], ref, rlo, t.Z))
+            per_level[f"Z{t.Z}"] = [float(v) for v in lv]
         res[prec]["parity_max_abs_err"] = err
         res[prec]["parity_lo_mismatch"] = mism
+        res[prec]["per_level_max_abs_err"] = per_level
         log(f"[batched] {prec} parity on {samp.size} sampled cells (seeded state, host field): "
             f"max |dN| {err:.2e}, lo mismatches {mism}")
         del g_all, g_field, P, L, E
@@ -853,15 +1074,17 @@ def measure_ceilings(ak):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=300, help="timed steps of the 3D run (after the run-in)")
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--window", type=int, default=3)
     ap.add_argument("--eps", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--no-mesh3d", action="store_true")
-    ap.add_argument("--mesh3d-steps", type=int, default=40)
+    ap.add_argument("--no-mesh2d", action="store_true")
+    ap.add_argument("--mesh2d-steps", type=int, default=2000)
+    ap.add_argument("--yield-steps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-extra-seconds", type=float, default=3.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--batched-cells", type=int, default=1 << 24)
@@ -903,55 +1126,100 @@ def main():
         del src, dst
 
     w, eps = args.window, args.eps
-    mesh = wl.mesh_2d()
-    K = min(args.steps, mesh.steps)
+    mesh3 = wl.mesh_3d()
+    K = max(1, min(args.steps, mesh3.steps))
+    g36 = wl.synthetic_gas(36)
+    gas36 = adkion.Gas.from_table(g36)
+    spec36 = oracle.GasSpec(g36.U, g36.l, g36.m)
+    n3 = mesh3.ncells
+    log(f"[setup] 3D mesh {n3} cells, Z=36 m-averaged, w={w}, {K} timed steps, fields resident in HBM")
+    head = headline_3d(adkion, oracle, gas36, spec36, mesh3, K, args.warmup, w, eps)
+    mid_state = head.pop("_mid_state")
+
+    # the 2D mesh (cache-resident working set), formerly the headline
+    mesh2 = wl.mesh_2d()
     g18 = wl.synthetic_gas(18)
     gas = adkion.Gas.from_table(g18)
     spec = oracle.GasSpec(g18.U, g18.l, g18.m)
-    n = mesh.ncells
-
-    log(f"[setup] {n} cells, Z=18, w={w}, {K} timed steps, fields resident in HBM")
-    f64 = torch.empty((K, n), dtype=torch.float64, device="cuda")
-    for t in range(K):
-        f64[t] = mesh.field_torch(t, "cuda", torch.float64)
-    f32 = f64.to(torch.float32)
-
-    res = {}
-    res["mixed"] = measure_path(adkion, gas, mesh, f32, "mixed", w, eps, 18, args.warmup, "mesh2d")
-    res["f64"] = measure_path(adkion, gas, mesh, f64, "f64", w, eps, 18, args.warmup, "mesh2d")
-    del f64, f32
-    torch.cuda.empty_cache()
-
-    parity = None if args.no_parity else parity_check(adkion, oracle, gas, spec, mesh, w, eps, 1000, 2024)
-    subcycle = None if args.no_subcycle else subcycle_measure(adkion, oracle, gas, spec, mesh, w, eps, 1000, 2025)
-    study = None if args.no_study else window_study(adkion, mesh, eps)
+    mesh2d = None
+    if not args.no_mesh2d:
+        K2 = min(args.mesh2d_steps, mesh2.steps)
+        f64 = torch.empty((K2, mesh2.ncells), dtype=torch.float64, device="cuda")
+        for t in range(K2):
+            f64[t] = mesh2.field_torch(t, "cuda", torch.float64)
+        f32 = f64.to(torch.float32)
+        mesh2d = {"workload": f"laser2d_1024x1024_Z18_w{w}", "cells": mesh2.ncells,
+                  "note": "state (~25 MB) resident in the 256 MB Infinity Cache: a cache-resident measurement",
+                  "timed_steps": f"steps 0..{K2 - 1} of the {mesh2.steps}-step run"}
+        mesh2d["mixed"] = measure_path(adkion, gas, mesh2, f32, "mixed", w, eps, 18, args.warmup, "mesh2d")
+        mesh2d["f64"] = measure_path(adkion, gas, mesh2, f64, "f64", w, eps, 18, args.warmup, "mesh2d")
+        mesh2d["speedup_mixed_vs_f64"] = mesh2d["mixed"]["value"] / mesh2d["f64"]["value"]
+        del f64, f32
+        torch.cuda.empty_cache()
+        if not args.no_parity:
+            mesh2d["parity"] = parity_check(adkion, oracle, gas, spec, mesh2, w, eps, 1000, 2024)
+    subcycle = None if args.no_subcycle else subcycle_measure(adkion, oracle, gas, spec, mesh2, w, eps, 1000, 2025)
+    study = None if args.no_study else window_study(adkion, mesh2, eps)
     study3d = None
     if not args.no_study and args.study3d_steps > 0:
-        study3d = window_study_3d(adkion, wl.mesh_3d(), eps, args.study3d_steps)
-    mesh3d = surrogate = None
-    if not (args.no_mesh3d and args.no_surrogate):
-        g36 = wl.synthetic_gas(36)
-        gas36 = adkion.Gas.from_table(g36)
-        if not args.no_mesh3d:
-            mesh3d = mesh3d_measure(adkion, gas36, w, eps, args.mesh3d_steps, 200)
-            mesh3d["electron_yield"] = yield_measure(adkion, gas36, w, eps, args.mesh3d_steps)
-        if not args.no_surrogate:
-            surrogate = surrogate_measure(adkion, oracle, gas36, oracle.GasSpec(g36.U, g36.l, g36.m), w, eps,
-                                          args.surrogate_steps, args.surrogate_train_iters)
-            if mesh3d:
-                surrogate["speedup_vs_fp64_analytic"] = surrogate["value"] / mesh3d["f64"]["value"]
-                surrogate["speedup_vs_mixed_analytic"] = surrogate["value"] / mesh3d["mixed"]["value"]
-        gas36.close()
+        study3d = window_study_3d(adkion, mesh3, eps, args.study3d_steps)
+    head["electron_yield"] = yield_measure(adkion, gas36, w, eps, args.yield_steps)
+    surrogate = None
+    if not args.no_surrogate:
+        surrogate = surrogate_measure(adkion, oracle, gas36, spec36, w, eps, args.surrogate_steps,
+                                      args.surrogate_train_iters)
+        surrogate["speedup_vs_fp64_analytic"] = surrogate["value"] / head["f64"]["value"]
+        surrogate["speedup_vs_mixed_analytic"] = surrogate["value"] / head["mixed"]["value"]
+    gas36.close()
     batched = None if args.no_batched else batched_measure(adkion, oracle, args.batched_steps, args.batched_cells)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(oracle, spec, mesh, w, eps, 1000, 7,
-                                                         args.cpu_seconds)
+    cpu = cpu_other = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_3d(oracle, spec36, mesh3, mid_state, w, eps, 7, args.cpu_seconds)
+        cpu_other = {"chain7_4096": cpu_baseline_chain7(oracle, args.cpu_extra_seconds),
+                     "mesh2d": cpu_baseline(oracle, spec, mesh2, w, eps, 1000, 7, args.cpu_extra_seconds),
+                     "batched": cpu_baseline_batched(oracle, args.batched_cells, args.cpu_extra_seconds),
+                     "nproc": os.cpu_count()}
+    del mid_state
 
     ceil = None if args.no_ceilings else measure_ceilings(adkion)
-    if ceil and mesh3d:
+    if ceil:
         for prec in ("mixed", "f64"):
-            mesh3d[prec]["frac_of_measured_hbm_copy"] = mesh3d[prec]["achieved_gbps"] / ceil["hbm_copy_gbps"]
+            head[prec]["frac_of_measured_hbm_copy"] = head[prec]["achieved_gbps"] / ceil["hbm_copy_gbps"]
+        if mesh2d:
+            for prec in ("mixed", "f64"):
+                mesh2d[prec]["frac_of_measured_cache_copy"] = mesh2d[prec]["achieved_gbps"] / ceil["cache_copy_gbps"]
 
-    m = res["mixed"]
+    m = head["mixed"]
+    us = m["kernel_avg_us"]
+    alg = bytes_per_cell(w, "mixed") * n3
+    traffic = measured_traffic("traffic_bytes_per_launch_mixed") if w == 3 else None
+    roof = {"bound": "hbm", "achieved": m["achieved_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": m["achieved_gbps"] / HBM_PEAK_GBPS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a "
+                            f"512 MiB copy; profiles/{PROFILE_3D_BYTES})",
+            "algorithmic_bytes_per_launch": alg, "bytes_per_cell": bytes_per_cell(w, "mixed"),
+            "kernel": f"step_compact_kernel<PolicyMixed,{w}>", "kernel_avg_us": us,
+            "timing": "HIP events around one graph replay of the timed steps, divided by the steps",
+            "kernel_trace": "profiles/step_compact_mixed_w3_mesh3d_default_bench_trace.md"}
+    if traffic:
+        roof["counter_bytes_gbps"] = traffic / (us * 1e-6) / 1e9
+        roof["frac_counter_bytes"] = roof["counter_bytes_gbps"] / HBM_PEAK_GBPS
+    if ceil:
+        roof["measured_hbm_copy_gbps"] = ceil["hbm_copy_gbps"]
+        roof["frac_of_measured_hbm_copy"] = m["achieved_gbps"] / ceil["hbm_copy_gbps"]
+        if traffic:
+            roof["frac_counter_bytes_of_measured_hbm_copy"] = roof["counter_bytes_gbps"] / ceil["hbm_copy_gbps"]
+    per_level = {"laser3d_Z36_w3": {p: {"run_state": head[p]["parity_run_state"]["per_level_max_abs_err"],
+                                        "random_state": head[p]["parity_random_state"]["per_level_max_abs_err"]}
+                                    for p in ("mixed", "f64")}}
+    if mesh2d and mesh2d.get("parity"):
+        per_level["laser2d_Z18_w3"] = {p: mesh2d["parity"][p]["per_level_max_abs_err"] for p in ("mixed", "f64")}
+    if batched:
+        per_level["batched"] = {p: batched[p]["per_level_max_abs_err"] for p in ("mixed", "f64")}
+    if surrogate:
+        per_level["surrogate_laser3d_Z36_w3"] = {
+            "surrogate": surrogate["error_vs_fp64"]["oracle_sample"]["per_level_max_abs_err"],
+            "mixed_analytic_same_cells": surrogate["error_vs_fp64"]["mixed_analytic_same_cells"]["per_level_max_abs_err"]}
     line = {
         "metric": METRIC,
         "value": m["value"],
@@ -965,36 +1233,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"laser2d_1024x1024_Z18_w{w}", "cells": n, "levels": 18, "window_w": w,
-                   "eps": eps, "layout": "compact", "precision": "mixed", "dt_s": mesh.dt,
-                   "timed_steps": f"steps 0..{K - 1} of the {mesh.steps}-step run", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": m["achieved_gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": m["achieved_gbps"] / HBM_PEAK_GBPS,
-                     "traffic": measured_traffic("traffic_bytes_per_launch_mixed") if w == 3 else None,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
-                                     "calibrated on a 512 MiB copy; profiles/step_compact_mixed_w3_mesh2d_bytes.txt)",
-                     "algorithmic_bytes_per_launch": bytes_per_cell(w, "mixed") * n,
-                     "kernel": f"step_compact_kernel<PolicyMixed,{w}>",
-                     "bytes_per_cell": bytes_per_cell(w, "mixed"), "kernel_avg_us": m["kernel_ms"] * 1e3,
-                     "timing": "HIP events around one graph replay of the timed steps / steps",
-                     "kernel_trace": "profiles/step_compact_mixed_w3_mesh2d_default_bench_trace.md",
-                     "frac_of_measured_hbm_copy": m["achieved_gbps"] / ceil["hbm_copy_gbps"] if ceil else None,
-                     "frac_of_measured_cache_copy": m["achieved_gbps"] / ceil["cache_copy_gbps"] if ceil else None},
+        "config": {"workload": head["workload"], "cells": n3, "levels": 36, "rates": "m averaged", "window_w": w,
+                   "eps": eps, "layout": "compact", "precision": "mixed", "dt_s": mesh3.dt,
+                   "timed_steps": head["timed_steps"], "parallelism": "single GPU"},
+        "roofline": roof,
         "ceilings": ceil,
-        "launch": "timed steps captured in one HIP graph; eager per-call launches reported as eager_ms_per_step",
-        "eager_ms_per_step": m["eager_ms_per_step"],
-        "fp64": {"value": res["f64"]["value"], "ms_per_step": res["f64"]["ms_per_step"],
-                 "kernel_avg_us": res["f64"]["kernel_ms"] * 1e3, "achieved_gbps": res["f64"]["achieved_gbps"],
-                 "eager_ms_per_step": res["f64"]["eager_ms_per_step"]},
-        "speedup_vs_fp64": m["value"] / res["f64"]["value"],
-        "parity": parity,
-        "mesh3d": mesh3d,
+        "launch": "timed steps captured in one HIP graph",
+        "fp64": {k: head["f64"][k] for k in ("value", "ms_per_step", "kernel_avg_us", "achieved_gbps", "frac_hbm")},
+        "speedup_vs_fp64": head["speedup_mixed_vs_f64"],
+        "parity": {p: {k: head[p][k] for k in ("parity_run_state", "parity_random_state")} for p in ("mixed", "f64")},
+        "per_level_max_abs_err": per_level,
+        "mesh3d": head,
+        "mesh2d": mesh2d,
         "batched": batched,
         "surrogate": surrogate,
         "subcycled_baseline": subcycle,
         "window_study": study,
         "window_study_3d": study3d,
         "cpu_baseline": cpu,
+        "cpu_baseline_other_configs": cpu_other,
     }
     gas.close()
     print(json.dumps(line), flush=True)

@@ -32,11 +32,13 @@ def test_measured_traffic_is_tied_to_the_kernel_sources():
     hash to the value recorded with the counters; then it is the measured
     HBM bytes of a launch, below the algorithmic 38 B per cell (wavefronts
     that keep their windows store nothing) and above the read bytes."""
-    v = bench.measured_traffic("traffic_bytes_per_launch_mixed")
-    if v is None:
-        pytest.skip("step kernel sources changed since the byte counters were taken")
-    n = 1024 * 1024
-    assert 21 * n <= v <= 38 * n
+    for profile, n in ((bench.PROFILE_2D_BYTES, 1024 * 1024), (bench.PROFILE_3D_BYTES, 256 * 256 * 512)):
+        v = bench.measured_traffic("traffic_bytes_per_launch_mixed", profile)
+        if v is None:
+            continue  # the step kernel's sources changed since these counters were taken
+        assert 21 * n <= v <= 38 * n
+        v = bench.measured_traffic("traffic_bytes_per_launch_f64", profile)
+        assert 41 * n <= v <= 74 * n
     assert bench.measured_traffic("no_such_key") is None
 
 
