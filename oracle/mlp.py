@@ -126,6 +126,32 @@ def forward(params: np.ndarray, Z: int, u, v, k, bf16_ops: bool = True):
     return Q, cache
 
 
+def layer_maps(params: np.ndarray, Z: int, u, v, k, z1, z2, z3):
+    """The network one layer at a time, for checking an evaluation whose
+    rounding decisions are given: z1, z2, z3 [n][64] are pre-activations of
+    layers 1-3 as another evaluation computed them (before the rounding to
+    bfloat16).  Returns the FP64 pre-activations each layer makes from the
+    previous layer's given ones, rounded as the network rounds them:
+        z1 = W1u u + W1v v + W1e emb[k] + b1,
+        z2 = bf16(W2) bf16(relu(z1_given)) + b2,   likewise z3 from z2_given,
+        z4 = bf16(W4) bf16(relu(z3_given)) + b4,
+    each with the sum of the magnitudes of its terms (S1..S4), which bounds
+    the rounding of any float32 summation order of those terms."""
+    p = unpack(params, Z)
+    u = np.asarray(u, np.float64)
+    v = np.asarray(v, np.float64)
+    k = np.asarray(k, np.int64)
+    tu, tv = np.outer(u, p["W1u"]), np.outer(v, p["W1v"])
+    out = {"z1": tu + tv + p["emb"][k] @ p["W1e"].T + p["b1"],
+           "S1": np.abs(tu) + np.abs(tv) + np.abs(p["emb"][k]) @ np.abs(p["W1e"]).T + np.abs(p["b1"])}
+    for i, (zg, Wn, bn) in enumerate(((z1, "W2", "b2"), (z2, "W3", "b3"), (z3, "W4", "b4")), start=2):
+        h = bf16(np.maximum(np.asarray(zg, np.float64), 0.0))
+        W = bf16(p[Wn])
+        out[f"z{i}"] = h @ W.T + p[bn]
+        out[f"S{i}"] = h @ np.abs(W).T + np.abs(p[bn])
+    return out
+
+
 def loss(Q, P):
     """Mean cross entropy; terms with P = 0 contribute nothing."""
     P = np.asarray(P, np.float64)
@@ -134,9 +160,18 @@ def loss(Q, P):
     return float(-t.sum() / P.shape[0])
 
 
-def loss_and_grad(params: np.ndarray, Z: int, u, v, k, P, bf16_ops: bool = True):
-    """Loss and its gradient with respect to the flat parameter vector."""
+def loss_and_grad(params: np.ndarray, Z: int, u, v, k, P, bf16_ops: bool = True, acts=None):
+    """Loss and its gradient with respect to the flat parameter vector.
+    acts = (h1, h2, h3) (optional): bfloat16 activations to take instead of
+    the forward pass's own (the rounding decisions of another evaluation of
+    the same network); the rest of the pass is unchanged."""
     Q, c = forward(params, Z, u, v, k, bf16_ops)
+    if acts is not None:
+        h1, h2, h3 = (np.asarray(a, np.float64) for a in acts)
+        z4 = h3 @ c["W4"].T + c["p"]["b4"]
+        zm = z4 - z4.max(axis=1, keepdims=True)
+        Q = np.exp(zm) / np.exp(zm).sum(axis=1, keepdims=True)
+        c.update(h1=h1, h2=h2, h3=h3, Q=Q)
     P = np.asarray(P, np.float64)
     n = P.shape[0]
     p = c["p"]
@@ -217,13 +252,18 @@ def window_shift(N, lo, Z, eps):
 NEGLIGIBLE_XDT = 1e-9
 
 
-def surrogate_step(orc, spec, Z, params, rng: Range, E, dt, pops, lo, w, eps, bf16_ops=True):
+def surrogate_step(orc, spec, Z, params, rng: Range, E, dt, pops, lo, w, eps, bf16_ops=True, cols_given=None,
+                   negligible=None):
     """Reference of the surrogate form of the step: cells whose |E| lies in
     the trained range (and a step dt in range) take band columns after the
     window shift, the network's for source levels with W dt >= NEGLIGIBLE_XDT
     and the identity column for the others; all other cells take the exact
     step of the analytic oracle `orc.ionize_step`.  Also returns the window
-    rates times dt, x[w][n] (0 past level Z-1)."""
+    rates times dt, x[w][n] (0 past level Z-1).
+    cols_given [w][4][n] (optional): network columns of another evaluation of
+    the same network (its own bfloat16 rounding decisions) to use instead of
+    this module's; negligible [w][n] (optional, bool): the identity decision
+    per source slot instead of W dt < NEGLIGIBLE_XDT."""
     E = np.abs(np.asarray(E, np.float64))
     ana, alo = orc.ionize_step(spec, E, dt, np.asarray(pops, np.float64), np.asarray(lo, np.uint8), w, eps)
     dt_ok = rng.dt_lo <= dt <= rng.dt_hi
@@ -238,9 +278,13 @@ def surrogate_step(orc, spec, Z, params, rng: Range, E, dt, pops, lo, w, eps, bf
         k = p + s
         ok = k < Z
         x[s, ok] = Wall[k[ok], np.nonzero(ok)[0]] * dt
-        Q, _ = forward(params, Z, u, v, np.minimum(k, Z - 1), bf16_ops)
-        Q = Q.T
-        Q[:, x[s] < NEGLIGIBLE_XDT] = np.array([1.0, 0.0, 0.0, 0.0])[:, None]
+        if cols_given is not None:
+            Q = np.array(cols_given[s], np.float64)
+        else:
+            Q, _ = forward(params, Z, u, v, np.minimum(k, Z - 1), bf16_ops)
+            Q = Q.T
+        negl = x[s] < NEGLIGIBLE_XDT if negligible is None else np.asarray(negligible[s], bool)
+        Q[:, negl] = np.array([1.0, 0.0, 0.0, 0.0])[:, None]
         cols.append(Q)
     band = band_update(N, p, w, Z, cols, use)
     out = np.where(use[None, :], band, ana)

@@ -292,3 +292,36 @@ def test_surrogate_step_composition(orc):
     out, olo, use, _ = mlp.surrogate_step(orc, spec, Z, params, r, E, 5e-16, N, lo, w, eps, bf16_ops=False)
     ana, alo = orc.ionize_step(spec, E, 5e-16, N, lo, w, eps)
     assert not use.any() and np.array_equal(out, ana) and np.array_equal(olo, alo)
+
+
+def test_layer_maps_reproduce_the_forward_pass():
+    """Given the forward pass's own pre-activations, each layer map returns
+    them again (to FP64 rounding), and the magnitude sums bound them."""
+    Z = 36
+    p = wl.mlp_init(Z, 4).astype(np.float64)
+    b = mlp.unpack(p.copy(), Z)
+    r = np.random.default_rng(2)
+    for name in ("b1", "b2", "b3", "b4"):
+        b[name][:] = r.uniform(-0.2, 0.2, b[name].shape)
+    p = mlp.pack(b, Z)
+    u, v, k = r.uniform(-1, 1, 300), r.uniform(-1, 1, 300), r.integers(0, Z, 300)
+    # the forward pass's own pre-activations, layer by layer
+    z1 = np.outer(u, b["W1u"]) + np.outer(v, b["W1v"]) + b["emb"][k] @ b["W1e"].T + b["b1"]
+    h1 = mlp.bf16(np.maximum(z1, 0))
+    z2 = h1 @ mlp.bf16(b["W2"]).T + b["b2"]
+    h2 = mlp.bf16(np.maximum(z2, 0))
+    z3 = h2 @ mlp.bf16(b["W3"]).T + b["b3"]
+    h3 = mlp.bf16(np.maximum(z3, 0))
+    z4 = h3 @ mlp.bf16(b["W4"]).T + b["b4"]
+    m = mlp.layer_maps(p, Z, u, v, k, z1, z2, z3)
+    for i, z in enumerate((z1, z2, z3, z4), start=1):
+        assert np.allclose(m[f"z{i}"], z, rtol=0, atol=1e-14)
+        assert np.all(np.abs(m[f"z{i}"]) <= m[f"S{i}"] * (1 + 1e-12))
+    Q, _ = mlp.forward(p, Z, u, v, k)
+    ez = np.exp(z4 - z4.max(axis=1, keepdims=True))
+    assert np.allclose(Q, ez / ez.sum(axis=1, keepdims=True), atol=1e-15)
+    # the gradient with the forward pass's own activations is the gradient
+    P = _targets(300, r)
+    L0, g0 = mlp.loss_and_grad(p, Z, u, v, k, P)
+    L1, g1 = mlp.loss_and_grad(p, Z, u, v, k, P, acts=(h1, h2, h3))
+    assert L1 == pytest.approx(L0, rel=1e-14) and np.allclose(g1, g0, rtol=1e-12, atol=1e-15)

@@ -185,7 +185,7 @@ MLP_MUTANTS = [
     ("band update drops the window top", "o[top] = N[top, c]", "o[top] = 0.0"),
     ("field feature not centred", "- 0.5 * (lE0 + lE1)) / (0.5 * (lE1 - lE0))", "- lE0) / (0.5 * (lE1 - lE0))"),
     ("stripped cells take the band", "use &= p < Z", "use &= p <= Z"),
-    ("negligible-source test reversed", "Q[:, x[s] < NEGLIGIBLE_XDT]", "Q[:, x[s] > NEGLIGIBLE_XDT]"),
+    ("negligible-source test reversed", "negl = x[s] < NEGLIGIBLE_XDT if", "negl = x[s] > NEGLIGIBLE_XDT if"),
     ("field range open above", "(E <= rng.E_hi)", "(E <= 2 * rng.E_hi)"),
     ("band applied before the shift", "band = band_update(N, p, w, Z, cols, use)",
      "band = band_update(np.asarray(pops, np.float64), p, w, Z, cols, use)"),
