@@ -458,6 +458,84 @@ def headline_3d(ak, orc, gas36, spec36, mesh, K, warmup, w, eps, t0=200, parity_
     return res
 
 
+def adaptive_measure(ak, gas36, mesh, steps, eps, wmax=24, tol=1e-9, t0=200):
+    """Adaptive windows (ionize_step_adaptive, mixed precision) on the whole
+    3D mesh: widths 1..wmax per cell and step (leak tolerance tol per step),
+    the pulse run in from neutral cells over steps 0..t0-1, then `steps`
+    steps timed as one graph replay (HIP events); an untimed eager pass
+    counts window populations (wc + 1 per live cell) and the cells the
+    wavefront-per-cell tier solved."""
+    import torch
+    n = mesh.ncells
+    Z = 36
+    fields = torch.empty((steps, n), dtype=torch.float32, device="cuda")
+    for i in range(steps):
+        fields[i] = mesh.field_torch(t0 + i, "cuda", torch.float32)
+    P = torch.zeros((wmax + 1, n), dtype=torch.float32, device="cuda")
+    P[0] = 1.0
+    L = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    Wc = torch.ones(n, dtype=torch.uint8, device="cuda")
+    work = ak.adaptive_workspace(n)
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    t_run = time.perf_counter()
+    for t in range(t0):
+        ak.ionize_step_adaptive(gas36, mesh.field_torch(t, "cuda", torch.float32), mesh.dt, P, L, Wc, 1, wmax, eps=eps,
+                                tol=tol, work=work, counters=cnt)
+    torch.cuda.synchronize()
+    run_in_s = time.perf_counter() - t_run
+    held_run_in = int(cnt[1])
+    P0, L0, W0 = P.clone(), L.clone(), Wc.clone()
+
+    def restore():
+        P.copy_(P0)
+        L.copy_(L0)
+        Wc.copy_(W0)
+        cnt.zero_()
+        torch.cuda.synchronize()
+
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for i in range(steps):
+            ak.ionize_step_adaptive(gas36, fields[i], mesh.dt, P, L, Wc, 1, wmax, eps=eps, tol=tol, work=work,
+                                    counters=cnt)
+    restore()
+    graph.replay()
+    restore()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    graph.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    total_ms = a.elapsed_time(b)
+    wide_cells, held = (int(v) for v in cnt.cpu().numpy())
+    del graph
+    restore()
+    units = 0
+    wsum = wlive = 0.0
+    for i in range(steps):
+        ak.ionize_step_adaptive(gas36, fields[i], mesh.dt, P, L, Wc, 1, wmax, eps=eps, tol=tol, work=work)
+        live = L < Z
+        units += int((Wc.to(torch.int64) + 1)[live].sum()) + int((~live).sum())
+        wsum += float(Wc[live].double().sum())
+        wlive += float(live.sum())
+    torch.cuda.synchronize()
+    ms = total_ms / steps
+    res = {"workload": f"laser3d_256x256x512_Z36mavg_adaptive_w1to{wmax}_mixed", "tolerance_per_step": tol,
+           "timed_steps": f"steps {t0}..{t0 + steps - 1} after {t0} steps of run-in (run-in {run_in_s:.1f} s eager)",
+           "ms_per_step": ms, "value": units / (total_ms * 1e-3), "unit": "cell·level updates/s",
+           "mean_width_live_cells": wsum / max(wlive, 1.0), "max_width": int(Wc.max()),
+           "wide_tier_cells_per_step": wide_cells / steps, "held_by_wmax_timed_steps": held,
+           "held_by_wmax_run_in": held_run_in,
+           "launches_per_step": 3}
+    log(f"[adaptive] mixed, widths 1..{wmax}: {ms * 1e3:.1f} us/step, {res['value']:.3e} cell-level/s, mean width "
+        f"{res['mean_width_live_cells']:.2f} (max {res['max_width']}), {wide_cells / steps:.0f} cells/step on the "
+        f"wavefront tier, held by wmax: {held} (timed) {held_run_in} (run-in)")
+    del fields, P, L, Wc, P0, L0, W0, work
+    torch.cuda.empty_cache()
+    return res
+
+
 def yield_measure(ak, gas36, w, eps, steps):
     """Cost of the fused electron yield on the 3D mesh (mixed): the same
     steps with and without the dne output, per-launch HIP events."""
@@ -679,14 +757,17 @@ def window_study(ak, mesh, eps, widths=(2, 3, 4, 8), every=10):
     return res
 
 
-def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width=32):
+def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width=32, tol=1e-9):
     """Full-vs-reduced study on the 3D mesh (256 x 256 x 512 cells, 36 levels,
-    m averaged): FP64 windows of w = 2, 3, 4 rates against the full 36-level
-    chain (w = Z on the wide path, no shift), `steps` steps of the pulse from
-    t = 0, on the central transverse box of (2 half_width)^2 x 512 cells (the
-    strongest fields: |x|, |y| < 10 um around the axis).  Every `every` steps:
-    max |dN_k| per cell and the relative error of n_e = sum_k k N_k; the
-    full-chain step time."""
+    m averaged): FP64 windows of w = 2, 3, 4 rates and the adaptive window
+    (ionize_step_adaptive: width 1..36 per cell and step, leak tolerance
+    `tol` per step) against the full 36-level chain (w = Z on the wide path,
+    no shift), `steps` steps of the pulse from t = 0, on the central
+    transverse box of (2 half_width)^2 x 512 cells (the strongest fields:
+    |x|, |y| < 10 um around the axis).  Every `every` steps: max |dN_k| per
+    cell and the relative error of n_e = sum_k k N_k, and the adaptive
+    windows' widths; the step times of the full chain and of the adaptive
+    window."""
     import torch
     from paper_2202_10647_amd import workloads as wl
     Z = 36
@@ -704,6 +785,18 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
         P = torch.zeros((w + 1, n), dtype=torch.float64, device="cuda")
         P[0] = 1.0
         st[w] = (P, torch.zeros(n, dtype=torch.uint8, device="cuda"))
+    # adaptive windows: storage for every level, widths start at 1
+    Pa = torch.zeros((Z + 1, n), dtype=torch.float64, device="cuda")
+    Pa[0] = 1.0
+    La = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    Wa = torch.ones(n, dtype=torch.uint8, device="cuda")
+    work = ak.adaptive_workspace(n)
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ada_s = 0.0
+    width_sum = width_cells = 0.0
+    width_max = 0
+    dmax_a = torch.zeros(n, dtype=torch.float64, device="cuda")
+    nemax_a = torch.zeros(n, dtype=torch.float64, device="cuda")
     # cells whose field over the first laser period already exceeds 1 GV/m
     # start ionizing in a strong field (the pulse is partly inside the mesh at
     # t = 0); reported apart from the cells the pulse reaches gradually
@@ -728,6 +821,11 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
             if w == Z:
                 torch.cuda.synchronize()
                 ref_s += time.perf_counter() - tr
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ak.ionize_step_adaptive(gas, E, mesh.dt, Pa, La, Wa, 1, Z, eps=eps, tol=tol, work=work, counters=cnt)
+        torch.cuda.synchronize()
+        ada_s += time.perf_counter() - ta
         ne_now = (lev * st[Z][0]).sum(0)
         jump = torch.maximum(jump, ne_now - ne_prev)
         ne_prev = ne_now
@@ -740,6 +838,15 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
                 ne = (lev * full).sum(0)
                 nemax[w] = torch.maximum(nemax[w], torch.where(ne_ref > 1e-3, (ne - ne_ref).abs() / ne_ref,
                                                                torch.zeros_like(ne)))
+            full = _to_full(Pa, La, Z, Z)
+            dmax_a = torch.maximum(dmax_a, (full - ref).abs().amax(dim=0))
+            ne = (lev * full).sum(0)
+            nemax_a = torch.maximum(nemax_a, torch.where(ne_ref > 1e-3, (ne - ne_ref).abs() / ne_ref,
+                                                         torch.zeros_like(ne)))
+            live = La < Z
+            width_sum += float(Wa[live].double().sum())
+            width_cells += float(live.sum())
+            width_max = max(width_max, int(Wa.max()))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ne_final = (lev * st[Z][0]).sum(0)
@@ -765,12 +872,24 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
         log(f"[study3d] w={w}: gradual-onset cells max |dN| {gr['max_abs_dN']:.2e} (p99.9 {gr['p99_9_abs_dN']:.1e}), "
             f"max rel n_e error {gr['max_rel_err_ne']:.2e}; strong-start cells max |dN| "
             f"{ss['max_abs_dN'] if ss else float('nan'):.2e}")
+    ga, sa = stats(dmax_a[gradual], nemax_a[gradual]), stats(dmax_a[~gradual], nemax_a[~gradual])
+    c = cnt.cpu().numpy()
+    res["adaptive"] = {"tolerance_per_step": tol, "wmin": 1, "wmax": Z, "gradual": ga, "strong_start": sa,
+                       "mean_width": width_sum / max(width_cells, 1.0), "max_width": width_max,
+                       "width_sampling": f"every {every} steps over cells with lo < Z",
+                       "us_per_step": ada_s / steps * 1e6,
+                       "wide_tier_cells_per_step": float(c[0]) / steps, "held_by_wmax": int(c[1]),
+                       "storage": "Z + 1 rows allotted (wmax = Z); a cell uses wc + 1 of them"}
+    log(f"[study3d] adaptive (tol {tol:g}/step): gradual-onset cells max |dN| {ga['max_abs_dN']:.2e}, max rel n_e "
+        f"error {ga['max_rel_err_ne']:.2e}; strong-start cells max |dN| {sa['max_abs_dN'] if sa else float('nan'):.2e}; "
+        f"mean width {res['adaptive']['mean_width']:.2f} (max {width_max}); {res['adaptive']['us_per_step']:.0f} "
+        f"us/step against {res['full_chain_us_per_step']:.0f} for the full chain")
     jg = res["largest_charge_gain_in_one_step"]["gradual"]
     log(f"[study3d] largest charge gain of the full chain in one step (gradual-onset cells): median "
         f"{jg['median']:.2f}, max {jg['max']:.2f} levels")
     log(f"[study3d] full 36-level chain: {res['full_chain_us_per_step']:.0f} us/step on {n} cells; "
         f"final mean charge {res['final_mean_charge']['mean']:.3f} (max {res['final_mean_charge']['max']:.2f})")
-    del st, dmax, nemax
+    del st, dmax, nemax, Pa, La, Wa, work
     gas.close()
     torch.cuda.empty_cache()
     return res
@@ -1097,6 +1216,7 @@ def main():
     ap.add_argument("--no-study", action="store_true")
     ap.add_argument("--study3d-steps", type=int, default=500, help="0 skips the 3D full-vs-reduced study")
     ap.add_argument("--surrogate-steps", type=int, default=40)
+    ap.add_argument("--adaptive-steps", type=int, default=20, help="0 skips the adaptive-window leg")
     ap.add_argument("--surrogate-train-iters", type=int, default=24000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -1164,6 +1284,9 @@ def main():
     if not args.no_study and args.study3d_steps > 0:
         study3d = window_study_3d(adkion, mesh3, eps, args.study3d_steps)
     head["electron_yield"] = yield_measure(adkion, gas36, w, eps, args.yield_steps)
+    adaptive = None if args.adaptive_steps <= 0 else adaptive_measure(adkion, gas36, mesh3, args.adaptive_steps, eps)
+    if adaptive:
+        adaptive["speedup_vs_fixed_w3_mixed"] = adaptive["value"] / head["mixed"]["value"]
     surrogate = None
     if not args.no_surrogate:
         surrogate = surrogate_measure(adkion, oracle, gas36, spec36, w, eps, args.surrogate_steps,
@@ -1244,6 +1367,7 @@ def main():
         "parity": {p: {k: head[p][k] for k in ("parity_run_state", "parity_random_state")} for p in ("mixed", "f64")},
         "per_level_max_abs_err": per_level,
         "mesh3d": head,
+        "adaptive_window": adaptive,
         "mesh2d": mesh2d,
         "batched": batched,
         "surrogate": surrogate,

@@ -28,6 +28,7 @@
 #ifndef ADKION_H
 #define ADKION_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -131,9 +132,13 @@ int adk_rates(const adk_gas *gas, const void *E, int64_t n, int32_t k0, int32_t 
  * levels, top absorbing, no window shift): pops[(w+1)][ncells] <-
  * expm(dt A(W)) pops, with W[w][ncells] in 1/s (rates >= 0).  The update is
  * the analytic (Bateman / divided-difference) solution, valid for equal,
- * zero and crossing rates.  Errors: ADK_EINVAL (null pointers with ncells > 0,
- * ncells < 0, dt <= 0 or non-finite, bad prec), ADK_ERANGE (w outside
- * [1, ADK_MAX_W]). */
+ * zero and crossing rates.  Windows up to ADK_MAX_W rates run one cell per
+ * lane, wider ones (up to ADK_MAX_WIDE_W) one cell per wavefront in double
+ * arithmetic; there a table of divided differences whose rounding bound
+ * exceeds 1e-13 (dozens of rates within a band of a few tens per step) is
+ * recomputed by scaling and squaring.  Errors: ADK_EINVAL (null pointers
+ * with ncells > 0, ncells < 0, dt <= 0 or non-finite, bad prec), ADK_ERANGE
+ * (w outside [1, ADK_MAX_WIDE_W]). */
 int adk_chain_advance(int32_t w, const void *W, int64_t ncells, double dt, void *pops,
                       adk_prec prec, hipStream_t stream);
 
@@ -167,6 +172,64 @@ int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, vo
  * than ADK_LAYOUT_COMPACT or a null dne with ncells > 0. */
 int ionize_step_yield(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops,
                       uint8_t *lo, const adk_window *win, void *dne, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Adaptive window.  The reduced system of Sec. 3 is "specified independently
+ * for each computational cell"; here each cell's window also chooses its own
+ * width, step by step, so that it follows populations that spread over more
+ * levels than a fixed window holds (a slowly ionizing level below a fast
+ * cascade).  Per cell and step:
+ *   1. the window shift at the start of the step (cut-off criterion after
+ *      Eq. (9), as ionize_step); the top level stays, so the width wc drops
+ *      by the number of shifts (not below 0);
+ *   2. the top slot t starts at min(max(wmin, wc), Z - lo) and moves up,
+ *      at most to min(wmax, Z - lo), while leak(t) > tol (or is NaN), where
+ *        leak(t) = sum_{s <= t, N_s != 0} N_s x_s x_{s+1} ... x_t / (t-s+1)!,
+ *      x_k = W_{lo+k} dt, bounds the population the full chain (Eq. (3)
+ *      with every level) moves past slot t within the step: the absorbing
+ *      top holds back at most leak(t), and below the top the window's
+ *      solution is the full chain's;
+ *   3. the window [lo, lo + t] is solved exactly (Eqs. (4)-(5)), top
+ *      absorbing; wc = t.
+ * With tol = 0 and wmax >= Z - lo the result is the full chain; with
+ * wmin = wmax = w it is ionize_step with window w.  Cells whose window fits
+ * three rates run one per lane, wider ones one per wavefront (double
+ * arithmetic), up to ADK_MAX_WIDE_W rates.
+ */
+typedef struct {
+    int32_t wmin; /* 0 <= wmin <= wmax: narrowest window (rates)                 */
+    int32_t wmax; /* 1 <= wmax <= min(Z, ADK_MAX_WIDE_W): widest; rows wmax + 1  */
+    double eps;   /* shift threshold, >= 0 and finite (as adk_window)            */
+    double tol;   /* leak tolerance per step, >= 0 (not NaN)                     */
+    adk_prec prec;
+} adk_adaptive;
+
+/* Bytes of the device workspace ionize_step_adaptive needs for ncells cells
+ * (a list of the cells the wide tier solves, and its length): 256 + 4 ncells. */
+size_t adk_adaptive_work_bytes(int64_t ncells);
+
+/* One step with adaptive windows for ncells cells (compact layout):
+ * E[ncells], pops[(wmax+1)][ncells] (slot s holds level lo + s for s <= wc;
+ * slots above wc are not read and are written as zero when the window
+ * leaves them), lo[ncells] (uint8, values above Z read as Z) and wc[ncells]
+ * (uint8, rates in the window, values above wmax read as wmax; start with
+ * wmin) are device arrays of the precision's type, updated in place.  work
+ * is a device buffer of at least adk_adaptive_work_bytes(ncells) bytes that
+ * the call uses as scratch (contents need no initialisation; calls sharing
+ * one workspace must be ordered).  counters (device, 2 x uint64, may be
+ * NULL) are incremented by: [0] cells solved one per wavefront (window wider
+ * than three rates), [1] cells whose top the storage limit wmax held back
+ * with leak above tol.  A cell below the gas's field cutoff (every rate
+ * below 1e-30 per step) with no shift due keeps its populations when
+ * tol >= 1e-30.  Three launches on stream (clear the list, lane-per-cell
+ * tier, wavefront-per-cell tier); allocates nothing and never synchronises.
+ * Errors: ADK_EINVAL (null gas/win, null arrays or work with ncells > 0,
+ * ncells < 0, work_bytes too small, dt <= 0 or non-finite, eps < 0 or
+ * non-finite, tol < 0 or NaN, bad prec), ADK_ERANGE (wmin/wmax outside the
+ * ranges above, ncells >= 2^31). */
+int ionize_step_adaptive(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops, uint8_t *lo,
+                         uint8_t *wc, const adk_adaptive *win, void *work, size_t work_bytes,
+                         unsigned long long *counters, hipStream_t stream);
 
 /* Comparison baseline, not the method: ionize_step (compact layout, ADK_F64)
  * with the chain integrated by nsub explicit classical Runge-Kutta substeps
@@ -375,6 +438,15 @@ int adk_band_columns(const adk_gas *gas, const double *E, const double *dt, cons
  * (double) and k[n] (int32, clamped to [0, Z-1]).  Errors: ADK_EINVAL. */
 int adk_mlp_forward(const adk_mlp *mlp, const double *E, const double *dt, const int32_t *k, int64_t n,
                     float *Q, hipStream_t stream);
+
+/* adk_mlp_forward that also writes, for testing the network element by
+ * element, each sample's float32 pre-activations of layers 1-3 before their
+ * rounding to bfloat16 and its four logits: Zt[n][196] (device floats), row
+ * i = z1[64], z2[64], z3[64] (hidden units in order) then z4[4].  Q and the
+ * evaluation are those of adk_mlp_forward (the same kernel code).  Errors:
+ * ADK_EINVAL. */
+int adk_mlp_forward_trace(const adk_mlp *mlp, const double *E, const double *dt, const int32_t *k, int64_t n,
+                          float *Q, float *Zt, hipStream_t stream);
 
 /* Loss and gradient of the current parameters over the n given samples
  * (targets from adk_band_columns, computed inside): grad[adk_mlp_nparams(Z)]

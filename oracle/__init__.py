@@ -72,7 +72,7 @@ def _load():
     lib.orc_adaptive_step.restype = None
     lib.orc_adaptive_step.argtypes = [ctypes.c_int, dp, i8p, i8p, dp, ctypes.c_int64, dp, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, u8p, u8p,
-                                      ip, ip, dp, dp]
+                                      ip, ip, dp, dp, dp]
     lib.orc_max_threads.restype = ctypes.c_int
     lib.orc_max_threads.argtypes = []
     _lib = lib
@@ -172,9 +172,10 @@ def ionize_step(gas: GasSpec, E, dt, pops, lo, w, eps, layout=0, consts=None):
 def adaptive_step(gas: GasSpec, E, dt, pops, lo, wc, wmin, wmax, eps, tol, force_top=None, consts=None):
     """One step with an adaptive window (see orc_adaptive_step): pops[(wmax+1)][n],
     lo[n] and wc[n] (rates in each cell's window) in; returns (pops, lo, wc,
-    info) as new arrays, info = dict(top, leak_top, leak_below) per cell.
-    force_top[n] (optional, int): where >= 0, the top slot to take instead of
-    the leak criterion."""
+    info) as new arrays, info = dict(top, leak_top, leak_below, leaks) per cell
+    (leaks[(wmax+1)][n]: leak(t) for the slots the criterion may test, -1
+    elsewhere).  force_top[n] (optional, int): where >= 0, the top slot to
+    take instead of the leak criterion."""
     E = np.ascontiguousarray(np.asarray(E, dtype=np.float64).ravel())
     n = E.size
     pops = np.array(pops, dtype=np.float64, order="C", copy=True)
@@ -186,6 +187,7 @@ def adaptive_step(gas: GasSpec, E, dt, pops, lo, wc, wmin, wmax, eps, tol, force
     top = np.zeros(n, np.int32)
     lt = np.zeros(n)
     lb = np.zeros(n)
+    lk = np.zeros((wmax + 1, n))
     ip = ctypes.POINTER(ctypes.c_int)
     ft = None
     if force_top is not None:
@@ -196,8 +198,8 @@ def adaptive_step(gas: GasSpec, E, dt, pops, lo, wc, wmin, wmax, eps, tol, force
     _load().orc_adaptive_step(gas.Z, *gas._ptrs(), _dp(c), n, _dp(E), float(dt), int(wmin), int(wmax), float(eps),
                               float(tol), _dp(pops), lo.ctypes.data_as(u8), wc.ctypes.data_as(u8),
                               ft.ctypes.data_as(ip) if ft is not None else None, top.ctypes.data_as(ip),
-                              _dp(lt), _dp(lb))
-    return pops, lo, wc, dict(top=top, leak_top=lt, leak_below=lb)
+                              _dp(lt), _dp(lb), _dp(lk))
+    return pops, lo, wc, dict(top=top, leak_top=lt, leak_below=lb, leaks=lk)
 
 
 def max_threads() -> int:

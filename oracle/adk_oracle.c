@@ -279,12 +279,13 @@ static double orc_leak(const double *N, const double *x, int t)
  *   5. slots 0..wmax stored (zero above top), wc = top.
  * force_top (may be NULL): a value >= 0 replaces step 3 for that cell.
  * top_out, leak_top, leak_below (may be NULL): the top taken, leak at it,
- * and leak one slot lower (-1 when top == t0).
+ * and leak one slot lower (-1 when top == t0).  leaks (may be NULL,
+ * [(wmax+1)][ncells]): leak(t) for t = t0..room after the shift, -1 elsewhere.
  */
 void orc_adaptive_step(int Z, const double *U, const int8_t *l, const int8_t *m, const double *consts,
                        int64_t ncells, const double *E, double dt, int wmin, int wmax, double eps, double tol,
                        double *pops, uint8_t *p, uint8_t *wc, const int *force_top, int *top_out,
-                       double *leak_top, double *leak_below)
+                       double *leak_top, double *leak_below, double *leaks)
 {
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t c = 0; c < ncells; ++c) {
@@ -309,6 +310,9 @@ void orc_adaptive_step(int Z, const double *U, const int8_t *l, const int8_t *m,
             W[k] = orc_level_rate(U[lo + k], lo + k + 1, l[lo + k], m[lo + k], E[c], consts);
             x[k] = W[k] * dt;
         }
+        if (leaks)
+            for (int t = 0; t <= wmax; ++t)
+                leaks[(int64_t)t * ncells + c] = (t >= t0 && t <= room) ? orc_leak(N, x, t) : -1.0;
         int top = t0;
         if (force_top && force_top[c] >= 0) {
             top = force_top[c];

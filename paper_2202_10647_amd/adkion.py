@@ -28,7 +28,8 @@ EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "a
            "adk_plan_step", "adk_plan_graph_replay", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash", "adk_mlp_nparams",
            "adk_mlp_create", "adk_mlp_destroy", "adk_mlp_get_state", "adk_band_columns", "adk_mlp_forward",
            "adk_mlp_loss_grad", "adk_mlp_train", "adk_mlp_save", "adk_mlp_load", "adk_surrogate_step",
-           "adk_ceiling_copy", "adk_ceiling_valu")
+           "adk_ceiling_copy", "adk_ceiling_valu", "adk_adaptive_work_bytes", "ionize_step_adaptive",
+           "adk_mlp_forward_trace")
 ADK_PLAN_MAX_GAS, ADK_PLAN_MAX_W = 8, 6
 
 
@@ -75,7 +76,20 @@ class _Window(ctypes.Structure):
                 ("prec", ctypes.c_int)]
 
 
+class _Adaptive(ctypes.Structure):
+    _fields_ = [("wmin", ctypes.c_int32), ("wmax", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("tol", ctypes.c_double), ("prec", ctypes.c_int)]
+
+
 _lib = None
+
+
+def _sig(L, name, attr, value):
+    """Set a symbol's ctypes signature; a symbol the loaded library lacks is
+    left for the call itself to report (the CPU tests check that the built
+    library exports every declared function)."""
+    if hasattr(L, name):
+        setattr(getattr(L, name), attr, value)
 
 
 def lib():
@@ -88,67 +102,74 @@ def lib():
                            "(no fallback path exists)")
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
-    L.adk_version.restype = ctypes.c_char_p
-    L.adk_version.argtypes = []
-    L.adk_strerror.restype = ctypes.c_char_p
-    L.adk_strerror.argtypes = [ctypes.c_int]
-    L.adk_gas_coeffs.restype = ctypes.c_int
-    L.adk_gas_coeffs.argtypes = [ctypes.POINTER(_GasDesc), ctypes.POINTER(_Consts), ctypes.POINTER(dbl)]
-    L.adk_gas_create.restype = ctypes.c_int
-    L.adk_gas_create.argtypes = [ctypes.POINTER(_GasDesc), ctypes.POINTER(_Consts), ctypes.POINTER(vp)]
-    L.adk_gas_destroy.restype = ctypes.c_int
-    L.adk_gas_destroy.argtypes = [vp]
-    L.adk_gas_levels.restype = ctypes.c_int
-    L.adk_gas_levels.argtypes = [vp]
-    L.adk_rates.restype = ctypes.c_int
-    L.adk_rates.argtypes = [vp, vp, i64, i32, i32, vp, ctypes.c_int, vp]
-    L.adk_chain_advance.restype = ctypes.c_int
-    L.adk_chain_advance.argtypes = [i32, vp, i64, dbl, vp, ctypes.c_int, vp]
-    L.ionize_step.restype = ctypes.c_int
-    L.ionize_step.argtypes = [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp]
-    L.adk_subcycle_step.restype = ctypes.c_int
-    L.adk_subcycle_step.argtypes = [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), i32, vp]
-    L.ionize_step_yield.restype = ctypes.c_int
-    L.ionize_step_yield.argtypes = [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp, vp]
-    L.adk_plan_create.restype = ctypes.c_int
-    L.adk_plan_create.argtypes = [ctypes.POINTER(vp), i32, vp, vp, i64, ctypes.c_int, dbl, i32,
-                                  ctypes.POINTER(vp)]
-    L.adk_plan_step.restype = ctypes.c_int
-    L.adk_plan_step.argtypes = [vp, vp, dbl, vp, vp, vp]
-    L.adk_plan_graph_replay.restype = ctypes.c_int
-    L.adk_plan_graph_replay.argtypes = [vp, i32, vp]
-    L.adk_plan_get_info.restype = ctypes.c_int
-    L.adk_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
-    L.adk_plan_destroy.restype = ctypes.c_int
-    L.adk_plan_destroy.argtypes = [vp]
-    L.adk_field_hash.restype = ctypes.c_int
-    L.adk_field_hash.argtypes = [vp, i64, ctypes.c_uint64, i64, dbl, dbl, ctypes.c_int, vp]
-    L.adk_ceiling_copy.restype = ctypes.c_int
-    L.adk_ceiling_copy.argtypes = [vp, vp, i64, i64, vp]
-    L.adk_ceiling_valu.restype = ctypes.c_int
-    L.adk_ceiling_valu.argtypes = [i32, i64, vp, i64, vp]
-    L.adk_mlp_nparams.restype = i64
-    L.adk_mlp_nparams.argtypes = [i32]
-    L.adk_mlp_create.restype = ctypes.c_int
-    L.adk_mlp_create.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_MlpRange), ctypes.POINTER(vp)]
-    L.adk_mlp_destroy.restype = ctypes.c_int
-    L.adk_mlp_destroy.argtypes = [vp]
-    L.adk_mlp_get_state.restype = ctypes.c_int
-    L.adk_mlp_get_state.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64)]
-    L.adk_band_columns.restype = ctypes.c_int
-    L.adk_band_columns.argtypes = [vp, vp, vp, vp, i64, vp, vp]
-    L.adk_mlp_forward.restype = ctypes.c_int
-    L.adk_mlp_forward.argtypes = [vp, vp, vp, vp, i64, vp, vp]
-    L.adk_mlp_loss_grad.restype = ctypes.c_int
-    L.adk_mlp_loss_grad.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp]
-    L.adk_mlp_train.restype = ctypes.c_int
-    L.adk_mlp_train.argtypes = [vp, vp, ctypes.POINTER(_TrainCfg), vp, vp]
-    L.adk_mlp_save.restype = ctypes.c_int
-    L.adk_mlp_save.argtypes = [vp, ctypes.c_char_p]
-    L.adk_mlp_load.restype = ctypes.c_int
-    L.adk_mlp_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
-    L.adk_surrogate_step.restype = ctypes.c_int
-    L.adk_surrogate_step.argtypes = [vp, vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp, vp]
+    _sig(L, "adk_version", "restype", ctypes.c_char_p)
+    _sig(L, "adk_version", "argtypes", [])
+    _sig(L, "adk_strerror", "restype", ctypes.c_char_p)
+    _sig(L, "adk_strerror", "argtypes", [ctypes.c_int])
+    _sig(L, "adk_gas_coeffs", "restype", ctypes.c_int)
+    _sig(L, "adk_gas_coeffs", "argtypes", [ctypes.POINTER(_GasDesc), ctypes.POINTER(_Consts), ctypes.POINTER(dbl)])
+    _sig(L, "adk_gas_create", "restype", ctypes.c_int)
+    _sig(L, "adk_gas_create", "argtypes", [ctypes.POINTER(_GasDesc), ctypes.POINTER(_Consts), ctypes.POINTER(vp)])
+    _sig(L, "adk_gas_destroy", "restype", ctypes.c_int)
+    _sig(L, "adk_gas_destroy", "argtypes", [vp])
+    _sig(L, "adk_gas_levels", "restype", ctypes.c_int)
+    _sig(L, "adk_gas_levels", "argtypes", [vp])
+    _sig(L, "adk_rates", "restype", ctypes.c_int)
+    _sig(L, "adk_rates", "argtypes", [vp, vp, i64, i32, i32, vp, ctypes.c_int, vp])
+    _sig(L, "adk_chain_advance", "restype", ctypes.c_int)
+    _sig(L, "adk_chain_advance", "argtypes", [i32, vp, i64, dbl, vp, ctypes.c_int, vp])
+    _sig(L, "ionize_step", "restype", ctypes.c_int)
+    _sig(L, "ionize_step", "argtypes", [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp])
+    _sig(L, "adk_adaptive_work_bytes", "restype", ctypes.c_size_t)
+    _sig(L, "adk_adaptive_work_bytes", "argtypes", [i64])
+    _sig(L, "ionize_step_adaptive", "restype", ctypes.c_int)
+    _sig(L, "ionize_step_adaptive", "argtypes", [vp, vp, i64, dbl, vp, vp, vp, ctypes.POINTER(_Adaptive), vp,
+                                                 ctypes.c_size_t, vp, vp])
+    _sig(L, "adk_subcycle_step", "restype", ctypes.c_int)
+    _sig(L, "adk_subcycle_step", "argtypes", [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), i32, vp])
+    _sig(L, "ionize_step_yield", "restype", ctypes.c_int)
+    _sig(L, "ionize_step_yield", "argtypes", [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp, vp])
+    _sig(L, "adk_plan_create", "restype", ctypes.c_int)
+    _sig(L, "adk_plan_create", "argtypes", [ctypes.POINTER(vp), i32, vp, vp, i64, ctypes.c_int, dbl, i32,
+                                            ctypes.POINTER(vp)])
+    _sig(L, "adk_plan_step", "restype", ctypes.c_int)
+    _sig(L, "adk_plan_step", "argtypes", [vp, vp, dbl, vp, vp, vp])
+    _sig(L, "adk_plan_graph_replay", "restype", ctypes.c_int)
+    _sig(L, "adk_plan_graph_replay", "argtypes", [vp, i32, vp])
+    _sig(L, "adk_plan_get_info", "restype", ctypes.c_int)
+    _sig(L, "adk_plan_get_info", "argtypes", [vp, ctypes.POINTER(_PlanInfo)])
+    _sig(L, "adk_plan_destroy", "restype", ctypes.c_int)
+    _sig(L, "adk_plan_destroy", "argtypes", [vp])
+    _sig(L, "adk_field_hash", "restype", ctypes.c_int)
+    _sig(L, "adk_field_hash", "argtypes", [vp, i64, ctypes.c_uint64, i64, dbl, dbl, ctypes.c_int, vp])
+    _sig(L, "adk_ceiling_copy", "restype", ctypes.c_int)
+    _sig(L, "adk_ceiling_copy", "argtypes", [vp, vp, i64, i64, vp])
+    _sig(L, "adk_ceiling_valu", "restype", ctypes.c_int)
+    _sig(L, "adk_ceiling_valu", "argtypes", [i32, i64, vp, i64, vp])
+    _sig(L, "adk_mlp_nparams", "restype", i64)
+    _sig(L, "adk_mlp_nparams", "argtypes", [i32])
+    _sig(L, "adk_mlp_create", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_create", "argtypes", [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_MlpRange), ctypes.POINTER(vp)])
+    _sig(L, "adk_mlp_destroy", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_destroy", "argtypes", [vp])
+    _sig(L, "adk_mlp_get_state", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_get_state", "argtypes", [vp, vp, vp, vp, ctypes.POINTER(i64)])
+    _sig(L, "adk_band_columns", "restype", ctypes.c_int)
+    _sig(L, "adk_band_columns", "argtypes", [vp, vp, vp, vp, i64, vp, vp])
+    _sig(L, "adk_mlp_forward", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_forward", "argtypes", [vp, vp, vp, vp, i64, vp, vp])
+    _sig(L, "adk_mlp_loss_grad", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_loss_grad", "argtypes", [vp, vp, vp, vp, vp, i64, vp, vp, vp])
+    _sig(L, "adk_mlp_forward_trace", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_forward_trace", "argtypes", [vp, vp, vp, vp, i64, vp, vp, vp])
+    _sig(L, "adk_mlp_train", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_train", "argtypes", [vp, vp, ctypes.POINTER(_TrainCfg), vp, vp])
+    _sig(L, "adk_mlp_save", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_save", "argtypes", [vp, ctypes.c_char_p])
+    _sig(L, "adk_mlp_load", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_load", "argtypes", [vp, ctypes.c_char_p, ctypes.POINTER(vp)])
+    _sig(L, "adk_surrogate_step", "restype", ctypes.c_int)
+    _sig(L, "adk_surrogate_step", "argtypes", [vp, vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp, vp])
     _lib = L
     return L
 
@@ -302,6 +323,43 @@ def ionize_step(gas: Gas, E, dt: float, pops, lo, w: int, eps: float = 1e-8, lay
                            ctypes.byref(win), _stream(stream))
     _check(st, "ionize_step")
     return pops, lo
+
+
+def adaptive_work_bytes(ncells: int) -> int:
+    """Bytes of the device workspace ionize_step_adaptive needs for ncells cells."""
+    return int(lib().adk_adaptive_work_bytes(int(ncells)))
+
+
+def adaptive_workspace(ncells: int, device="cuda"):
+    """A device workspace for ionize_step_adaptive (a uint8 tensor)."""
+    import torch
+    return torch.empty(adaptive_work_bytes(ncells), dtype=torch.uint8, device=device)
+
+
+def ionize_step_adaptive(gas: Gas, E, dt: float, pops, lo, wc, wmin: int, wmax: int, eps: float = 1e-8,
+                         tol: float = 1e-9, work=None, counters=None, stream=None):
+    """One step with per-cell adaptive windows, in place on pops
+    [(wmax+1)][ncells], lo and wc (uint8[ncells]); see include/adkion.h.
+    float64 tensors select ADK_F64, float32 tensors ADK_MIXED.  work: a
+    device workspace (adaptive_workspace); counters: optional int64[2]."""
+    import torch
+    n = E.numel()
+    if pops.dtype != E.dtype or tuple(pops.shape) != (wmax + 1, n):
+        raise ValueError(f"pops must be [{wmax + 1}][{n}] of dtype {E.dtype}, got {tuple(pops.shape)} {pops.dtype}")
+    for t, name in ((lo, "lo"), (wc, "wc")):
+        if t.dtype != torch.uint8 or t.numel() != n:
+            raise ValueError(f"{name} must be uint8[ncells]")
+    if work is None:
+        raise ValueError("work: a device workspace of adaptive_work_bytes(ncells) bytes is required")
+    if counters is not None and (counters.dtype != torch.int64 or counters.numel() < 2):
+        raise ValueError("counters must be int64[2]")
+    win = _Adaptive(int(wmin), int(wmax), float(eps), float(tol), _prec_of(E))
+    st = lib().ionize_step_adaptive(gas.handle, _dev(E, "E"), n, float(dt), _dev(pops, "pops"), _dev(lo, "lo"),
+                                    _dev(wc, "wc"), ctypes.byref(win), _dev(work, "work"),
+                                    work.numel() * work.element_size(),
+                                    _dev(counters, "counters") if counters is not None else None, _stream(stream))
+    _check(st, "ionize_step_adaptive")
+    return pops, lo, wc
 
 
 def subcycle_step(gas: Gas, E, dt: float, pops, lo, w: int, nsub: int, eps: float = 1e-8, stream=None):
@@ -495,6 +553,18 @@ class Mlp:
                                      _dev(g, "grad"), _dev(L, "loss"), _stream(stream))
         _check(st, "adk_mlp_loss_grad")
         return L, g
+
+    def forward_trace(self, E, dt, k, stream=None):
+        """(Q[4][n], Zt[n][196]): the forward pass with its float32
+        pre-activations of layers 1-3 and logits (adk_mlp_forward_trace)."""
+        import torch
+        n = E.numel()
+        Q = torch.empty((4, n), dtype=torch.float32, device=E.device)
+        Zt = torch.empty((n, 196), dtype=torch.float32, device=E.device)
+        st = lib().adk_mlp_forward_trace(self._h, _dev(E, "E"), _dev(dt, "dt"), _dev(k, "k"), n, _dev(Q, "Q"),
+                                         _dev(Zt, "Zt"), _stream(stream))
+        _check(st, "adk_mlp_forward_trace")
+        return Q, Zt
 
     def train(self, iters: int, nsamples: int = 1_000_000, batch: int = 4096, lr: float = 3e-3,
               lr_min: float = 1e-5, total_iters: Optional[int] = None, seed: int = 1, stream=None) -> np.ndarray:

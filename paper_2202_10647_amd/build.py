@@ -34,7 +34,7 @@ def _jobs(objdir):
                   "-o", obj], obj))
     obj = os.path.join(objdir, "abi.o")
     jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "abi.hip"), "-o", obj], obj))
-    for name in ("plan", "mlp", "sur", "subcycle", "wide", "ceiling"):
+    for name in ("plan", "mlp", "sur", "subcycle", "wide", "adapt", "ceiling"):
         obj = os.path.join(objdir, f"{name}.o")
         # matrix-core results in ordinary VGPRs (no accumulator-register copies)
         extra = ["-mllvm", "-amdgpu-mfma-vgpr-form"] if name in ("mlp", "sur") else []

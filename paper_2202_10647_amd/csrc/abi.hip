@@ -10,6 +10,14 @@
 
 #include "kernels.hpp"
 
+// Adaptive window (adapt.hip).
+hipError_t adk_step_adaptive(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,
+                             uint8_t *wc, const adk_adaptive *win, void *work, unsigned long long *counters,
+                             hipStream_t st);
+size_t adk_adaptive_work_bytes_impl(int64_t ncells);
+// Chain advance for windows wider than ADK_MAX_W (wide.hip).
+hipError_t adk_advance_wide(int w, const void *Wr, int64_t n, double dt, void *pops, adk_prec prec, hipStream_t st);
+
 namespace adk {
 
 // ---------------------------------------------------------------------------
@@ -236,9 +244,10 @@ int adk_chain_advance(int32_t w, const void *W, int64_t ncells, double dt, void 
 {
     if (ncells < 0 || !valid_prec(prec)) return ADK_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
-    if (w < 1 || w > ADK_MAX_W) return ADK_ERANGE;
+    if (w < 1 || w > ADK_MAX_WIDE_W) return ADK_ERANGE;
     if (ncells > 0 && (!W || !pops)) return ADK_EINVAL;
     if (ncells == 0) return ADK_OK;
+    if (w > ADK_MAX_W) return status_of(adk_advance_wide(w, W, ncells, dt, pops, prec, stream));
     const hipError_t e = (prec == ADK_F64 ? kAdvF64 : kAdvMixed)[w](W, ncells, dt, pops, stream);
     return status_of(e);
 }
@@ -258,6 +267,27 @@ int ionize_step(const adk_gas *gas, const void *E, int64_t ncells, double dt, vo
     const hipError_t e = (win->prec == ADK_F64 ? kStepF64 : kStepMixed)[win->w](gas, E, ncells, dt, pops, lo,
                                                                                win, nullptr, stream);
     return status_of(e);
+}
+
+size_t adk_adaptive_work_bytes(int64_t ncells) { return adk_adaptive_work_bytes_impl(ncells); }
+
+int ionize_step_adaptive(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops, uint8_t *lo,
+                         uint8_t *wc, const adk_adaptive *win, void *work, size_t work_bytes,
+                         unsigned long long *counters, hipStream_t stream)
+{
+    if (!gas || !win || ncells < 0) return ADK_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return ADK_EINVAL;
+    if (!(win->eps >= 0.0) || !std::isfinite(win->eps)) return ADK_EINVAL;
+    if (!(win->tol >= 0.0)) return ADK_EINVAL;
+    if (!valid_prec(win->prec)) return ADK_EINVAL;
+    if (win->wmax < 1 || win->wmax > ADK_MAX_WIDE_W || win->wmax > gas->Z || win->wmin < 0 ||
+        win->wmin > win->wmax)
+        return ADK_ERANGE;
+    if (ncells >= ((int64_t)1 << 31)) return ADK_ERANGE;
+    if (ncells > 0 && (!E || !pops || !lo || !wc || !work)) return ADK_EINVAL;
+    if (ncells > 0 && work_bytes < adk_adaptive_work_bytes_impl(ncells)) return ADK_EINVAL;
+    if (ncells == 0) return ADK_OK;
+    return status_of(adk_step_adaptive(gas, E, ncells, dt, pops, lo, wc, win, work, counters, stream));
 }
 
 int ionize_step_yield(const adk_gas *gas, const void *E, int64_t ncells, double dt, void *pops, uint8_t *lo,

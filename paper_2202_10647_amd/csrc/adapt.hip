@@ -1,0 +1,365 @@
+// Adaptive window (ionize_step_adaptive): the reduced system of Sec. 3, set
+// independently for each cell, with a top that moves up per cell and step.
+//
+// Per cell: the window shift at the start of the step (cut-off criterion
+// after Eq. (9)) moves the bottom up and keeps the top level, so the width wc
+// drops by the shifts; then the top slot t starts at max(wmin, wc) (clipped
+// to level Z) and moves up while the leak
+//     leak(t) = sum_{s <= t, N_s != 0} N_s x_s ... x_t / (t - s + 1)!
+// exceeds the tolerance (x_k = W_{lo+k} dt).  leak(t) bounds the population
+// the full chain moves past slot t within the step (a particle starting at
+// slot s has passed slot t once t - s + 1 exponential waiting times sum to
+// at most dt, probability at most prod x / (t - s + 1)!), which is exactly
+// what the absorbing top holds back: below the top the window's solution is
+// the full chain's.  The window [lo, lo + t] is then solved exactly.
+//
+// Two tiers:
+//   * narrow, one lane per cell: cells whose top stays within slot kNarrowW
+//     solve in registers with the narrow path's chain solution
+//     (chain_apply), rates above their own top set to zero, which makes the
+//     top absorbing and leaves the slots above it empty;
+//   * wide, one wavefront per cell: the narrow kernel lists the other cells
+//     (and cells already wider than kNarrowW) in the workspace, and the wide
+//     kernel solves them with the wide path's sorted-table solution
+//     (chain_sub), up to ADK_MAX_WIDE_W rates.
+// A step is three launches on the stream: clear the list header, narrow,
+// wide.  No allocation and no host synchronisation, so a step can be
+// captured in a HIP graph.
+#include "wide.hpp"
+
+namespace adk {
+namespace {
+
+constexpr int kNarrowW = 3;  // widest window the lane-per-cell tier solves
+
+struct AdaptArgs {
+    int wmin, wmax;
+    double tol;
+};
+
+struct AdaptHeader {
+    uint32_t count;  // cells listed for the wide tier
+    uint32_t pad[63];
+};
+
+__global__ void adaptive_clear_kernel(AdaptHeader *h)
+{
+    if (threadIdx.x == 0) h->count = 0u;
+}
+
+// leak(t) for t = 0..W of one lane's window (double; products of at most
+// W + 1 capped rates stay in range), populations N[0..W], rates x[0..W].
+template <int W, class R>
+__device__ __forceinline__ void leak_all(const double (&N)[W + 1], const R (&x)[W + 1], double (&L)[W + 1])
+{
+    static_for<0, W + 1>([&](auto tt) {
+        constexpr int t = decltype(tt)::value;
+        double acc = 0.0, c = 1.0;
+        static_for<0, t + 1>([&](auto qq) {
+            constexpr int s = t - decltype(qq)::value;  // s = t, t-1, ..., 0
+            constexpr double inv = 1.0 / (t - s + 1);
+            c *= (double)x[s] * inv;  // prod x_s..x_t / (t-s+1)!
+            acc += N[s] != 0.0 ? N[s] * c : 0.0;
+        });
+        L[t] = acc;
+    });
+}
+
+template <class P>
+__global__ __launch_bounds__(kBlock) void adaptive_narrow_kernel(StepArgs a, AdaptArgs ad, ChunkOrder ord,
+                                                                 const typename P::real *__restrict__ E,
+                                                                 typename P::real *__restrict__ pops,
+                                                                 uint8_t *__restrict__ lo, uint8_t *__restrict__ wc,
+                                                                 int64_t n, AdaptHeader *__restrict__ hdr,
+                                                                 int32_t *__restrict__ list,
+                                                                 unsigned long long *__restrict__ counters)
+{
+    using R = typename P::real;
+    constexpr int W = kNarrowW;
+    __shared__ double sc[kDevTableLen];
+    const double *slog = sc + kCoefRows * kCoefStride;
+    stage_coefficients(sc, a.tab, a.ln_dt);
+    const int Z = a.Z;
+    const int lane = threadIdx.x & 63;
+    const int64_t nv = (n + kBlock - 1) / kBlock;
+    for (int64_t v = blockIdx.x; v < nv; v += gridDim.x) {
+        const int64_t c = chunk_place(v, ord) * kBlock + threadIdx.x;
+        const bool valid = c < n;
+        double EL = 0.0;
+        int p = Z, w_in = 0;
+        double N[W + 1];
+        static_for<0, W + 1>([&](auto ss) { N[decltype(ss)::value] = 0.0; });
+        if (valid) {
+            EL = fabs((double)E[c]);
+            const int l0 = lo[c];
+            p = l0 < Z ? l0 : Z;
+            const int w0 = wc[c];
+            w_in = w0 < ad.wmax ? w0 : ad.wmax;
+            N[0] = (double)pops[c];
+        }
+        // windows already wider than this tier go to the wide tier
+        const bool wide_now = valid && p < Z && w_in > W;
+        static_for<1, W + 1>([&](auto ss) {
+            constexpr int s = decltype(ss)::value;
+            if (valid && !wide_now && s <= w_in) N[s] = (double)pops[(int64_t)s * n + c];
+        });
+        // fully stripped, or every rate of the gas below 1e-30 per step with
+        // no shift due: the step moves less than 1e-30 of the population, and
+        // with a tolerance of at least 1e-30 the top stays at max(wmin, wc)
+        const bool quiet = !valid || p >= Z || (ad.tol >= 1e-30 && EL < a.E_cut && N[0] >= a.eps);
+        bool go_wide = wide_now && !quiet;
+        if (!__all(quiet) && !quiet && !wide_now) {
+            int w = w_in;
+            while (p < Z && N[0] < a.eps) {
+                N[0] += N[1];
+                static_for<1, W>([&](auto ss) {
+                    constexpr int s = decltype(ss)::value;
+                    N[s] = N[s + 1];
+                });
+                N[W] = 0.0;
+                ++p;
+                w = w > 0 ? w - 1 : 0;
+            }
+            const int room = min(ad.wmax, Z - p);
+            const int t0 = min(max(ad.wmin, w), Z - p);
+            R x[W + 1];
+            const Field f = field_terms<RateEval<P>::kLogTerms>(EL, slog);
+            window_rates<P, W + 1>(sc, p, f, a.has_poly != 0, x);
+            double L[W + 1];
+            leak_all<W>(N, x, L);
+            // top: the lowest slot t in [t0, room) with leak(t) <= tol, else
+            // room (a NaN leak widens); above slot W it is the wide tier's
+            int top = t0;
+            bool found = false;
+            static_for<0, W + 1>([&](auto tt) {
+                constexpr int t = decltype(tt)::value;
+                if (!found && t >= t0 && t < room) {
+                    if (L[t] <= ad.tol) found = true;
+                    else top = t + 1;
+                }
+            });
+            if (!found) top = top > room ? top : room;  // every tested slot leaks: top = room
+            if (top > W) {
+                go_wide = true;
+            } else {
+                // the storage limit held the top back (its own leak above tol)
+                double Ltop = 0.0;
+                static_for<0, W + 1>([&](auto tt) {
+                    constexpr int t = decltype(tt)::value;
+                    Ltop = t == top ? L[t] : Ltop;  // selects, not a dynamic index
+                });
+                if (counters && !found && top < Z - p && !(Ltop <= ad.tol)) atomicAdd(&counters[1], 1ull);
+                const bool finite = EL <= 1.7976931348623157e308;
+                R xw[W];
+                static_for<0, W>([&](auto kk) {
+                    constexpr int k = decltype(kk)::value;
+                    xw[k] = k < top ? x[k] : R(0);
+                });
+                double out[W + 1];
+                chain_apply<P, W>(xw, N, out);
+                // slots above the top received only rounding residue of the
+                // absorbing row: it goes to the top, they hold zero
+                double extra = 0.0;
+                static_for<1, W + 1>([&](auto ss) {
+                    constexpr int s = decltype(ss)::value;
+                    const bool above = s > top;
+                    extra += above ? out[s] : 0.0;
+                    out[s] = above ? 0.0 : out[s];
+                });
+                static_for<0, W + 1>([&](auto ss) {
+                    constexpr int s = decltype(ss)::value;
+                    out[s] += s == top ? extra : 0.0;
+                });
+                const int wst = max(w_in, top);
+                static_for<0, W + 1>([&](auto ss) {
+                    constexpr int s = decltype(ss)::value;
+                    if (s <= wst) pops[(int64_t)s * n + c] = finite ? (R)out[s] : R(NAN);
+                });
+                lo[c] = (uint8_t)p;
+                wc[c] = (uint8_t)top;
+            }
+        }
+        if (valid && quiet) {
+            // T = I: only an index past Z or a width below wmin changes
+            const int w_new = p >= Z ? 0 : min(max(ad.wmin, w_in), Z - p);
+            if (p != lo[c]) lo[c] = (uint8_t)p;
+            if (w_new != wc[c]) wc[c] = (uint8_t)w_new;
+        }
+        // list the wide cells: one atomic per wavefront
+        const unsigned long long mask = __ballot(go_wide);
+        if (mask) {
+            const int leader = __ffsll((long long)mask) - 1;
+            uint32_t base = 0;
+            if (lane == leader) {
+                const int cnt = __popcll(mask);
+                base = atomicAdd(&hdr->count, (uint32_t)cnt);
+                if (counters) atomicAdd(&counters[0], (unsigned long long)cnt);
+            }
+            base = __shfl(base, leader);
+            if (go_wide) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)c;
+        }
+    }
+}
+
+// Wide tier: one wavefront per listed cell (double arithmetic).  LDS as the
+// wide ionize_step path (wide_wave_doubles) plus the leak scratch.
+template <class R>
+__device__ void adaptive_wide_cell(const StepArgs &a, const AdaptArgs &ad, int64_t c, const R *__restrict__ E,
+                                   R *__restrict__ pops, uint8_t *__restrict__ lo, uint8_t *__restrict__ wc,
+                                   int64_t n, double *s, double *e, double *mm, double *Nb, int *cid, int *pos,
+                                   double *D, double *V, double *lx, double *lN,
+                                   unsigned long long *__restrict__ counters)
+{
+    const int lane = wide_lane();
+    const int Z = a.Z;
+    const int wmax = ad.wmax;
+    wave_sync();  // the previous cell's reads of LDS are done
+    const double EL = fabs((double)E[c]);
+    const int l0 = lo[c];
+    int p = l0 < Z ? l0 : Z;
+    const int w0 = wc[c];
+    const int w_in = w0 < wmax ? w0 : wmax;
+    double Ns = lane <= w_in ? (double)pops[(int64_t)lane * n + c] : 0.0;
+    int w = w_in;
+    while (p < Z && __shfl(Ns, 0) < a.eps) {
+        const double up = __shfl_down(Ns, 1);
+        Ns = lane == 0 ? Ns + up : (lane < wmax ? up : 0.0);
+        ++p;
+        w = w > 0 ? w - 1 : 0;
+    }
+    const int room = min(wmax, Z - p);
+    const int t0 = min(max(ad.wmin, w), Z - p);
+    const bool finite = EL <= 1.7976931348623157e308 || p >= Z;
+    double out = Ns;
+    int top = t0;
+    if (p < Z) {
+        const Field f = field_terms<RateEval<PolicyF64>::kLogTerms>(EL, a.tab + kCoefRows * kCoefStride);
+        double x = 0.0;
+        if (lane <= room && p + lane < Z) {
+            double row[kCoefStride];
+            for (int k = 0; k < kCoefStride; ++k) row[k] = a.tab[(p + lane) * kCoefStride + k];
+            row[0] += a.ln_dt * kLog2e;
+            x = RateEval<PolicyF64>::x_of(row, f, a.has_poly != 0);
+        }
+        // leak(t) of lane t, in the log domain (products of many capped
+        // rates leave the double range)
+        if (lane <= room) {
+            lx[lane] = log(x);
+            lN[lane] = Ns != 0.0 ? log(fabs(Ns)) : -INFINITY;
+        }
+        wave_sync();
+        double leak = 0.0;
+        if (lane >= t0 && lane <= room) {
+            double path = 0.0;
+            for (int q = lane; q >= 0; --q) {
+                path += lx[q];
+                if (lN[q] > -INFINITY) leak += exp(lN[q] + path - kLogFact.v[lane - q + 1]);
+            }
+        }
+        // top: the lowest slot t in [t0, room) with leak(t) <= tol (a NaN
+        // leak widens), else room
+        const unsigned long long okm = __ballot(lane >= t0 && lane < room && leak <= ad.tol);
+        top = okm ? __ffsll((long long)okm) - 1 : room;
+        // the storage limit held the top back
+        const bool held = !okm && room < Z - p && !(__shfl(leak, room) <= ad.tol);
+        if (held && counters && lane == 0) atomicAdd(&counters[1], 1ull);
+        wave_sync();
+        if (top > 0 && finite) {
+            const double r = chain_sub(top, lane < top ? x : 0.0, lane <= top ? Ns : 0.0, s, e, mm, Nb, cid, pos,
+                                       D, V, wmax);
+            if (lane <= top) out = r;
+        }
+    }
+    const int wst = max(w_in, top);
+    if (lane <= wst) {
+        const double v = finite ? (lane <= top ? out : 0.0) : (double)NAN;
+        pops[(int64_t)lane * n + c] = (R)v;
+    }
+    if (lane == 0) {
+        lo[c] = (uint8_t)p;
+        wc[c] = (uint8_t)(p >= Z ? 0 : top);
+    }
+}
+
+constexpr size_t adaptive_wave_doubles(int W) { return wide_wave_doubles(W) + 128; }
+
+template <class R>
+__global__ __launch_bounds__(kWideBlock) void adaptive_wide_kernel(StepArgs a, AdaptArgs ad,
+                                                                   const R *__restrict__ E, R *__restrict__ pops,
+                                                                   uint8_t *__restrict__ lo,
+                                                                   uint8_t *__restrict__ wc, int64_t n,
+                                                                   const AdaptHeader *__restrict__ hdr,
+                                                                   const int32_t *__restrict__ list,
+                                                                   unsigned long long *__restrict__ counters)
+{
+    extern __shared__ __align__(16) double wl[];
+    const int W = ad.wmax;
+    int *cid = (int *)(wl + 256);
+    int *pos = cid + 64;
+    double *D = wl + 384;
+    double *V = D + W * (W + 1) / 2;
+    double *lx = wl + wide_wave_doubles(W);
+    double *lN = lx + 64;
+    const uint32_t count = hdr->count;
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const int64_t c = list[i];
+        adaptive_wide_cell<R>(a, ad, c, E, pops, lo, wc, n, wl, wl + 64, wl + 128, wl + 192, cid, pos, D, V, lx,
+                              lN, counters);
+    }
+}
+
+template <class P>
+hipError_t launch_adaptive(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,
+                           uint8_t *wc, const adk_adaptive *win, void *work, unsigned long long *counters,
+                           hipStream_t st)
+{
+    using R = typename P::real;
+    const StepArgs a = step_args(g, dt, win->eps);
+    AdaptArgs ad;
+    ad.wmin = win->wmin;
+    ad.wmax = win->wmax;
+    ad.tol = win->tol;
+    AdaptHeader *hdr = (AdaptHeader *)work;
+    int32_t *list = (int32_t *)((char *)work + sizeof(AdaptHeader));
+    hipLaunchKernelGGL(adaptive_clear_kernel, dim3(1), dim3(64), 0, st, hdr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int grid = resident_grid<adaptive_narrow_kernel<P>>(n, kStepChunksPerGroup);
+    hipLaunchKernelGGL((adaptive_narrow_kernel<P>), dim3(grid), dim3(kBlock), 0, st, a, ad, chunk_order(n),
+                       (const R *)E, (R *)pops, lo, wc, n, hdr, list, counters);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t dyn = sizeof(double) * adaptive_wave_doubles(ad.wmax);
+    static int per_cu[ADK_MAX_WIDE_W + 1] = {};  // occupancy per widest window (LDS grows with it)
+    int b = per_cu[ad.wmax];
+    if (b <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, adaptive_wide_kernel<R>, kWideBlock, dyn) !=
+                hipSuccess ||
+            b <= 0)
+            b = 1;
+        per_cu[ad.wmax] = b;
+    }
+    const int64_t need = (n + kWideBlock - 1) / kWideBlock;
+    const int64_t cap = (int64_t)num_cus() * b;
+    const int wgrid = (int)(need < cap ? need : cap);
+    hipLaunchKernelGGL(adaptive_wide_kernel<R>, dim3(wgrid), dim3(kWideBlock), dyn, st, a, ad, (const R *)E,
+                       (R *)pops, lo, wc, n, (const AdaptHeader *)hdr, (const int32_t *)list, counters);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace adk
+
+size_t adk_adaptive_work_bytes_impl(int64_t ncells)
+{
+    return sizeof(adk::AdaptHeader) + sizeof(int32_t) * (size_t)(ncells > 0 ? ncells : 0);
+}
+
+hipError_t adk_step_adaptive(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,
+                             uint8_t *wc, const adk_adaptive *win, void *work, unsigned long long *counters,
+                             hipStream_t st)
+{
+    return win->prec == ADK_F64
+               ? adk::launch_adaptive<adk::PolicyF64>(g, E, n, dt, pops, lo, wc, win, work, counters, st)
+               : adk::launch_adaptive<adk::PolicyMixed>(g, E, n, dt, pops, lo, wc, win, work, counters, st);
+}

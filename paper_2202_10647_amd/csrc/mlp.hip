@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -135,7 +136,10 @@ struct FwdArgs {
     float *dZ4;            // (Q - P) / n, [n][4]
     float *lossv;          // per-sample cross entropy [n]
     float *Q;              // network output [4][n] or null
+    float *Zt;             // pre-activations and logits [n][kTraceRow] (fwd_kernel<true>) or null
 };
+
+constexpr int kTraceRow = 3 * kH + kBand;  // z1, z2, z3 (float32, before rounding), logits z4
 
 __device__ __forceinline__ void store_h(__bf16 *H, int64_t row, int g, const bf16x8 (&h)[2])
 {
@@ -149,6 +153,7 @@ __device__ __forceinline__ void store_h(__bf16 *H, int64_t row, int g, const bf1
     }
 }
 
+template <bool TRACE>
 __global__ __launch_bounds__(kBlock) void fwd_kernel(FwdArgs a)
 {
     __shared__ MlpShared s;
@@ -167,8 +172,13 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(FwdArgs a)
         const int64_t si = a.off + ii;
         const int k = a.K[si];
         bf16x8 h1[2], h2[2], h3[2];
-        const f32x4 z = mlp_logits<true>(r, s.b2 + opaque_zero(), ctab + k * kH, a.U[si], a.V[si], 0, h1,
-                                                   h2, h3);
+        float *zt = (TRACE && ok) ? a.Zt + ii * kTraceRow : nullptr;
+        const f32x4 z = mlp_logits<true, TRACE>(r, s.b2 + opaque_zero(), ctab + k * kH, a.U[si], a.V[si], 0, h1,
+                                                h2, h3, zt);
+        if (TRACE && ok && g == 0) {
+#pragma unroll
+            for (int j = 0; j < kBand; ++j) zt[3 * kH + j] = z[j];
+        }
         if (ok && a.H1) {
             store_h(a.H1, ii, g, h1);
             store_h(a.H2, ii, g, h2);
@@ -570,10 +580,20 @@ int ensure_scratch(adk_mlp *m, int64_t n)
     return ADK_OK;
 }
 
+// Device buffers of one gradient pass over n samples: activations, output
+// deltas, per-sample losses, per-chunk partial gradients and their sum, and
+// the gradient itself.
+struct GradBufs {
+    __bf16 *H1, *H2, *H3;
+    float *dZ4, *lossv, *part, *red, *grad;
+};
+
+GradBufs bufs_of(adk_mlp *m) { return {m->H1, m->H2, m->H3, m->dZ4, m->lossv, m->part, m->red, m->grad}; }
+
 // forward (storing activations), loss, backward and gradient of samples
-// off..off+n-1 of (U, V, K, P); the gradient lands in m->grad, the loss in *loss.
-hipError_t grad_pass(adk_mlp *m, const float *U, const float *V, const uint8_t *K, const float *P, int64_t off,
-                     int64_t n, float *loss, hipStream_t st)
+// off..off+n-1 of (U, V, K, P); the gradient lands in B.grad, the loss in *loss.
+hipError_t grad_pass(const adk_mlp *m, const GradBufs &B, const float *U, const float *V, const uint8_t *K,
+                     const float *P, int64_t off, int64_t n, float *loss, hipStream_t st)
 {
     FwdArgs f{};
     f.prm = m->prm;
@@ -585,16 +605,16 @@ hipError_t grad_pass(adk_mlp *m, const float *U, const float *V, const uint8_t *
     f.off = off;
     f.n = n;
     f.inv_n = (float)(1.0 / (double)n);
-    f.H1 = m->H1;
-    f.H2 = m->H2;
-    f.H3 = m->H3;
-    f.dZ4 = m->dZ4;
-    f.lossv = m->lossv;
+    f.H1 = B.H1;
+    f.H2 = B.H2;
+    f.H3 = B.H3;
+    f.dZ4 = B.dZ4;
+    f.lossv = B.lossv;
     const int64_t waves = (n + 15) / 16;
     const int64_t gmax = (int64_t)num_cus() * 2;
     int64_t g = (waves + 3) / 4;
     g = g < gmax ? g : gmax;
-    hipLaunchKernelGGL(fwd_kernel, dim3((int)g), dim3(kBlock), 0, st, f);
+    hipLaunchKernelGGL(fwd_kernel<false>, dim3((int)g), dim3(kBlock), 0, st, f);
     BwdArgs b{};
     b.prm = m->prm;
     b.L = m->L;
@@ -604,18 +624,18 @@ hipError_t grad_pass(adk_mlp *m, const float *U, const float *V, const uint8_t *
     b.K = K;
     b.off = off;
     b.n = n;
-    b.H1 = m->H1;
-    b.H2 = m->H2;
-    b.H3 = m->H3;
-    b.dZ4 = m->dZ4;
-    b.part = m->part;
+    b.H1 = B.H1;
+    b.H2 = B.H2;
+    b.H3 = B.H3;
+    b.dZ4 = B.dZ4;
+    b.part = B.part;
     const int nch = (int)((n + kCh - 1) / kCh);
     hipLaunchKernelGGL(bwd_kernel, dim3(nch), dim3(kBlock), 0, st, b);
-    hipLaunchKernelGGL(reduce_kernel, dim3(small_grid(m->PL.n)), dim3(kBlock), 0, st, (const float *)m->part, nch,
-                       m->PL.n, m->red);
+    hipLaunchKernelGGL(reduce_kernel, dim3(small_grid(m->PL.n)), dim3(kBlock), 0, st, (const float *)B.part, nch,
+                       m->PL.n, B.red);
     hipLaunchKernelGGL(finish_kernel, dim3(small_grid(m->L.n)), dim3(kBlock), 0, st, (const float *)m->prm, m->L,
-                       m->PL, (const float *)m->red, m->grad);
-    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(kBlock), 0, st, (const float *)m->lossv, n, f.inv_n, loss);
+                       m->PL, (const float *)B.red, B.grad);
+    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(kBlock), 0, st, (const float *)B.lossv, n, f.inv_n, loss);
     return hipGetLastError();
 }
 
@@ -721,6 +741,27 @@ int adk_band_columns(const adk_gas *gas, const double *E, const double *dt, cons
 
 namespace {
 
+// Features (and, with a gas, exact float columns) of caller-given samples
+// into U, V, K (and P).
+int launch_given(const adk_mlp *m, const adk_gas *gas, const double *E, const double *dt, const int32_t *k,
+                 int64_t n, float *U, float *V, uint8_t *K, float *P, hipStream_t stream)
+{
+    DataArgs a = gas ? data_args(gas, *m) : DataArgs{};
+    if (!gas) {
+        const MlpFeatures F = features(*m);
+        a.Z = m->Z;
+        a.au = F.au;
+        a.bu = F.bu;
+        a.av = F.av;
+        a.bv = F.bv;
+        a.omega_a = m->omega_a;
+    }
+    a.labels = gas ? 1 : 0;
+    hipLaunchKernelGGL(data_kernel, dim3(small_grid(n)), dim3(kBlock), 0, stream, a, E, dt, k, n, U, V, K,
+                       gas ? P : (float *)nullptr, (double *)nullptr);
+    return status_of(hipGetLastError());
+}
+
 // Features (and, with a gas, exact float columns) of caller-given samples in
 // the mlp's x-buffers.
 int prepare_given(adk_mlp *m, const adk_gas *gas, const double *E, const double *dt, const int32_t *k, int64_t n,
@@ -739,20 +780,7 @@ int prepare_given(adk_mlp *m, const adk_gas *gas, const double *E, const double 
         if (st) return st;
         m->xcap = n;
     }
-    DataArgs a = gas ? data_args(gas, *m) : DataArgs{};
-    if (!gas) {
-        const MlpFeatures F = features(*m);
-        a.Z = m->Z;
-        a.au = F.au;
-        a.bu = F.bu;
-        a.av = F.av;
-        a.bv = F.bv;
-        a.omega_a = m->omega_a;
-    }
-    a.labels = gas ? 1 : 0;
-    hipLaunchKernelGGL(data_kernel, dim3(small_grid(n)), dim3(kBlock), 0, stream, a, E, dt, k, n, m->xU, m->xV,
-                       m->xK, gas ? m->xP : (float *)nullptr, (double *)nullptr);
-    return status_of(hipGetLastError());
+    return launch_given(m, gas, E, dt, k, n, m->xU, m->xV, m->xK, m->xP, stream);
 }
 
 }  // namespace
@@ -779,7 +807,34 @@ int adk_mlp_forward(const adk_mlp *m, const double *E, const double *dt, const i
     const int64_t gmax = (int64_t)num_cus() * 2;
     int64_t g = (waves + 3) / 4;
     g = g < gmax ? g : gmax;
-    hipLaunchKernelGGL(fwd_kernel, dim3((int)g), dim3(kBlock), 0, stream, f);
+    hipLaunchKernelGGL(fwd_kernel<false>, dim3((int)g), dim3(kBlock), 0, stream, f);
+    return status_of(hipGetLastError());
+}
+
+int adk_mlp_forward_trace(const adk_mlp *m, const double *E, const double *dt, const int32_t *k, int64_t n,
+                          float *Q, float *Zt, hipStream_t stream)
+{
+    if (!m || n < 0) return ADK_EINVAL;
+    if (n > 0 && (!E || !dt || !k || !Q || !Zt)) return ADK_EINVAL;
+    if (n == 0) return ADK_OK;
+    adk_mlp *mm = const_cast<adk_mlp *>(m);
+    int st = prepare_given(mm, nullptr, E, dt, k, n, stream);
+    if (st) return st;
+    FwdArgs f{};
+    f.prm = m->prm;
+    f.L = m->L;
+    f.U = mm->xU;
+    f.V = mm->xV;
+    f.K = mm->xK;
+    f.n = n;
+    f.inv_n = 1.0f;
+    f.Q = Q;
+    f.Zt = Zt;
+    const int64_t waves = (n + 15) / 16;
+    const int64_t gmax = (int64_t)num_cus() * 2;
+    int64_t g = (waves + 3) / 4;
+    g = g < gmax ? g : gmax;
+    hipLaunchKernelGGL(fwd_kernel<true>, dim3((int)g), dim3(kBlock), 0, stream, f);
     return status_of(hipGetLastError());
 }
 
@@ -791,7 +846,7 @@ int adk_mlp_loss_grad(adk_mlp *m, const adk_gas *gas, const double *E, const dou
     int st = ensure_scratch(m, n);
     if (!st) st = prepare_given(m, gas, E, dt, k, n, stream);
     if (st) return st;
-    hipError_t e = grad_pass(m, m->xU, m->xV, m->xK, m->xP, 0, n, loss, stream);
+    hipError_t e = grad_pass(m, bufs_of(m), m->xU, m->xV, m->xK, m->xP, 0, n, loss, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(grad, m->grad, sizeof(float) * (size_t)m->L.n, hipMemcpyDeviceToDevice, stream);
     return status_of(e);
@@ -848,7 +903,7 @@ int adk_mlp_train(adk_mlp *m, const adk_gas *gas, const adk_train_cfg *cfg, floa
     for (int it = 0; it < cfg->iters; ++it) {
         const int64_t t = m->step;  // steps taken before this one
         const int64_t off = (t % nbatches) * cfg->batch;
-        hipError_t e = grad_pass(m, m->U, m->V, m->K, m->P, off, cfg->batch, m->losses + it, stream);
+        hipError_t e = grad_pass(m, bufs_of(m), m->U, m->V, m->K, m->P, off, cfg->batch, m->losses + it, stream);
         const double tt = (double)(t < cfg->total_iters ? t : cfg->total_iters);
         const double lr = cfg->lr_min + 0.5 * (cfg->lr - cfg->lr_min) * (1.0 + std::cos(M_PI * tt / T));
         const double c1 = 1.0 / (1.0 - std::pow(b1, (double)(t + 1)));

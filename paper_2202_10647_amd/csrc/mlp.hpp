@@ -189,9 +189,14 @@ __device__ __forceinline__ bf16x8 relu_pack(const f32x4 &lo, const f32x4 &hi)
 // The output tile has the four logits in rows 4 qo .. 4 qo + 3 (the other
 // rows are zero), so lane (qo, n) receives sample n's logits: lane group qo
 // is chosen by the caller (the lanes that own the samples).
-template <bool USE_V>
+//
+// With TRACE the float32 pre-activations of layers 1-3 (before rounding to
+// bfloat16) go to zt, the row of the lane's sample (units in order: z1 at
+// 0..63, z2 at 64..127, z3 at 128..191), when zt is not null.
+template <bool USE_V, bool TRACE = false>
 __device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *sf, const float *crow, float u, float v,
-                                            int qo, bf16x8 (&h1)[2], bf16x8 (&h2)[2], bf16x8 (&h3)[2])
+                                            int qo, bf16x8 (&h1)[2], bf16x8 (&h2)[2], bf16x8 (&h3)[2],
+                                            float *zt = nullptr)
 {
     const int g = (threadIdx.x & 63) >> 4;
     const float *b2 = sf, *b3 = sf + kH, *b4 = sf + 2 * kH, *wu = b4 + 16, *wv = wu + kH;
@@ -210,6 +215,10 @@ __device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *sf, c
             z[i] = fmaf(u0[i], u, a0);
             z[i + 4] = fmaf(u1[i], u, a1);
         }
+        if (TRACE && zt) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) zt[hid(c, g, i)] = z[i];
+        }
         const u32x4 w = {pack2(z[0], z[1]), pack2(z[2], z[3]), pack2(z[4], z[5]), pack2(z[6], z[7])};
         h1[c] = relu_bf16(w);
     }
@@ -220,6 +229,12 @@ __device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *sf, c
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], h1[c], acc[t], 0, 0, 0);
     }
+    if (TRACE && zt) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) zt[kH + 16 * t + 4 * g + i] = acc[t][i];
+    }
 #pragma unroll
     for (int c = 0; c < 2; ++c) h2[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);
 #pragma unroll
@@ -227,6 +242,12 @@ __device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *sf, c
         acc[t] = lds4(b3 + 16 * t + 4 * g);
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], h2[c], acc[t], 0, 0, 0);
+    }
+    if (TRACE && zt) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) zt[2 * kH + 16 * t + 4 * g + i] = acc[t][i];
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) h3[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);

@@ -112,7 +112,7 @@ def test_chain_advance_validation_before_device(L):
     f = L.adk_chain_advance
     p = ctypes.c_void_p(16)
     assert f(0, p, 10, 1e-16, p, 0, None) == adkion.ADK_ERANGE
-    assert f(9, p, 10, 1e-16, p, 0, None) == adkion.ADK_ERANGE
+    assert f(64, p, 10, 1e-16, p, 0, None) == adkion.ADK_ERANGE
     assert f(3, p, -1, 1e-16, p, 0, None) == adkion.ADK_EINVAL
     assert f(3, p, 10, 0.0, p, 0, None) == adkion.ADK_EINVAL
     assert f(3, p, 10, float("inf"), p, 0, None) == adkion.ADK_EINVAL
@@ -238,3 +238,15 @@ def test_ceiling_host_validation(L):
 def test_plan_graph_replay_host_validation(L):
     assert L.adk_plan_graph_replay(None, 1, None) == adkion.ADK_EINVAL
     assert L.adk_plan_graph_replay(None, -1, None) == adkion.ADK_EINVAL
+
+
+def test_adaptive_host_validation(L):
+    """Workspace size and the host-side rejections of ionize_step_adaptive
+    that need no gas on a device."""
+    assert L.adk_adaptive_work_bytes(0) == 256
+    assert L.adk_adaptive_work_bytes(1000) == 256 + 4000
+    win = adkion._Adaptive(1, 8, 1e-8, 1e-9, adkion.ADK_MIXED)
+    E = adkion.ADK_EINVAL
+    assert L.ionize_step_adaptive(None, None, 4, 1e-16, None, None, None, ctypes.byref(win), None, 0, None,
+                                  None) == E
+    assert L.ionize_step_adaptive(None, None, 0, 1e-16, None, None, None, None, None, 0, None, None) == E

@@ -1,16 +1,25 @@
 """Band-column surrogate on the GPU against the CPU references: exact band
-columns (FP64 analytic solver) against the oracle, network output and
-gradient against the FP64 network with bfloat16 operands, one Adam step,
-deterministic and resumable training, the surrogate-form step against its
-reference, graph replay, fallback, and what training gains.
+columns (FP64 analytic solver) against the oracle, the network element by
+element against its FP64 reference, the gradient element by element, one
+Adam step, deterministic and resumable training, the surrogate-form step
+against its reference, graph replay, fallback, and what training gains.
 
-Tolerances of the network comparisons.  The device network rounds h1, h2 and
-h3 to bfloat16 after FP32 arithmetic, the reference after FP64 arithmetic.
-The pre-rounding values differ by ~1e-7 relative, so on a small fraction of
-the activations the two sides round to neighbouring bfloat16 values (one
-unit in the 8th bit, 0.4-0.8 % of the value); such a sample's output moves
-by up to ~1e-3.  Elsewhere the outputs agree to FP32 rounding (~1e-6).  The
-tests therefore bound a high quantile tightly and the maximum loosely."""
+Rounding decisions of the network.  The device rounds each hidden layer's
+float32 pre-activations to bfloat16; the FP64 reference computes the same
+pre-activations to within float32 accumulation error but can land on the
+other side of a bfloat16 rounding boundary, and one such flip moves the
+output by up to ~1e-3.  The decisions are the kernel's (its precision), so
+the tests take them from the device: the traced forward pass exports every
+float32 pre-activation, and each layer is checked element by element
+against the reference layer map applied to the previous layer's device
+values rounded by the reference's own bfloat16 function
+(oracle.mlp.layer_maps): |z_dev - z_ref| within float32 accumulation error
+of the terms (4e-6 of the sum of their magnitudes), for every unit of every
+sample, and the output against the softmax of the device logits to 1e-6.
+Validated this way, the device's activations then serve as the rounding
+decisions of the gradient and surrogate-step references (loss_and_grad with
+acts, surrogate_step with cols_given), which are compared element by
+element."""
 import numpy as np
 import pytest
 
@@ -62,25 +71,72 @@ def test_band_columns_match_oracle(env, orc, Z):
     assert np.all(np.isnan(bad))
 
 
+def check_trace(params, Z, E, dt, k, Q, Zt):
+    """Element-wise check of one traced forward pass (see the module
+    docstring); returns the validated bfloat16 activations (h1, h2, h3) and
+    the columns softmax(z4_dev) in FP64 ([4][n])."""
+    params = np.asarray(params, np.float64)
+    b = mlp.unpack(params, Z)
+    u, v = RNG.features(E, dt)
+    z1, z2, z3, z4 = Zt[:, :64], Zt[:, 64:128], Zt[:, 128:192], Zt[:, 192:196]
+    m = mlp.layer_maps(params, Z, u, v, k, z1, z2, z3)
+    # layer 1: the device's features are float32 (log2 in float): |du| <= 2e-6, |dv| <= 2e-7
+    tol1 = 2e-6 * np.abs(b["W1u"]) + 2e-7 * np.abs(b["W1v"]) + 2e-6 * m["S1"]
+    d1 = np.abs(z1 - m["z1"])
+    assert np.all(d1 <= tol1), (float((d1 / tol1).max()), np.unravel_index(np.argmax(d1 / tol1), d1.shape))
+    for i, z in ((2, z2), (3, z3), (4, z4)):
+        d = np.abs(z - m[f"z{i}"])
+        tol = 4e-6 * m[f"S{i}"] + 1e-30
+        assert np.all(d <= tol), (i, float((d / tol).max()))
+    ez = np.exp(z4 - z4.max(axis=1, keepdims=True))
+    cols = (ez / ez.sum(axis=1, keepdims=True)).T
+    assert np.max(np.abs(Q - cols)) <= 1e-6
+    acts = tuple(mlp.bf16(np.maximum(z, 0.0)) for z in (z1, z2, z3))
+    return acts, cols
+
+
+def traced(net, torch, E, dt, k):
+    Q, Zt = net.forward_trace(*_dev(torch, E, dt, k))
+    return Q.cpu().numpy().astype(np.float64), Zt.cpu().numpy().astype(np.float64)
+
+
 def test_forward_matches_oracle(env, orc):
+    """Every unit of every sample, layer by layer, against the reference
+    (module docstring); the plain forward entry point gives the traced pass's
+    output bit for bit; conservation and positivity of the columns."""
     torch, ak, gases = env
     Z = 36
     gas, _ = gases[Z]
     params = wl.mlp_init(Z, 5)
+    b = mlp.unpack(params.astype(np.float64).copy(), Z)
+    r = np.random.default_rng(4)
+    for name in ("b1", "b2", "b3", "b4"):
+        b[name][:] = r.uniform(-0.2, 0.2, b[name].shape)
+    params = mlp.pack(b, Z).astype(np.float32)
     net = ak.Mlp(gas, params)
     n = 20000 + 7
     E, dt, k = wl.surrogate_samples(n, 22, Z)
+    E[:50] = 10.0
+    E[50:100] = 5000.0
+    Qt, Zt = traced(net, torch, E, dt, k)
+    check_trace(params, Z, E, dt, k, Qt, Zt)
     Q = net.forward(*_dev(torch, E, dt, k)).cpu().numpy().astype(np.float64)
+    assert np.array_equal(Q, Qt)
+    assert np.all(Q >= 0) and np.allclose(Q.sum(axis=0), 1.0, atol=1e-6)
+    # the FP64 network's own rounding decisions reach the same columns except
+    # where a pre-activation lies at a rounding boundary: report how often
     u, v = RNG.features(E, dt)
     Qo, _ = mlp.forward(params.astype(np.float64), Z, u, v, k)
     d = np.abs(Q - Qo.T).max(axis=0)
-    assert np.quantile(d, 0.9) <= 1e-5, np.quantile(d, [0.5, 0.9, 0.99])
-    assert d.max() <= 1e-2
-    assert np.all(Q >= 0) and np.allclose(Q.sum(axis=0), 1.0, atol=1e-6)
+    print(f"samples whose columns differ from the FP64 network's own roundings by > 1e-5: {np.mean(d > 1e-5):.4f}")
     net.close()
 
 
 def test_loss_grad_matches_oracle(env, orc):
+    """Loss and every gradient entry against the FP64 backward pass taken
+    with the device's validated activations (its rounding decisions): relative
+    1e-3 with an absolute floor of 1e-5 of the largest entry of the block
+    (float32 sums over the batch)."""
     torch, ak, gases = env
     Z = 36
     gas, spec = gases[Z]
@@ -95,16 +151,20 @@ def test_loss_grad_matches_oracle(env, orc):
     E, dt, k = wl.surrogate_samples(n, 23, Z)
     P = mlp.exact_band_columns(orc, spec, Z, E, dt, k).T
     u, v = RNG.features(E, dt)
-    Lo, go = mlp.loss_and_grad(params.astype(np.float64), Z, u, v, k, P)
+    Qt, Zt = traced(net, torch, E, dt, k)
+    acts, _ = check_trace(params, Z, E, dt, k, Qt, Zt)
+    Lo, go = mlp.loss_and_grad(params.astype(np.float64), Z, u, v, k, P, acts=acts)
     L, g = net.loss_grad(*_dev(torch, E, dt, k))
     L = float(L.item())
     g = g.cpu().numpy().astype(np.float64)
-    assert abs(L - Lo) <= 1e-4 * Lo, (L, Lo)
+    assert abs(L - Lo) <= 1e-5 * Lo, (L, Lo)
     off = 0
     for name, shape in mlp.block_shapes(Z):
         m = int(np.prod(shape))
         a, o = g[off:off + m], go[off:off + m]
-        assert np.linalg.norm(a - o) <= 2e-3 * np.linalg.norm(o) + 1e-9, (name, np.linalg.norm(a - o), np.linalg.norm(o))
+        tol = 1e-3 * np.abs(o) + 1e-5 * np.abs(o).max() + 1e-12
+        worst = float((np.abs(a - o) / tol).max())
+        assert worst <= 1.0, (name, worst, float(np.abs(a - o).max()), float(np.abs(o).max()))
         off += m
     net.close()
 
@@ -185,6 +245,49 @@ def _mixed_fields(n, seed):
     return E.astype(np.float32)
 
 
+def surrogate_check(orc, spec, Z, params, net, torch, E, dt, N, lo, w, eps, got, glo):
+    """The device's surrogate step against the reference taken with the
+    device network's validated columns (check_trace on every (cell, source)
+    pair of an in-range cell): every level of every cell to 1e-6.  A source
+    whose W dt lies within a factor 3 of the negligible threshold may be
+    judged either way by the two sides' rate evaluations (the device compares
+    |E| with a per-level field threshold), so both decisions are accepted
+    there.  Returns (use, x, per-cell error, ambiguous-decision cells)."""
+    E64 = np.abs(E.astype(np.float64))
+    N64 = N.astype(np.float64)
+    _, p = mlp.window_shift(N64, lo, Z, eps)
+    inr = (E64 >= RNG.E_lo) & (E64 <= RNG.E_hi) & (p < Z)
+    idx = np.nonzero(inr)[0]
+    cols = np.zeros((w, 4, E.size))
+    cols[:, 0, :] = 1.0
+    for s_ in range(w):
+        k = np.minimum(p[idx] + s_, Z - 1)
+        Qt, Zt = traced(net, torch, E64[idx], np.full(idx.size, dt), k)
+        _, c = check_trace(params, Z, E64[idx], np.full(idx.size, dt), k, Qt, Zt)
+        cols[s_][:, idx] = c
+    ref, rlo, use, x = mlp.surrogate_step(orc, spec, Z, params.astype(np.float64), RNG, E.astype(np.float64), dt,
+                                          N64, lo, w, eps, cols_given=cols)
+    assert np.array_equal(glo, rlo)
+    d = np.abs(got - ref).max(axis=0)
+    th = mlp.NEGLIGIBLE_XDT
+    amb = (x > th / 3) & (x < 3 * th)
+    for c in np.nonzero((d > 1e-6) & amb.any(axis=0))[0]:
+        # the other decisions for the ambiguous sources of this cell
+        slots = np.nonzero(amb[:, c])[0]
+        best = d[c]
+        for mask in range(1, 1 << slots.size):
+            negl = (x[:, c:c + 1] < th).copy()
+            for b_, s_ in enumerate(slots):
+                if mask >> b_ & 1:
+                    negl[s_, 0] = not negl[s_, 0]
+            alt, _, _, _ = mlp.surrogate_step(orc, spec, Z, params.astype(np.float64), RNG,
+                                              E[c:c + 1].astype(np.float64), dt, N64[:, c:c + 1], lo[c:c + 1], w, eps,
+                                              cols_given=cols[:, :, c:c + 1], negligible=negl)
+            best = min(best, float(np.abs(got[:, c] - alt[:, 0]).max()))
+        d[c] = best
+    return use, x, d, int(amb.any(axis=0).sum())
+
+
 @pytest.mark.parametrize("w", [1, 2, 3])
 def test_surrogate_step_matches_reference(env, orc, w):
     torch, ak, gases = env
@@ -205,22 +308,10 @@ def test_surrogate_step_matches_reference(env, orc, w):
     cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
     ak.surrogate_step(gas, net, torch.from_numpy(E).cuda(), DT, Pt, Lt, w=w, eps=eps, counters=cnt)
     got, glo = Pt.cpu().numpy().astype(np.float64), Lt.cpu().numpy()
-    ref, rlo, use, x = mlp.surrogate_step(orc, spec, Z, params.astype(np.float64), RNG, E.astype(np.float64), DT,
-                                          N.astype(np.float64), lo, w, eps)
-    assert np.array_equal(glo, rlo)
-    ana = ~use
-    assert np.max(np.abs(got[:, ana] - ref[:, ana])) <= 1e-6
-    # a source whose W dt lies within a factor 3 of the negligible threshold
-    # may be judged either way by the two sides' rate evaluations
-    th = mlp.NEGLIGIBLE_XDT
-    clear = ~np.any((x > th / 3) & (x < 3 * th), axis=0)
-    sel = use & clear
-    assert sel.sum() > 0.9 * use.sum()
-    d = np.abs(got[:, sel] - ref[:, sel]).max(axis=0)
-    assert np.quantile(d, 0.9) <= 1e-5 and d.max() <= 1e-2, np.quantile(d, [0.5, 0.9, 0.99, 1.0])
-    # negligible sources keep their population exactly (identity columns)
-    negl = sel & np.all((x < th) | (np.arange(w)[:, None] >= np.minimum(w, Z - rlo.astype(int))[None, :]), axis=0)
-    assert np.max(np.abs(got[:, negl] - ref[:, negl]), initial=0.0) <= 1e-6
+    use, x, d, namb = surrogate_check(orc, spec, Z, params, net, torch, E, DT, N, lo, w, eps, got, glo)
+    print(f"w={w}: max |dN| {d.max():.2e} over {n} cells ({int(use.sum())} network cells, {namb} with a source "
+          f"at the negligible threshold)")
+    assert d.max() <= 1e-6
     # conservation and non-negativity of the network columns
     assert np.allclose(got[:, use].sum(axis=0), N[:, use].astype(np.float64).sum(axis=0), atol=3e-6)
     assert np.all(got[:, use] >= 0)
@@ -229,8 +320,10 @@ def test_surrogate_step_matches_reference(env, orc, w):
     E64 = E.astype(np.float64)
     fb = (~use) & (p_shift < Z) & (E64 > 5000.0)
     assert c[0] == fb.sum()
+    th = mlp.NEGLIGIBLE_XDT
     top = np.minimum(w, Z - p_shift)
     needed = (np.arange(w)[:, None] < top[None, :]) & (x >= th)
+    clear = ~np.any((x > th / 3) & (x < 3 * th), axis=0)
     assert abs(int(c[1]) - int(needed[:, use].sum())) <= int((~clear & use).sum()) * w
     net.close()
 
@@ -340,6 +433,46 @@ def test_trained_network_gain(env, orc):
     print({k: (float(v.mean()), float(np.quantile(v, 0.99)), float(v.max())) for k, v in err.items()})
     assert err["trained"].mean() <= 0.05 * err["init"].mean()
     assert err["trained"].mean() <= 0.2 * err["identity"].mean()
+    # one step on 65,536 cells of the 3D pulse (seeded window states, field of
+    # step 210): per-level error against the FP64 oracle of the surrogate form
+    # with the trained and the initial network, beside the mixed analytic step
+    # on the same cells (the method the network stands in for), and the time
+    # of each call
+    mesh = wl.mesh_3d()
+    rng = np.random.default_rng(7)
+    samp = np.sort(rng.choice(mesh.ncells, 65536, replace=False))
+    E = mesh.field_at(210, samp).astype(np.float32)
+    N, lo = wl.random_window_state(samp.size, Z, 3, seed=78, dtype=np.float32)
+    ref, rlo = orc.ionize_step(spec, E.astype(np.float64), mesh.dt, N.astype(np.float64), lo, 3, 1e-8)
+    Et = torch.from_numpy(E).cuda()
+    stream = torch.cuda.current_stream()
+    rows = {}
+    for name, fn in (("trained", lambda P, L: ak.surrogate_step(gas, net, Et, mesh.dt, P, L, w=3)),
+                     ("initial", lambda P, L: ak.surrogate_step(gas, init, Et, mesh.dt, P, L, w=3)),
+                     ("mixed analytic", lambda P, L: ak.ionize_step(gas, Et, mesh.dt, P, L, 3))):
+        P, L = torch.from_numpy(N).cuda(), torch.from_numpy(lo).cuda()
+        fn(P.clone(), L.clone())  # warm
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn(P, L)
+        b.record(stream)
+        torch.cuda.synchronize()
+        g, gl = P.cpu().numpy().astype(np.float64), L.cpu().numpy()
+        assert np.array_equal(gl, rlo)
+        lev = np.zeros(Z + 1)
+        for s_ in range(4):
+            kk = gl.astype(int) + s_
+            ok = kk <= Z
+            np.maximum.at(lev, kk[ok], np.abs(g[s_] - ref[s_])[ok])
+        rows[name] = (lev, a.elapsed_time(b) * 1e3)
+    for name, (lev, us) in rows.items():
+        print(f"{name}: {us:.1f} us per call on {samp.size} cells, max |dN| {lev.max():.2e}, per level "
+              + " ".join(f"{v:.1e}" for v in lev))
+    tr, ini, ana = rows["trained"][0], rows["initial"][0], rows["mixed analytic"][0]
+    assert ana.max() <= 1e-6
+    assert tr.max() < 0.25 * ini.max()
+    big = ini > 1e-3
+    assert np.all(tr[big] < ini[big])
     net.close()
     init.close()
 
@@ -348,8 +481,8 @@ def test_surrogate_full_size_sampled(env, orc):
     """The surrogate form at the 3D mesh's full size (33,554,432 cells, 36
     levels m averaged, w = 3) in the pulse (t = 210 dt), from a seeded window
     state, in the launch configuration the benchmark times; 65,536 sampled
-    cells against the CPU reference of the same network (tolerances as in the
-    small-mesh comparison above)."""
+    cells against the reference with the device network's validated columns,
+    every level to 1e-6 (as the small-mesh comparison above)."""
     torch, ak, gases = env
     Z, w, eps = 36, 3, 1e-8
     gas, spec = gases[Z]
@@ -367,18 +500,12 @@ def test_surrogate_full_size_sampled(env, orc):
     samp = np.sort(rng.choice(n, 65536, replace=False))
     idx = torch.from_numpy(samp).cuda()
     got, glo = Pt[:, idx].cpu().numpy().astype(np.float64), Lt[idx].cpu().numpy()
-    ref, rlo, use, x = mlp.surrogate_step(orc, spec, Z, params.astype(np.float64), RNG, E[samp].astype(np.float64),
-                                          mesh.dt, N[:, samp].astype(np.float64), lo[samp], w, eps)
-    assert np.array_equal(glo, rlo)
-    assert use.sum() > 10000  # the pulse puts many sampled cells in the network's range
-    ana = ~use
-    assert np.max(np.abs(got[:, ana] - ref[:, ana])) <= 1e-6
-    th = mlp.NEGLIGIBLE_XDT
-    clear = ~np.any((x > th / 3) & (x < 3 * th), axis=0)
-    sel = use & clear
-    d = np.abs(got[:, sel] - ref[:, sel]).max(axis=0)
-    assert np.quantile(d, 0.9) <= 1e-5 and d.max() <= 1e-2, np.quantile(d, [0.5, 0.9, 0.99, 1.0])
-    assert np.allclose(got[:, use].sum(axis=0), N[:, samp][:, use].astype(np.float64).sum(axis=0), atol=3e-6)
     del Pt, Lt, idx
+    use, x, d, namb = surrogate_check(orc, spec, Z, params, net, torch, E[samp], mesh.dt, N[:, samp], lo[samp], w,
+                                      eps, got, glo)
+    print(f"full size: max |dN| {d.max():.2e} over {samp.size} sampled cells ({int(use.sum())} network cells)")
+    assert use.sum() > 10000  # the pulse puts many sampled cells in the network's range
+    assert d.max() <= 1e-6
+    assert np.allclose(got[:, use].sum(axis=0), N[:, samp][:, use].astype(np.float64).sum(axis=0), atol=3e-6)
     net.close()
     torch.cuda.empty_cache()

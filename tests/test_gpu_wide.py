@@ -211,3 +211,48 @@ def test_full_chain_full_size_sampled(env, orc, prec, mesh_name):
     check(out, ref, prec, f"full chain {mesh_name} {prec}")
     del out_t, lo_t, idx
     torch.cuda.empty_cache()
+
+
+def clustered_rates(rng, w, n, hi):
+    """Rates per step of the wide path's hardest tables: w rates spread
+    uniformly over [0, hi] (no physical gas does this; the recurrence's
+    rounding grows with every order), in random chain order; a third of the
+    cells also carry six saturated rates (1e4 .. 1e12 per step) in place of
+    the last six, and a tenth carry ties and exact zeros."""
+    x = rng.uniform(0.0, hi, (w, n))
+    sat = rng.random(n) < 1 / 3
+    x[-6:, sat] = np.exp(rng.uniform(np.log(1e4), np.log(1e12), (6, int(sat.sum()))))
+    tie = rng.random(n) < 0.1
+    x[1, tie] = x[0, tie]
+    x[2, tie] = 0.0
+    for c in range(n):
+        x[:, c] = x[rng.permutation(w), c]
+    return x
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("w,hi", [(18, 20.0), (36, 20.0), (36, 10.0), (36, 60.0), (48, 20.0), (63, 20.0)])
+def test_clustered_tables_match_oracle(env, orc, prec, w, hi):
+    """adk_chain_advance with w > 8 (the wide path's solution with given
+    rates) on clustered tables against the oracle's binary128 exponential:
+    the tables whose divided differences lose accuracy in the recurrence are
+    recomputed by scaling and squaring, so every cell stays within the
+    per-call tolerance."""
+    torch, ak, _ = env
+    rng = np.random.default_rng(7000 + w + int(hi))
+    n = 192 if w >= 48 else 320
+    x = clustered_rates(rng, w, n, hi)
+    W = (x / DT).astype(npdt(prec))
+    pops = rng.random((w + 1, n))
+    pops /= pops.sum(axis=0)
+    pops = pops.astype(npdt(prec))
+    Wt = torch.from_numpy(W).cuda()
+    Pt = torch.from_numpy(pops).cuda()
+    print(f"clustered chain_advance: w={w} hi={hi} prec={prec} n={n}", flush=True)
+    ak.chain_advance(Wt, DT, Pt)
+    torch.cuda.synchronize()
+    out = Pt.cpu().numpy().astype(np.float64)
+    ref = orc.chain_advance(W.astype(np.float64), DT, pops.astype(np.float64))
+    err = check(out, ref, prec, f"clustered w={w} hi={hi} {prec}")
+    print(f"max |dN| {err:.2e}")
+    assert np.allclose(out.sum(axis=0), pops.astype(np.float64).sum(axis=0), atol=TOL[prec])
