@@ -457,6 +457,22 @@ int adk_mlp_forward_trace(const adk_mlp *mlp, const double *E, const double *dt,
 int adk_mlp_loss_grad(adk_mlp *mlp, const adk_gas *gas, const double *E, const double *dt, const int32_t *k,
                       int64_t n, float *grad, float *loss, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): adk_mlp_loss_grad without any allocation.  Same arguments and
+ * results as adk_mlp_loss_grad (the same kernels, the same summation order),
+ * for n <= ADK_MLP_NOALLOC_MAX_SAMPLES samples; the network is not modified.
+ * Its scratch (activations, partial gradients, sample features, about 8.4 MB)
+ * is one file-scope device array of the library that each GPU holds until
+ * the process ends; every buffer in it is written before it is read, and
+ * calls that overlap on one GPU share it and race (order them).  Calls no
+ * hipMalloc or hipFree; the first call on a device looks up that device's
+ * copy of the array.  Errors: as adk_mlp_loss_grad, ADK_ERANGE for n above
+ * the maximum, ADK_EDEVICE when the array cannot be located. */
+#define ADK_MLP_NOALLOC_MAX_SAMPLES 4096
+int adk_mlp_loss_grad_noalloc(const adk_mlp *mlp, const adk_gas *gas, const double *E, const double *dt,
+                              const int32_t *k, int64_t n, float *grad, float *loss, hipStream_t stream);
+
 /* Train on the analytic solver's columns: the training set is samples
  * 0..nsamples-1 of cfg->seed (sample i: E log-uniform in the field range, dt
  * log-uniform in the step range, k uniform in 0..Z-1, from three uniforms

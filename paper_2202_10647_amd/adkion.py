@@ -20,6 +20,7 @@ ADK_OK, ADK_EINVAL, ADK_ERANGE, ADK_EDEVICE, ADK_ENOMEM = 0, -1, -2, -3, -4
 ADK_F64, ADK_MIXED = 0, 1
 ADK_LAYOUT_COMPACT, ADK_LAYOUT_FULL = 0, 1
 ADK_MAX_Z, ADK_MAX_W, ADK_MAX_WIDE_W, ADK_M_AVERAGE = 64, 8, 63, -1
+ADK_MLP_NOALLOC_MAX_SAMPLES = 4096
 
 #: every function the header declares (checked by the CPU test suite)
 EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "adk_gas_destroy",
@@ -29,7 +30,7 @@ EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "a
            "adk_mlp_create", "adk_mlp_destroy", "adk_mlp_get_state", "adk_band_columns", "adk_mlp_forward",
            "adk_mlp_loss_grad", "adk_mlp_train", "adk_mlp_save", "adk_mlp_load", "adk_surrogate_step",
            "adk_ceiling_copy", "adk_ceiling_valu", "adk_adaptive_work_bytes", "ionize_step_adaptive",
-           "adk_mlp_forward_trace")
+           "adk_mlp_loss_grad_noalloc", "adk_mlp_forward_trace")
 ADK_PLAN_MAX_GAS, ADK_PLAN_MAX_W = 8, 6
 
 
@@ -162,6 +163,8 @@ def lib():
     _sig(L, "adk_mlp_loss_grad", "argtypes", [vp, vp, vp, vp, vp, i64, vp, vp, vp])
     _sig(L, "adk_mlp_forward_trace", "restype", ctypes.c_int)
     _sig(L, "adk_mlp_forward_trace", "argtypes", [vp, vp, vp, vp, i64, vp, vp, vp])
+    _sig(L, "adk_mlp_loss_grad_noalloc", "restype", ctypes.c_int)
+    _sig(L, "adk_mlp_loss_grad_noalloc", "argtypes", [vp, vp, vp, vp, vp, i64, vp, vp, vp])
     _sig(L, "adk_mlp_train", "restype", ctypes.c_int)
     _sig(L, "adk_mlp_train", "argtypes", [vp, vp, ctypes.POINTER(_TrainCfg), vp, vp])
     _sig(L, "adk_mlp_save", "restype", ctypes.c_int)
@@ -565,6 +568,18 @@ class Mlp:
                                          _dev(Zt, "Zt"), _stream(stream))
         _check(st, "adk_mlp_forward_trace")
         return Q, Zt
+
+    def loss_grad_noalloc(self, E, dt, k, grad, loss, stream=None):
+        """adk_mlp_loss_grad_noalloc: loss and gradient into the caller's
+        device tensors grad (float32[nparams]) and loss (float32[1]), with no
+        allocation in the library (n <= ADK_MLP_NOALLOC_MAX_SAMPLES)."""
+        import torch
+        if grad.dtype != torch.float32 or grad.numel() != self.nparams or loss.dtype != torch.float32:
+            raise ValueError("grad must be float32[nparams] and loss float32[1]")
+        st = lib().adk_mlp_loss_grad_noalloc(self._h, self._gas.handle, _dev(E, "E"), _dev(dt, "dt"), _dev(k, "k"),
+                                             E.numel(), _dev(grad, "grad"), _dev(loss, "loss"), _stream(stream))
+        _check(st, "adk_mlp_loss_grad_noalloc")
+        return loss, grad
 
     def train(self, iters: int, nsamples: int = 1_000_000, batch: int = 4096, lr: float = 3e-3,
               lr_min: float = 1e-5, total_iters: Optional[int] = None, seed: int = 1, stream=None) -> np.ndarray:

@@ -639,6 +639,46 @@ hipError_t grad_pass(const adk_mlp *m, const GradBufs &B, const float *U, const 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of adk_mlp_loss_grad_noalloc: one file-scope device array (each GPU
+// holds its own copy), laid out for ADK_MLP_NOALLOC_MAX_SAMPLES samples and a
+// gas of up to ADK_MAX_Z levels.  Every buffer in it is written in full
+// before it is read within a call, so nothing needs clearing; calls that
+// overlap on one GPU share it and race.
+constexpr int64_t kNaN = ADK_MLP_NOALLOC_MAX_SAMPLES;
+constexpr int64_t kNaPL = 2 * kH + 2 * (kH * kH + kH) + kBand * kH + kBand + (int64_t)ADK_MAX_Z * kH;  // PartLayout n
+constexpr int64_t kNaChunks = (kNaN + kCh - 1) / kCh;
+constexpr size_t na_round(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kNaH = na_round(sizeof(__bf16) * kNaN * kH);
+constexpr size_t kNaDZ4 = na_round(sizeof(float) * kNaN * kBand);
+constexpr size_t kNaLoss = na_round(sizeof(float) * kNaN);
+constexpr size_t kNaPart = na_round(sizeof(float) * kNaChunks * kNaPL);
+constexpr size_t kNaRed = na_round(sizeof(float) * kNaPL);
+constexpr size_t kNaX = na_round(sizeof(float) * kNaN);
+constexpr size_t kNaXP = na_round(sizeof(float) * kNaN * kBand);
+constexpr size_t kNaXK = na_round(sizeof(uint8_t) * kNaN);
+constexpr size_t kNaBytes = 3 * kNaH + kNaDZ4 + kNaLoss + kNaPart + kNaRed + 2 * kNaX + kNaXP + kNaXK;
+
+__device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+void *g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch` (looked up once per device,
+// with that device current); nullptr on failure.
+void *na_scratch(int dev)
+{
+    if (dev < 0 || dev >= kNaMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_na_ptr[dev] = ptr;
+    }
+    return g_na_ptr[dev];
+}
+
 constexpr char kMagic[8] = {'A', 'D', 'K', 'M', 'L', 'P', '0', '1'};
 
 struct FileHeader {
@@ -850,6 +890,35 @@ int adk_mlp_loss_grad(adk_mlp *m, const adk_gas *gas, const double *E, const dou
     if (e == hipSuccess)
         e = hipMemcpyAsync(grad, m->grad, sizeof(float) * (size_t)m->L.n, hipMemcpyDeviceToDevice, stream);
     return status_of(e);
+}
+
+int adk_mlp_loss_grad_noalloc(const adk_mlp *m, const adk_gas *gas, const double *E, const double *dt,
+                              const int32_t *k, int64_t n, float *grad, float *loss, hipStream_t stream)
+{
+    if (!m || !gas || !E || !dt || !k || !grad || !loss || n < 1) return ADK_EINVAL;
+    if (gas->Z != m->Z) return ADK_EINVAL;
+    if (n > ADK_MLP_NOALLOC_MAX_SAMPLES) return ADK_ERANGE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return ADK_EDEVICE;
+    unsigned char *base = (unsigned char *)na_scratch(dev);
+    if (!base) return ADK_EDEVICE;
+    GradBufs B{};
+    size_t o = 0;
+    B.H1 = (__bf16 *)(base + o); o += kNaH;
+    B.H2 = (__bf16 *)(base + o); o += kNaH;
+    B.H3 = (__bf16 *)(base + o); o += kNaH;
+    B.dZ4 = (float *)(base + o); o += kNaDZ4;
+    B.lossv = (float *)(base + o); o += kNaLoss;
+    B.part = (float *)(base + o); o += kNaPart;
+    B.red = (float *)(base + o); o += kNaRed;
+    float *xU = (float *)(base + o); o += kNaX;
+    float *xV = (float *)(base + o); o += kNaX;
+    float *xP = (float *)(base + o); o += kNaXP;
+    uint8_t *xK = (uint8_t *)(base + o); o += kNaXK;
+    B.grad = grad;  // the gradient goes straight to the caller's buffer
+    int st = launch_given(m, gas, E, dt, k, n, xU, xV, xK, xP, stream);
+    if (st) return st;
+    return status_of(grad_pass(m, B, xU, xV, xK, xP, 0, n, loss, stream));
 }
 
 int adk_mlp_train(adk_mlp *m, const adk_gas *gas, const adk_train_cfg *cfg, float *loss_out, hipStream_t stream)
