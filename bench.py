@@ -520,8 +520,11 @@ def adaptive_measure(ak, gas36, mesh, steps, eps, wmax=24, tol=1e-9, t0=200):
         wsum += float(Wc[live].double().sum())
         wlive += float(live.sum())
     torch.cuda.synchronize()
+    live = L < Z
+    hist = torch.bincount(Wc[live].to(torch.int64), minlength=wmax + 1).cpu().numpy()
     ms = total_ms / steps
     res = {"workload": f"laser3d_256x256x512_Z36mavg_adaptive_w1to{wmax}_mixed", "tolerance_per_step": tol,
+           "width_histogram_last_step": [int(v) for v in hist],
            "timed_steps": f"steps {t0}..{t0 + steps - 1} after {t0} steps of run-in (run-in {run_in_s:.1f} s eager)",
            "ms_per_step": ms, "value": units / (total_ms * 1e-3), "unit": "cell·level updates/s",
            "mean_width_live_cells": wsum / max(wlive, 1.0), "max_width": int(Wc.max()),
@@ -1018,12 +1021,15 @@ def surrogate_measure(ak, orc, gas36, spec36, w, eps, steps, train_iters, nsampl
     return res
 
 
-def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
+def batched_measure(ak, orc, steps, ncells, parity_cells=20000, layouts=("mesh", "grouped")):
     """Mixed gases with uneven windows (1-level host gas, 1 % dopants of 7, 18,
     36 and 54 levels, w in 1..6): one launch per launch group per step.  Each
     step's field is generated on the device by the hash harness; the timed
     graph holds [field, step] x steps and the field-only graph is timed
-    separately and subtracted."""
+    separately and subtracted.  Layout "mesh": arrays indexed by mesh cell
+    (the dopants scattered over the mesh); "grouped": the arrays in the plan's
+    order (each gas and width contiguous, as in species-major storage), the
+    same cells, the field drawn per storage position."""
     import torch
     from paper_2202_10647_amd import workloads as wl
     tables = [wl.synthetic_gas(z) for z in (1,) + wl.DOPANT_Z]
@@ -1031,11 +1037,14 @@ def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
     cell_gas, cell_w = wl.batched_cells(ncells, seed=4)
     dt = 1.334e-16
     res = {"workload": f"batched_{ncells}_cells_1pct_dopants_Z7_18_36_54_w1to6", "steps": steps}
-    for prec, tdt in (("mixed", torch.float32), ("f64", torch.float64)):
+    for prec, tdt, layout in [(p, t, lay) for p, t in (("mixed", torch.float32), ("f64", torch.float64))
+                              for lay in layouts]:
+        rk = prec if layout == "mesh" else f"{prec}_{layout}"
         t0 = time.perf_counter()
-        plan = ak.Plan(gases, cell_gas, cell_w, prec=prec, eps=1e-8, cells_per_lane=0)
+        plan = ak.Plan(gases, cell_gas, cell_w, prec=prec, eps=1e-8, cells_per_lane=0, layout=layout)
         create_s = time.perf_counter() - t0
         info = plan.info
+        order = plan.order() if layout == "grouped" else None
         rows = info["rows"]
         E = torch.empty(ncells, dtype=tdt, device="cuda")
         P = torch.zeros((rows, ncells), dtype=tdt, device="cuda")
@@ -1072,18 +1081,20 @@ def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
             torch.cuda.synchronize()
             times[name] = a.elapsed_time(b)
         step_ms = (times["all"] - times["field"]) / steps
-        top = np.minimum(L.cpu().numpy().astype(np.int64) + cell_w, np.array([t.Z for t in tables])[cell_gas])
+        sg, sw = (cell_gas, cell_w) if order is None else (cell_gas[order], cell_w[order])  # storage order
+        top = np.minimum(L.cpu().numpy().astype(np.int64) + sw, np.array([t.Z for t in tables])[sg])
         units_last = int((top - L.cpu().numpy().astype(np.int64) + 1).sum())
         es = 4 if prec == "mixed" else 8
         bytes_step = int(ncells * (es + 2 + 4) + 2 * es * int((cell_w.astype(np.int64) + 1).sum()))
-        res[prec] = dict(ms_per_step=step_ms, field_ms_per_step=times["field"] / steps,
-                         value=units_last / (step_ms * 1e-3), achieved_gbps=bytes_step / (step_ms * 1e-3) / 1e9,
-                         algorithmic_bytes_per_step=bytes_step, plan_create_s=create_s,
-                         cells_per_lane=info["cells_per_lane"], grid=info["grid"], tiles=info["ntiles"],
-                         buckets=info["nbuckets"], tuned_us=info["tuned_us"])
-        log(f"[batched] {prec}: {step_ms * 1e3:.1f} us/step (+{times['field'] / steps * 1e3:.1f} us field), "
-            f"{res[prec]['value']:.3e} cell-level/s (final windows), {res[prec]['achieved_gbps']:.0f} GB/s, "
-            f"cells/lane {info['cells_per_lane']}, {info['ntiles']} tiles, {info['nbuckets']} groups")
+        res[rk] = dict(layout=layout, ms_per_step=step_ms, field_ms_per_step=times["field"] / steps,
+                       value=units_last / (step_ms * 1e-3), achieved_gbps=bytes_step / (step_ms * 1e-3) / 1e9,
+                       algorithmic_bytes_per_step=bytes_step, plan_create_s=create_s,
+                       cells_per_lane=info["cells_per_lane"], grid=info["grid"], tiles=info["ntiles"],
+                       buckets=info["nbuckets"], tuned_us=info["tuned_us"], launch_cpl=info["launch_cpl"],
+                       launch_cells=info["launch_cells"])
+        log(f"[batched] {prec} ({layout} order): {step_ms * 1e3:.1f} us/step (+{times['field'] / steps * 1e3:.1f} us "
+            f"field), {res[rk]['value']:.3e} cell-level/s (final windows), {res[rk]['achieved_gbps']:.0f} GB/s, "
+            f"cells/lane {info['launch_cpl']}, {info['ntiles']} tiles, {info['nbuckets']} groups")
         # parity of one launch from a seeded synthetic state and host-generated
         # field (the same bits go to the oracle), on sampled cells
         rng = np.random.default_rng(5)
@@ -1094,12 +1105,21 @@ def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
         zs = [t.Z for t in tables]
         pops0, lo0 = wl.plan_window_state(cell_gas, cell_w, zs, rows, seed=31, dtype=npdt)
         E0 = wl.hash_field(ncells, 99, 7, dtype=npdt)
-        P.copy_(torch.from_numpy(pops0))
-        L.copy_(torch.from_numpy(lo0))
-        E.copy_(torch.from_numpy(E0))
+        if order is None:
+            P.copy_(torch.from_numpy(pops0))
+            L.copy_(torch.from_numpy(lo0))
+            E.copy_(torch.from_numpy(E0))
+            pos = samp
+        else:  # the same mesh cells stored in the plan's order
+            P.copy_(torch.from_numpy(np.ascontiguousarray(pops0[:, order])))
+            L.copy_(torch.from_numpy(np.ascontiguousarray(lo0[order])))
+            E.copy_(torch.from_numpy(np.ascontiguousarray(E0[order])))
+            inv = np.empty(ncells, np.int64)
+            inv[order] = np.arange(ncells)
+            pos = inv[samp]
         plan.step(E, dt, P, L)
         torch.cuda.synchronize()
-        idx = torch.from_numpy(samp).cuda()
+        idx = torch.from_numpy(pos).cuda()
         out, l2 = P[:, idx].cpu().numpy().astype(np.float64), L[idx].cpu().numpy()
         pre_p, pre_l, e_s = pops0[:, samp], lo0[samp], E0[samp]
         del pops0
@@ -1118,15 +1138,17 @@ def batched_measure(ak, orc, steps, ncells, parity_cells=20000):
                 mism += int(np.sum(l2[sel] != rlo))
                 lv = np.maximum(lv, per_level_error(out[: w + 1, sel], l2[sel], ref, rlo, t.Z))
             per_level[f"Z{t.Z}"] = [float(v) for v in lv]
-        res[prec]["parity_max_abs_err"] = err
-        res[prec]["parity_lo_mismatch"] = mism
-        res[prec]["per_level_max_abs_err"] = per_level
-        log(f"[batched] {prec} parity on {samp.size} sampled cells (seeded state, host field): "
+        res[rk]["parity_max_abs_err"] = err
+        res[rk]["parity_lo_mismatch"] = mism
+        res[rk]["per_level_max_abs_err"] = per_level
+        log(f"[batched] {prec} ({layout} order) parity on {samp.size} sampled cells (seeded state, host field): "
             f"max |dN| {err:.2e}, lo mismatches {mism}")
         del g_all, g_field, P, L, E
         plan.close()
         torch.cuda.empty_cache()
     res["speedup_mixed_vs_f64"] = res["f64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    if "mixed_grouped" in res:
+        res["speedup_grouped_vs_mesh_order_mixed"] = res["mixed"]["ms_per_step"] / res["mixed_grouped"]["ms_per_step"]
     for g in gases:
         g.close()
     return res

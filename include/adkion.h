@@ -193,7 +193,8 @@ int ionize_step_yield(const adk_gas *gas, const void *E, int64_t ncells, double 
  *      absorbing; wc = t.
  * With tol = 0 and wmax >= Z - lo the result is the full chain; with
  * wmin = wmax = w it is ionize_step with window w.  Cells whose window fits
- * three rates run one per lane, wider ones one per wavefront (double
+ * three rates run one per lane in a sweep of the mesh, those that fit eight
+ * one per lane over a list of them, wider ones one per wavefront (double
  * arithmetic), up to ADK_MAX_WIDE_W rates.
  */
 typedef struct {
@@ -205,7 +206,9 @@ typedef struct {
 } adk_adaptive;
 
 /* Bytes of the device workspace ionize_step_adaptive needs for ncells cells
- * (a list of the cells the wide tier solves, and its length): 256 + 4 ncells. */
+ * (a bit mask of the cells handed from the first to the second tier, a list
+ * of those handed to the third, and its length):
+ * 256 + 32 ceil(ncells / 256) + 4 ncells. */
 size_t adk_adaptive_work_bytes(int64_t ncells);
 
 /* One step with adaptive windows for ncells cells (compact layout):
@@ -218,11 +221,13 @@ size_t adk_adaptive_work_bytes(int64_t ncells);
  * the call uses as scratch (contents need no initialisation; calls sharing
  * one workspace must be ordered).  counters (device, 2 x uint64, may be
  * NULL) are incremented by: [0] cells solved one per wavefront (window wider
- * than three rates), [1] cells whose top the storage limit wmax held back
+ * than eight rates), [1] cells whose top the storage limit wmax held back
  * with leak above tol.  A cell below the gas's field cutoff (every rate
  * below 1e-30 per step) with no shift due keeps its populations when
- * tol >= 1e-30.  Three launches on stream (clear the list, lane-per-cell
- * tier, wavefront-per-cell tier); allocates nothing and never synchronises.
+ * tol >= 1e-30.  Four launches on stream (clear the list, lane-per-cell
+ * sweep, lane-per-cell tier over the cells it marked, wavefront-per-cell
+ * tier); allocates nothing and never synchronises.  Results do not depend
+ * on timing: repeated calls on the same inputs agree bit for bit.
  * Errors: ADK_EINVAL (null gas/win, null arrays or work with ncells > 0,
  * ncells < 0, work_bytes too small, dt <= 0 or non-finite, eps < 0 or
  * non-finite, tol < 0 or NaN, bad prec), ADK_ERANGE (wmin/wmax outside the
@@ -255,6 +260,17 @@ int adk_subcycle_step(const adk_gas *gas, const void *E, int64_t ncells, double 
  * compiled for that width; runs of smaller widths share one launch compiled
  * for the widest of them. */
 #define ADK_PLAN_SOLO_CELLS (1 << 19)
+/* Storage order of the arrays a plan steps (adk_plan_create's layout):
+ * ADK_PLAN_MESH_ORDER: E, pops and lo are indexed by mesh cell; each tile
+ *   gathers its cells through the plan's permutation (a sparse dopant's
+ *   cells lie scattered over many cache lines).
+ * ADK_PLAN_GROUPED: the arrays hold the cells in the plan's order
+ *   (adk_plan_order), each (gas, w) group contiguous, as a code that stores
+ *   each species' cells in arrays of its own does; every access of a tile
+ *   is then contiguous.  The caller keeps its populations in that order
+ *   and supplies the field in it. */
+#define ADK_PLAN_MESH_ORDER 0
+#define ADK_PLAN_GROUPED 1
 
 typedef struct adk_plan adk_plan; /* opaque: grouping of the cells, tiles, tuning */
 
@@ -274,6 +290,7 @@ typedef struct {
     int32_t launch_grid[ADK_PLAN_MAX_W];   /* workgroups (one per tile)             */
     int32_t launch_tiles[ADK_PLAN_MAX_W];  /* tiles                                 */
     int64_t launch_cells[ADK_PLAN_MAX_W];  /* cells                                 */
+    int32_t layout;                        /* ADK_PLAN_MESH_ORDER or ADK_PLAN_GROUPED */
 } adk_plan_info;
 
 /* Create a plan over ncells cells: cell c uses gases[cell_gas[c]] with window
@@ -285,13 +302,25 @@ typedef struct {
  * launch groups (ADK_PLAN_SOLO_CELLS).  cells_per_lane = 0 runs the
  * autotuner for each launch group (timed trials on scratch device buffers of
  * the plan's size; result cached in the file named by ADK_TUNE_CACHE when
- * set), 1, 2 or 4 fixes it for every launch.  Synchronous; allocates device
+ * set; a line of that file that does not parse is skipped), 1, 2 or 4
+ * fixes it for every launch.  layout: ADK_PLAN_MESH_ORDER or
+ * ADK_PLAN_GROUPED (the order of the arrays adk_plan_step is given; cell_gas
+ * and cell_w are always in mesh order).  Synchronous; allocates device
  * memory.  Errors: ADK_EINVAL (null pointers, bad prec, eps < 0 or
- * non-finite, cells_per_lane not in {0,1,2,4}), ADK_ERANGE (ngas outside
+ * non-finite, cells_per_lane not in {0,1,2,4}, unknown layout), ADK_ERANGE (ngas outside
  * [1, ADK_PLAN_MAX_GAS], a cell's gas index or width out of range,
  * ncells >= 2^31 - 256), ADK_EDEVICE/ADK_ENOMEM. */
 int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *cell_gas, const uint8_t *cell_w,
-                    int64_t ncells, adk_prec prec, double eps, int32_t cells_per_lane, adk_plan **out);
+                    int64_t ncells, adk_prec prec, double eps, int32_t cells_per_lane, int32_t layout,
+                    adk_plan **out);
+
+/* The plan's cell order: order[i] = the mesh cell (index into cell_gas /
+ * cell_w of adk_plan_create) at plan position i, for i < ncells; each
+ * (gas, w) group is one contiguous run, mesh order kept within it.  With
+ * ADK_PLAN_GROUPED, element i of E, lo and every pops row belongs to mesh
+ * cell order[i].  order: host array of ncells int32, written.  Errors:
+ * ADK_EINVAL (null plan, null order with ncells > 0). */
+int adk_plan_order(const adk_plan *plan, int32_t *order);
 
 /* One ionization step of every cell of the plan (same semantics per cell as
  * ionize_step with the cell's gas and width): one launch per launch group

@@ -26,7 +26,7 @@ ADK_MLP_NOALLOC_MAX_SAMPLES = 4096
 EXPORTS = ("adk_version", "adk_strerror", "adk_gas_coeffs", "adk_gas_create", "adk_gas_destroy",
            "adk_gas_levels", "adk_rates", "adk_chain_advance", "ionize_step", "ionize_step_yield",
            "adk_subcycle_step", "adk_plan_create",
-           "adk_plan_step", "adk_plan_graph_replay", "adk_plan_get_info", "adk_plan_destroy", "adk_field_hash", "adk_mlp_nparams",
+           "adk_plan_step", "adk_plan_graph_replay", "adk_plan_get_info", "adk_plan_order", "adk_plan_destroy", "adk_field_hash", "adk_mlp_nparams",
            "adk_mlp_create", "adk_mlp_destroy", "adk_mlp_get_state", "adk_band_columns", "adk_mlp_forward",
            "adk_mlp_loss_grad", "adk_mlp_train", "adk_mlp_save", "adk_mlp_load", "adk_surrogate_step",
            "adk_ceiling_copy", "adk_ceiling_valu", "adk_adaptive_work_bytes", "ionize_step_adaptive",
@@ -50,6 +50,7 @@ class _GasDesc(ctypes.Structure):
 
 
 PLAN_MAX_W = 6
+ADK_PLAN_MESH_ORDER, ADK_PLAN_GROUPED = 0, 1
 
 
 class _PlanInfo(ctypes.Structure):
@@ -58,7 +59,7 @@ class _PlanInfo(ctypes.Structure):
                 ("from_cache", ctypes.c_int32), ("tuned_us", ctypes.c_double), ("nlaunches", ctypes.c_int32),
                 ("launch_wmax", ctypes.c_int32 * PLAN_MAX_W), ("launch_cpl", ctypes.c_int32 * PLAN_MAX_W),
                 ("launch_grid", ctypes.c_int32 * PLAN_MAX_W), ("launch_tiles", ctypes.c_int32 * PLAN_MAX_W),
-                ("launch_cells", ctypes.c_int64 * PLAN_MAX_W)]
+                ("launch_cells", ctypes.c_int64 * PLAN_MAX_W), ("layout", ctypes.c_int32)]
 
 
 class _MlpRange(ctypes.Structure):
@@ -131,8 +132,10 @@ def lib():
     _sig(L, "ionize_step_yield", "restype", ctypes.c_int)
     _sig(L, "ionize_step_yield", "argtypes", [vp, vp, i64, dbl, vp, vp, ctypes.POINTER(_Window), vp, vp])
     _sig(L, "adk_plan_create", "restype", ctypes.c_int)
-    _sig(L, "adk_plan_create", "argtypes", [ctypes.POINTER(vp), i32, vp, vp, i64, ctypes.c_int, dbl, i32,
+    _sig(L, "adk_plan_create", "argtypes", [ctypes.POINTER(vp), i32, vp, vp, i64, ctypes.c_int, dbl, i32, i32,
                                             ctypes.POINTER(vp)])
+    _sig(L, "adk_plan_order", "restype", ctypes.c_int)
+    _sig(L, "adk_plan_order", "argtypes", [vp, vp])
     _sig(L, "adk_plan_step", "restype", ctypes.c_int)
     _sig(L, "adk_plan_step", "argtypes", [vp, vp, dbl, vp, vp, vp])
     _sig(L, "adk_plan_graph_replay", "restype", ctypes.c_int)
@@ -385,10 +388,12 @@ class Plan:
     """Batched step over cells of several gases (see adk_plan_create).
 
     gases: list of Gas; cell_gas, cell_w: per-cell gas index and window width
-    (host arrays); prec: "mixed" (float) or "f64"; cells_per_lane: 0 = autotune.
-    Populations use pops[info.rows][ncells] (compact slots per cell)."""
+    (host arrays, mesh order); prec: "mixed" (float) or "f64"; cells_per_lane:
+    0 = autotune; layout: "mesh" (arrays indexed by mesh cell) or "grouped"
+    (arrays in the plan's order, see order()).  Populations use
+    pops[info.rows][ncells] (compact slots per cell)."""
 
-    def __init__(self, gases, cell_gas, cell_w, prec="mixed", eps=1e-8, cells_per_lane=0):
+    def __init__(self, gases, cell_gas, cell_w, prec="mixed", eps=1e-8, cells_per_lane=0, layout="mesh"):
         cg = np.ascontiguousarray(np.asarray(cell_gas, dtype=np.uint8))
         cw = np.ascontiguousarray(np.asarray(cell_w, dtype=np.uint8))
         if cg.shape != cw.shape or cg.ndim != 1:
@@ -398,7 +403,9 @@ class Plan:
         self._prec = {"mixed": ADK_MIXED, "f64": ADK_F64}[prec]
         st = lib().adk_plan_create(arr, len(gases), cg.ctypes.data_as(ctypes.c_void_p),
                                    cw.ctypes.data_as(ctypes.c_void_p), int(cg.size), self._prec, float(eps),
-                                   int(cells_per_lane), ctypes.byref(h))
+                                   int(cells_per_lane),
+                                   {"mesh": ADK_PLAN_MESH_ORDER, "grouped": ADK_PLAN_GROUPED}[layout],
+                                   ctypes.byref(h))
         _check(st, "adk_plan_create")
         self._h = h
         self._gases = list(gases)  # keep the gas tables alive
@@ -412,6 +419,12 @@ class Plan:
         for k, _ in _PlanInfo._fields_:
             v = getattr(inf, k)
             out[k] = list(v)[: inf.nlaunches] if k.startswith("launch_") else v
+        return out
+
+    def order(self):
+        """adk_plan_order: int32[ncells], the mesh cell at each plan position."""
+        out = np.empty(self.ncells, dtype=np.int32)
+        _check(lib().adk_plan_order(self._h, out.ctypes.data_as(ctypes.c_void_p)), "adk_plan_order")
         return out
 
     def step(self, E, dt: float, pops, lo, stream=None):

@@ -24,13 +24,16 @@ PLAN_WMAX = range(1, 7)
 
 
 def _jobs(objdir):
-    """(command, object) pairs: host table builder, ABI, batched plan,
+    """(command, object) pairs: host table builder, tuner cache file, ABI, batched plan,
     surrogate network and step, one kernel instantiation per (precision,
     window width)."""
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     jobs = []
     obj = os.path.join(objdir, "gas_table.o")
     jobs.append((["hipcc", "-O2", "-std=c++17", "-fPIC", *inc, "-c", os.path.join(CSRC, "gas_table.cpp"),
+                  "-o", obj], obj))
+    obj = os.path.join(objdir, "tune_cache.o")
+    jobs.append((["hipcc", "-O2", "-std=c++17", "-fPIC", *inc, "-c", os.path.join(CSRC, "tune_cache.cpp"),
                   "-o", obj], obj))
     obj = os.path.join(objdir, "abi.o")
     jobs.append((["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, "abi.hip"), "-o", obj], obj))

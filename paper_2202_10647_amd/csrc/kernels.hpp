@@ -709,7 +709,7 @@ __device__ __forceinline__ void plan_tile(const PlanTile &tile, const PlanGasArg
     CellLoad<R, W> nxt;
     int64_t cn = 0;
     if (idx < end) {
-        cn = perm[idx];
+        cn = perm ? perm[idx] : idx;  // no permutation: the plan's own cell order
         load_cell(nxt, E, pops, lo, n, cn);
     }
     stage_coefficients(sc, g.tab, ln_dt);
@@ -720,7 +720,7 @@ __device__ __forceinline__ void plan_tile(const PlanTile &tile, const PlanGasArg
             const int64_t c = cn;
             if constexpr (k + 1 < CPL) {
                 if (idx + kBlock < end) {
-                    cn = perm[idx + kBlock];
+                    cn = perm ? perm[idx + kBlock] : idx + kBlock;
                     load_cell(nxt, E, pops, lo, n, cn);
                 }
             }

@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "tune_cache.hpp"
 
 namespace adk {
 
@@ -64,7 +65,9 @@ struct adk_plan {
     int ngroups = 0;
     adk::PlanGroup group[adk::kPlanMaxW];
     int main_group = 0;  // the launch group with the most cells (caller's stream)
-    int32_t *d_perm = nullptr;
+    int layout = ADK_PLAN_MESH_ORDER;
+    std::vector<int32_t> order;  // plan position -> mesh cell (host copy)
+    int32_t *d_perm = nullptr;   // the same on the device (mesh order only)
     adk::PlanTile *d_tiles = nullptr;
     hipStream_t side = nullptr;  // the other launch groups (ngroups > 1)
     hipEvent_t fork = nullptr, join = nullptr;
@@ -235,35 +238,11 @@ static std::string tune_key(const adk_plan *p, const std::vector<Bucket> &b, con
         h = splitmix64(h ^ (uint64_t)p->gas[k.gas]->Z);
     }
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s|n=%lld|prec=%d|wmax=%d|b=%016llx", arch.c_str(), (long long)p->ncells,
-                  (int)p->prec, grp.wmax, (unsigned long long)h);
+    std::snprintf(buf, sizeof(buf), "%s|n=%lld|prec=%d|wmax=%d|layout=%d|b=%016llx", arch.c_str(),
+                  (long long)p->ncells, (int)p->prec, grp.wmax, p->layout, (unsigned long long)h);
     for (char *c = buf; *c; ++c)
         if (*c == ' ') *c = '_';
     return buf;
-}
-
-static int cache_lookup(const std::string &key)
-{
-    const char *path = std::getenv("ADK_TUNE_CACHE");
-    if (!path) return 0;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return 0;
-    char k[512];
-    int v = 0, found = 0;
-    while (std::fscanf(f, "%511s %d", k, &v) == 2)
-        if (key == k && (v == 1 || v == 2 || v == 4)) found = v;  // last entry wins
-    std::fclose(f);
-    return found;
-}
-
-static void cache_store(const std::string &key, int cpl)
-{
-    const char *path = std::getenv("ADK_TUNE_CACHE");
-    if (!path) return;
-    FILE *f = std::fopen(path, "a");
-    if (!f) return;
-    std::fprintf(f, "%s %d\n", key.c_str(), cpl);
-    std::fclose(f);
 }
 
 // Timed trials of cells_per_lane in {1, 2, 4} for every launch group whose
@@ -347,7 +326,8 @@ using namespace adk;
 extern "C" {
 
 int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *cell_gas, const uint8_t *cell_w,
-                    int64_t ncells, adk_prec prec, double eps, int32_t cells_per_lane, adk_plan **out)
+                    int64_t ncells, adk_prec prec, double eps, int32_t cells_per_lane, int32_t layout,
+                    adk_plan **out)
 {
     if (!out) return ADK_EINVAL;
     *out = nullptr;
@@ -357,6 +337,7 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
     if (prec != ADK_F64 && prec != ADK_MIXED) return ADK_EINVAL;
     if (!(eps >= 0.0) || !std::isfinite(eps)) return ADK_EINVAL;
     if (cells_per_lane != 0 && cells_per_lane != 1 && cells_per_lane != 2 && cells_per_lane != 4) return ADK_EINVAL;
+    if (layout != ADK_PLAN_MESH_ORDER && layout != ADK_PLAN_GROUPED) return ADK_EINVAL;
     for (int g = 0; g < ngas; ++g)
         if (!gases[g]) return ADK_EINVAL;
     int wmax = 0;
@@ -395,7 +376,14 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
         run += k.count;
     }
     p->nbuckets = (int)b.size();
-    std::vector<int32_t> perm((size_t)ncells);
+    p->layout = layout;
+    try {
+        p->order.resize((size_t)ncells);
+    } catch (...) {
+        delete p;
+        return ADK_ENOMEM;
+    }
+    std::vector<int32_t> &perm = p->order;
     for (int64_t c = 0; c < ncells; ++c) {
         int64_t &o = offset[(size_t)cell_gas[c] * (kPlanMaxW + 1) + cell_w[c]];
         perm[(size_t)o++] = (int32_t)c;
@@ -403,7 +391,7 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
     std::vector<PlanGroup> groups = make_groups(b);
     int st = ADK_OK;
     hipError_t e = hipSuccess;
-    if (ncells > 0) {
+    if (ncells > 0 && layout == ADK_PLAN_MESH_ORDER) {  // grouped: cell c of the arrays is plan position c
         e = hipMalloc((void **)&p->d_perm, sizeof(int32_t) * (size_t)ncells);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_perm, perm.data(), sizeof(int32_t) * (size_t)ncells, hipMemcpyHostToDevice);
@@ -414,7 +402,7 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
         for (PlanGroup &grp : groups) {
             grp.cpl = cells_per_lane;
             if (grp.cpl == 0) {
-                grp.cpl = cache_lookup(tune_key(p, b, grp));
+                grp.cpl = tune_cache_lookup(std::getenv("ADK_TUNE_CACHE"), tune_key(p, b, grp));
                 grp.from_cache = grp.cpl != 0;
                 tune = tune || grp.cpl == 0;
             }
@@ -423,7 +411,7 @@ int adk_plan_create(const adk_gas *const *gases, int32_t ngas, const uint8_t *ce
             st = autotune(p, b, groups);
             if (st == ADK_OK)
                 for (const PlanGroup &grp : groups)
-                    if (!grp.from_cache) cache_store(tune_key(p, b, grp), grp.cpl);
+                    if (!grp.from_cache) tune_cache_store(std::getenv("ADK_TUNE_CACHE"), tune_key(p, b, grp), grp.cpl);
         }
     }
     std::vector<PlanTile> t;
@@ -587,6 +575,14 @@ int adk_plan_get_info(const adk_plan *plan, adk_plan_info *info)
     info->cells_per_lane = big >= 0 ? plan->group[big].cpl : 1;
     info->grid = big >= 0 ? plan->group[big].grid : 0;
     info->from_cache = tuned > 0 && cached == tuned;
+    info->layout = plan->layout;
+    return ADK_OK;
+}
+
+int adk_plan_order(const adk_plan *plan, int32_t *order)
+{
+    if (!plan || (!order && plan->ncells > 0)) return ADK_EINVAL;
+    if (plan->ncells > 0) std::memcpy(order, plan->order.data(), sizeof(int32_t) * (size_t)plan->ncells);
     return ADK_OK;
 }
 

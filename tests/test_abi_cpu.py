@@ -150,18 +150,21 @@ def test_plan_validation_before_device(L):
     cw = np.ones(4, np.uint8)
     f = L.adk_plan_create
     c = lambda a: a.ctypes.data_as(vp)
-    assert f(one, 1, c(cg), c(cw), 4, 0, 1e-8, 0, None) == adkion.ADK_EINVAL
-    assert f(None, 1, c(cg), c(cw), 4, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
-    assert f(one, 0, c(cg), c(cw), 4, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
-    assert f(one, 9, c(cg), c(cw), 4, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_ERANGE
-    assert f(one, 1, c(cg), c(cw), -1, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_ERANGE
-    assert f(one, 1, None, c(cw), 4, 0, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
-    assert f(one, 1, c(cg), c(cw), 4, 5, 1e-8, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
-    assert f(one, 1, c(cg), c(cw), 4, 0, -1.0, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
-    assert f(one, 1, c(cg), c(cw), 4, 0, 1e-8, 3, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 0, 1e-8, 0, 0, None) == adkion.ADK_EINVAL
+    assert f(None, 1, c(cg), c(cw), 4, 0, 1e-8, 0, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 0, c(cg), c(cw), 4, 0, 1e-8, 0, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 9, c(cg), c(cw), 4, 0, 1e-8, 0, 0, ctypes.byref(out)) == adkion.ADK_ERANGE
+    assert f(one, 1, c(cg), c(cw), -1, 0, 1e-8, 0, 0, ctypes.byref(out)) == adkion.ADK_ERANGE
+    assert f(one, 1, None, c(cw), 4, 0, 1e-8, 0, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 5, 1e-8, 0, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 0, -1.0, 0, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 0, 1e-8, 3, 0, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 0, 1e-8, 0, 2, ctypes.byref(out)) == adkion.ADK_EINVAL
+    assert f(one, 1, c(cg), c(cw), 4, 0, 1e-8, 0, -1, ctypes.byref(out)) == adkion.ADK_EINVAL
     assert out.value is None
     info = adkion._PlanInfo()
     assert L.adk_plan_get_info(None, ctypes.byref(info)) == adkion.ADK_EINVAL
+    assert L.adk_plan_order(None, vp(16)) == adkion.ADK_EINVAL
     assert L.adk_plan_step(None, vp(16), 1e-16, vp(16), vp(16), None) == adkion.ADK_EINVAL
     assert L.adk_plan_destroy(None) == adkion.ADK_OK
     fh = L.adk_field_hash
@@ -244,7 +247,8 @@ def test_adaptive_host_validation(L):
     """Workspace size and the host-side rejections of ionize_step_adaptive
     that need no gas on a device."""
     assert L.adk_adaptive_work_bytes(0) == 256
-    assert L.adk_adaptive_work_bytes(1000) == 256 + 4000
+    assert L.adk_adaptive_work_bytes(1000) == 256 + 32 * 4 + 4000
+    assert L.adk_adaptive_work_bytes(1024) == 256 + 32 * 4 + 4096
     win = adkion._Adaptive(1, 8, 1e-8, 1e-9, adkion.ADK_MIXED)
     E = adkion.ADK_EINVAL
     assert L.ionize_step_adaptive(None, None, 4, 1e-16, None, None, None, ctypes.byref(win), None, 0, None,

@@ -285,3 +285,96 @@ def test_plan_full_size_sampled(env, orc, prec):
     del Pt, Lt, idx
     plan.close()
     torch.cuda.empty_cache()
+
+
+def test_tune_cache_file(env, orc, tmp_path, monkeypatch):
+    """ADK_TUNE_CACHE: a first plan is tuned and stores one entry per launch
+    group; the same plan again takes every choice from the file (from_cache
+    = 1, same cells per lane); a corrupt file is tuned again and appended to;
+    valid entries after corrupt lines are still used, and a choice written
+    into the file is the one the plan runs with (checked against the oracle)."""
+    torch, ak, gases, specs = env
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("ADK_TUNE_CACHE", str(path))
+    n = 40000 + 123
+    cell_gas, cell_w = wl.batched_cells(n, seed=9, dopant_fraction=0.3)
+    p1 = ak.Plan(gases, cell_gas, cell_w, prec="mixed", eps=1e-8, cells_per_lane=0)
+    i1 = p1.info
+    p1.close()
+    nl = i1["nlaunches"]
+    assert i1["from_cache"] == 0 and i1["tuned_us"] > 0.0
+    lines = path.read_text().splitlines()
+    assert len(lines) == nl
+    assert sorted(int(l.split()[1]) for l in lines) == sorted(i1["launch_cpl"])
+    p2 = ak.Plan(gases, cell_gas, cell_w, prec="mixed", eps=1e-8, cells_per_lane=0)
+    i2 = p2.info
+    p2.close()
+    assert i2["from_cache"] == 1 and i2["launch_cpl"] == i1["launch_cpl"]
+    assert len(path.read_text().splitlines()) == nl  # nothing appended on a hit
+    # corrupt file: tuned again, entries appended
+    path.write_text("not a cache file\n\x00garbage 7\n")
+    p3 = ak.Plan(gases, cell_gas, cell_w, prec="mixed", eps=1e-8, cells_per_lane=0)
+    i3 = p3.info
+    p3.close()
+    assert i3["from_cache"] == 0
+    assert len(path.read_text().splitlines()) == 2 + nl
+    # valid entries after corrupt lines, each set to a choice of our own
+    keys = [l.split()[0] for l in lines]
+    forced = [4 if int(l.split()[1]) != 4 else 1 for l in lines]
+    path.write_text("junk line\n" + "".join(f"{k} {c}\n" for k, c in zip(keys, forced)) + keys[0][:10])
+    p4 = ak.Plan(gases, cell_gas, cell_w, prec="mixed", eps=1e-8, cells_per_lane=0)
+    i4 = p4.info
+    assert i4["from_cache"] == 1
+    assert sorted(i4["launch_cpl"]) == sorted(forced)
+    pops, lo = plan_state(cell_gas, cell_w, i4["rows"], seed=321)
+    pops = pops.astype(np.float32)
+    E = wl.hash_field(n, seed=23, step=2, dtype=np.float32)
+    Pt = torch.from_numpy(pops).cuda()
+    Lt = torch.from_numpy(lo).cuda()
+    p4.step(torch.from_numpy(E).cuda(), DT, Pt, Lt)
+    torch.cuda.synchronize()
+    ref, rlo = oracle_plan(orc, specs, cell_gas, cell_w, E.astype(np.float64), pops.astype(np.float64), lo, 1e-8)
+    assert np.array_equal(Lt.cpu().numpy(), rlo)
+    assert np.max(np.abs(Pt.cpu().numpy().astype(np.float64) - ref)) <= TOL["mixed"]
+    p4.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "f64"])
+def test_plan_grouped_layout(env, orc, prec):
+    """ADK_PLAN_GROUPED: the arrays hold the cells in the plan's order (each
+    (gas, w) group contiguous).  The order is a permutation whose groups are
+    contiguous runs in mesh order within each; a grouped step equals the
+    mesh-order step of the same cells bit for bit, and the oracle."""
+    torch, ak, gases, specs = env
+    n = 60000 + 77
+    cell_gas, cell_w = wl.batched_cells(n, seed=12, dopant_fraction=0.2)
+    pm = ak.Plan(gases, cell_gas, cell_w, prec=prec, eps=1e-8, cells_per_lane=2)
+    pg = ak.Plan(gases, cell_gas, cell_w, prec=prec, eps=1e-8, cells_per_lane=2, layout="grouped")
+    assert pg.info["layout"] == ak.ADK_PLAN_GROUPED and pm.info["layout"] == ak.ADK_PLAN_MESH_ORDER
+    order = pg.order()
+    assert np.array_equal(order, pm.order())
+    assert np.array_equal(np.sort(order), np.arange(n))
+    key = cell_gas[order].astype(np.int64) * 8 + cell_w[order]
+    runs = np.count_nonzero(np.diff(key)) + 1
+    assert runs == np.unique(key).size  # one contiguous run per (gas, w)
+    same = np.diff(key) == 0
+    assert np.all(np.diff(order)[same] > 0)  # mesh order kept within a group
+    npdt = np.float32 if prec == "mixed" else np.float64
+    rows = pg.info["rows"]
+    pops, lo = plan_state(cell_gas, cell_w, rows, seed=55)
+    pops = pops.astype(npdt)
+    E = wl.hash_field(n, seed=29, step=4, dtype=npdt)
+    E[::37] = 0.0
+    Pm, Lm = torch.from_numpy(pops).cuda(), torch.from_numpy(lo).cuda()
+    pm.step(torch.from_numpy(E).cuda(), DT, Pm, Lm)
+    Pg = torch.from_numpy(np.ascontiguousarray(pops[:, order])).cuda()
+    Lg = torch.from_numpy(np.ascontiguousarray(lo[order])).cuda()
+    pg.step(torch.from_numpy(np.ascontiguousarray(E[order])).cuda(), DT, Pg, Lg)
+    torch.cuda.synchronize()
+    outm, outg = Pm.cpu().numpy(), Pg.cpu().numpy()
+    assert np.array_equal(outg, outm[:, order]) and np.array_equal(Lg.cpu().numpy(), Lm.cpu().numpy()[order])
+    ref, rlo = oracle_plan(orc, specs, cell_gas, cell_w, E.astype(np.float64), pops.astype(np.float64), lo, 1e-8)
+    assert np.array_equal(Lm.cpu().numpy(), rlo)
+    assert np.max(np.abs(outm.astype(np.float64) - ref)) <= TOL[prec]
+    pm.close()
+    pg.close()
