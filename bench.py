@@ -530,10 +530,11 @@ def adaptive_measure(ak, gas36, mesh, steps, eps, wmax=24, tol=1e-9, t0=200):
            "mean_width_live_cells": wsum / max(wlive, 1.0), "max_width": int(Wc.max()),
            "wide_tier_cells_per_step": wide_cells / steps, "held_by_wmax_timed_steps": held,
            "held_by_wmax_run_in": held_run_in,
-           "launches_per_step": 3}
-    log(f"[adaptive] mixed, widths 1..{wmax}: {ms * 1e3:.1f} us/step, {res['value']:.3e} cell-level/s, mean width "
-        f"{res['mean_width_live_cells']:.2f} (max {res['max_width']}), {wide_cells / steps:.0f} cells/step on the "
-        f"wavefront tier, held by wmax: {held} (timed) {held_run_in} (run-in)")
+           "launches_per_step": 4}
+    log(f"[adaptive] mixed, widths 1..{wmax}, tol {tol:g}: {ms * 1e3:.1f} us/step, {res['value']:.3e} cell-level/s, "
+        f"mean width {res['mean_width_live_cells']:.2f} (max {res['max_width']}), {wide_cells / steps:.0f} "
+        f"cells/step on the wavefront tier, held by wmax: {held} (timed) {held_run_in} (run-in); widths "
+        f"{res['width_histogram_last_step']}")
     del fields, P, L, Wc, P0, L0, W0, work
     torch.cuda.empty_cache()
     return res
@@ -760,11 +761,11 @@ def window_study(ak, mesh, eps, widths=(2, 3, 4, 8), every=10):
     return res
 
 
-def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width=32, tol=1e-9):
+def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width=32, tols=(1e-9, 1e-6)):
     """Full-vs-reduced study on the 3D mesh (256 x 256 x 512 cells, 36 levels,
     m averaged): FP64 windows of w = 2, 3, 4 rates and the adaptive window
-    (ionize_step_adaptive: width 1..36 per cell and step, leak tolerance
-    `tol` per step) against the full 36-level chain (w = Z on the wide path,
+    (ionize_step_adaptive: width 1..36 per cell and step, leak tolerances
+    `tols` per step) against the full 36-level chain (w = Z on the wide path,
     no shift), `steps` steps of the pulse from t = 0, on the central
     transverse box of (2 half_width)^2 x 512 cells (the strongest fields:
     |x|, |y| < 10 um around the axis).  Every `every` steps: max |dN_k| per
@@ -788,18 +789,18 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
         P = torch.zeros((w + 1, n), dtype=torch.float64, device="cuda")
         P[0] = 1.0
         st[w] = (P, torch.zeros(n, dtype=torch.uint8, device="cuda"))
-    # adaptive windows: storage for every level, widths start at 1
-    Pa = torch.zeros((Z + 1, n), dtype=torch.float64, device="cuda")
-    Pa[0] = 1.0
-    La = torch.zeros(n, dtype=torch.uint8, device="cuda")
-    Wa = torch.ones(n, dtype=torch.uint8, device="cuda")
+    # adaptive windows, one run per tolerance: storage for every level,
+    # widths start at 1
     work = ak.adaptive_workspace(n)
-    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
-    ada_s = 0.0
-    width_sum = width_cells = 0.0
-    width_max = 0
-    dmax_a = torch.zeros(n, dtype=torch.float64, device="cuda")
-    nemax_a = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ada = {}
+    for tol in tols:
+        Pa = torch.zeros((Z + 1, n), dtype=torch.float64, device="cuda")
+        Pa[0] = 1.0
+        ada[tol] = dict(P=Pa, L=torch.zeros(n, dtype=torch.uint8, device="cuda"),
+                        W=torch.ones(n, dtype=torch.uint8, device="cuda"),
+                        cnt=torch.zeros(2, dtype=torch.int64, device="cuda"), s=0.0, wsum=0.0, wcells=0.0, wmax=0,
+                        dmax=torch.zeros(n, dtype=torch.float64, device="cuda"),
+                        nemax=torch.zeros(n, dtype=torch.float64, device="cuda"))
     # cells whose field over the first laser period already exceeds 1 GV/m
     # start ionizing in a strong field (the pulse is partly inside the mesh at
     # t = 0); reported apart from the cells the pulse reaches gradually
@@ -824,11 +825,13 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
             if w == Z:
                 torch.cuda.synchronize()
                 ref_s += time.perf_counter() - tr
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        ak.ionize_step_adaptive(gas, E, mesh.dt, Pa, La, Wa, 1, Z, eps=eps, tol=tol, work=work, counters=cnt)
-        torch.cuda.synchronize()
-        ada_s += time.perf_counter() - ta
+        for tol, a in ada.items():
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            ak.ionize_step_adaptive(gas, E, mesh.dt, a["P"], a["L"], a["W"], 1, Z, eps=eps, tol=tol, work=work,
+                                    counters=a["cnt"])
+            torch.cuda.synchronize()
+            a["s"] += time.perf_counter() - ta
         ne_now = (lev * st[Z][0]).sum(0)
         jump = torch.maximum(jump, ne_now - ne_prev)
         ne_prev = ne_now
@@ -841,15 +844,16 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
                 ne = (lev * full).sum(0)
                 nemax[w] = torch.maximum(nemax[w], torch.where(ne_ref > 1e-3, (ne - ne_ref).abs() / ne_ref,
                                                                torch.zeros_like(ne)))
-            full = _to_full(Pa, La, Z, Z)
-            dmax_a = torch.maximum(dmax_a, (full - ref).abs().amax(dim=0))
-            ne = (lev * full).sum(0)
-            nemax_a = torch.maximum(nemax_a, torch.where(ne_ref > 1e-3, (ne - ne_ref).abs() / ne_ref,
-                                                         torch.zeros_like(ne)))
-            live = La < Z
-            width_sum += float(Wa[live].double().sum())
-            width_cells += float(live.sum())
-            width_max = max(width_max, int(Wa.max()))
+            for a in ada.values():
+                full = _to_full(a["P"], a["L"], Z, Z)
+                a["dmax"] = torch.maximum(a["dmax"], (full - ref).abs().amax(dim=0))
+                ne = (lev * full).sum(0)
+                a["nemax"] = torch.maximum(a["nemax"], torch.where(ne_ref > 1e-3, (ne - ne_ref).abs() / ne_ref,
+                                                                   torch.zeros_like(ne)))
+                live = a["L"] < Z
+                a["wsum"] += float(a["W"][live].double().sum())
+                a["wcells"] += float(live.sum())
+                a["wmax"] = max(a["wmax"], int(a["W"].max()))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ne_final = (lev * st[Z][0]).sum(0)
@@ -875,24 +879,28 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
         log(f"[study3d] w={w}: gradual-onset cells max |dN| {gr['max_abs_dN']:.2e} (p99.9 {gr['p99_9_abs_dN']:.1e}), "
             f"max rel n_e error {gr['max_rel_err_ne']:.2e}; strong-start cells max |dN| "
             f"{ss['max_abs_dN'] if ss else float('nan'):.2e}")
-    ga, sa = stats(dmax_a[gradual], nemax_a[gradual]), stats(dmax_a[~gradual], nemax_a[~gradual])
-    c = cnt.cpu().numpy()
-    res["adaptive"] = {"tolerance_per_step": tol, "wmin": 1, "wmax": Z, "gradual": ga, "strong_start": sa,
-                       "mean_width": width_sum / max(width_cells, 1.0), "max_width": width_max,
-                       "width_sampling": f"every {every} steps over cells with lo < Z",
-                       "us_per_step": ada_s / steps * 1e6,
-                       "wide_tier_cells_per_step": float(c[0]) / steps, "held_by_wmax": int(c[1]),
-                       "storage": "Z + 1 rows allotted (wmax = Z); a cell uses wc + 1 of them"}
-    log(f"[study3d] adaptive (tol {tol:g}/step): gradual-onset cells max |dN| {ga['max_abs_dN']:.2e}, max rel n_e "
-        f"error {ga['max_rel_err_ne']:.2e}; strong-start cells max |dN| {sa['max_abs_dN'] if sa else float('nan'):.2e}; "
-        f"mean width {res['adaptive']['mean_width']:.2f} (max {width_max}); {res['adaptive']['us_per_step']:.0f} "
-        f"us/step against {res['full_chain_us_per_step']:.0f} for the full chain")
+    for tol, a in ada.items():
+        ga, sa = stats(a["dmax"][gradual], a["nemax"][gradual]), stats(a["dmax"][~gradual], a["nemax"][~gradual])
+        c = a["cnt"].cpu().numpy()
+        key = "adaptive" if tol == tols[0] else f"adaptive_tol_{tol:g}"
+        r = {"tolerance_per_step": tol, "wmin": 1, "wmax": Z, "gradual": ga, "strong_start": sa,
+             "mean_width": a["wsum"] / max(a["wcells"], 1.0), "max_width": a["wmax"],
+             "width_sampling": f"every {every} steps over cells with lo < Z",
+             "us_per_step": a["s"] / steps * 1e6,
+             "wide_tier_cells_per_step": float(c[0]) / steps, "held_by_wmax": int(c[1]),
+             "storage": "Z + 1 rows allotted (wmax = Z); a cell uses wc + 1 of them"}
+        res[key] = r
+        log(f"[study3d] adaptive (tol {tol:g}/step): gradual-onset cells max |dN| {ga['max_abs_dN']:.2e}, max rel "
+            f"n_e error {ga['max_rel_err_ne']:.2e}; strong-start cells max |dN| "
+            f"{sa['max_abs_dN'] if sa else float('nan'):.2e}; mean width {r['mean_width']:.2f} (max {a['wmax']}); "
+            f"{r['us_per_step']:.0f} us/step against {res['full_chain_us_per_step']:.0f} for the full chain; "
+            f"{r['wide_tier_cells_per_step']:.0f} cells/step on the wavefront tier")
     jg = res["largest_charge_gain_in_one_step"]["gradual"]
     log(f"[study3d] largest charge gain of the full chain in one step (gradual-onset cells): median "
         f"{jg['median']:.2f}, max {jg['max']:.2f} levels")
     log(f"[study3d] full 36-level chain: {res['full_chain_us_per_step']:.0f} us/step on {n} cells; "
         f"final mean charge {res['final_mean_charge']['mean']:.3f} (max {res['final_mean_charge']['max']:.2f})")
-    del st, dmax, nemax, Pa, La, Wa, work
+    del st, dmax, nemax, ada, work
     gas.close()
     torch.cuda.empty_cache()
     return res
@@ -1306,9 +1314,13 @@ def main():
     if not args.no_study and args.study3d_steps > 0:
         study3d = window_study_3d(adkion, mesh3, eps, args.study3d_steps)
     head["electron_yield"] = yield_measure(adkion, gas36, w, eps, args.yield_steps)
-    adaptive = None if args.adaptive_steps <= 0 else adaptive_measure(adkion, gas36, mesh3, args.adaptive_steps, eps)
-    if adaptive:
-        adaptive["speedup_vs_fixed_w3_mixed"] = adaptive["value"] / head["mixed"]["value"]
+    adaptive = None
+    if args.adaptive_steps > 0:
+        adaptive = {}
+        for tol in (1e-9, 1e-6):
+            r = adaptive_measure(adkion, gas36, mesh3, args.adaptive_steps, eps, tol=tol)
+            r["speedup_vs_fixed_w3_mixed"] = r["value"] / head["mixed"]["value"]
+            adaptive[f"tol_{tol:g}"] = r
     surrogate = None
     if not args.no_surrogate:
         surrogate = surrogate_measure(adkion, oracle, gas36, spec36, w, eps, args.surrogate_steps,

@@ -157,7 +157,7 @@ template <bool TRACE>
 __global__ __launch_bounds__(kBlock) void fwd_kernel(FwdArgs a)
 {
     __shared__ MlpShared s;
-    __shared__ float ctab[ADK_MAX_Z * kH];
+    __shared__ float ctab[ADK_MAX_Z * kCtabStride];
     stage_mlp(s, ctab, a.prm, a.L, 0.0f, false);
     const int lane = threadIdx.x & 63, g = lane >> 4, nn = lane & 15;
     MlpRegs r;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void fwd_kernel(FwdArgs a)
         const int k = a.K[si];
         bf16x8 h1[2], h2[2], h3[2];
         float *zt = (TRACE && ok) ? a.Zt + ii * kTraceRow : nullptr;
-        const f32x4 z = mlp_logits<true, TRACE>(r, s.b2 + opaque_zero(), ctab + k * kH, a.U[si], a.V[si], 0, h1,
+        const f32x4 z = mlp_logits<true, TRACE>(r, s.b2 + opaque_zero(), ctab + k * kCtabStride, a.U[si], a.V[si], 0, h1,
                                                 h2, h3, zt);
         if (TRACE && ok && g == 0) {
 #pragma unroll

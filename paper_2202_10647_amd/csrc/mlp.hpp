@@ -33,6 +33,10 @@ constexpr int kH = ADK_MLP_HIDDEN;  // hidden width
 constexpr int kEmb = ADK_MLP_EMB;   // embedding width
 constexpr int kBand = ADK_MLP_BAND; // output band
 constexpr int kWStride = 72;        // bf16 row stride of staged weights (spreads LDS banks)
+// Float row stride of the per-level layer-1 table in LDS: the 16 samples of a
+// group read rows of different levels, and with rows 64 floats apart every
+// such read would hit the same banks; 68 puts row k at bank offset 4k.
+constexpr int kCtabStride = kH + 4;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -78,7 +82,8 @@ __host__ __device__ constexpr int hid(int c, int g, int i)
 }
 
 // Stage the bf16 weights, the biases and the per-level layer-1 table ctab
-// (W1e emb[k] + b1, plus W1v v when fold_v: inference at one step size).
+// (W1e emb[k] + b1, plus W1v v when fold_v: inference at one step size; row
+// k at ctab + k kCtabStride).
 __device__ inline void stage_mlp(MlpShared &s, float *ctab, const float *__restrict__ prm, const MlpLayout &L,
                                  float v, bool fold_v)
 {
@@ -103,7 +108,7 @@ __device__ inline void stage_mlp(MlpShared &s, float *ctab, const float *__restr
         float acc = prm[L.b1 + h];
         for (int j = 0; j < kEmb; ++j) acc = fmaf(prm[L.W1e + h * kEmb + j], prm[L.emb + k * kEmb + j], acc);
         if (fold_v) acc = fmaf(prm[L.W1v + h], v, acc);
-        ctab[t] = acc;
+        ctab[k * kCtabStride + h] = acc;
     }
     __syncthreads();
 }

@@ -26,19 +26,23 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Dynamic LDS: the layer-1 table ctab[Z][64], then per wavefront the list of
-// (cell, source) pairs that need the network (u and level k, 64 W entries)
-// and their columns (64 W float4).
+constexpr int kSurBlock = kBlock;
+constexpr int kSurWaves = kSurBlock / 64;
+
+// Dynamic LDS: the layer-1 table ctab[Z][kCtabStride], then per wavefront
+// 64 W slots of 16 bytes: the (cell, source) pairs that need the network
+// (u and level k), overwritten by their columns once evaluated.
 template <int W>
 constexpr size_t sur_dyn_bytes(int Z)
 {
-    return (size_t)Z * kH * sizeof(float) + (size_t)(kBlock / 64) * 64 * W * (sizeof(float2) + sizeof(f32x4));
+    return (size_t)Z * kCtabStride * sizeof(float) + (size_t)kSurWaves * 64 * W * sizeof(f32x4);
 }
 
 template <int W>
-__global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const float *__restrict__ E,
-                                                              float *__restrict__ pops, uint8_t *__restrict__ lo,
-                                                              int64_t n, ChunkOrder ord)
+__global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, const float *__restrict__ E,
+                                                                             float *__restrict__ pops,
+                                                                             uint8_t *__restrict__ lo, int64_t n,
+                                                                             ChunkOrder ord)
 {
     __shared__ double sc[kDevTableLen];
     __shared__ MlpShared ms;
@@ -47,16 +51,16 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
     const int Z = a.st.Z;
     const int lane = threadIdx.x & 63;
     float *ctab = (float *)dyn;
-    float2 *cand = (float2 *)(dyn + (size_t)Z * kH * sizeof(float)) + (threadIdx.x >> 6) * 64 * W;
-    f32x4 *res = (f32x4 *)(dyn + (size_t)Z * kH * sizeof(float) + (size_t)(kBlock / 64) * 64 * W * sizeof(float2)) +
-                 (threadIdx.x >> 6) * 64 * W;
+    // a group reads its pairs before it writes their columns into the same
+    // slots, and no other group touches them
+    f32x4 *slot = (f32x4 *)(dyn + (size_t)Z * kCtabStride * sizeof(float)) + (threadIdx.x >> 6) * 64 * W;
     for (int t = threadIdx.x; t < Z; t += blockDim.x) sthr[t] = a.thr[t];
     stage_coefficients(sc, a.st.tab, a.st.ln_dt);
     stage_mlp(ms, ctab, a.prm, a.L, a.v, true);
     const double *slog = sc + kCoefRows * kCoefStride;
     const bool has_poly = a.st.has_poly != 0;
-    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t wave = ((int64_t)blockIdx.x * kSurBlock + threadIdx.x) >> 6;
+    const int64_t nwaves = (int64_t)gridDim.x * kSurWaves;
     const unsigned long long below = (1ull << lane) - 1ull;  // lanes under this one
     unsigned long long n_fb = 0, n_eval = 0;
 
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
                 need[s] = use_mlp && s < top && !(EL < (double)sthr[k < Z ? k : Z - 1]);
                 const unsigned long long m = __ballot(need[s]);
                 pos[s] = cnt + __popcll(m & below);
-                if (need[s]) cand[pos[s]] = make_float2(u, __int_as_float(k));
+                if (need[s]) slot[pos[s]] = (f32x4){u, __int_as_float(k), 0.0f, 0.0f};
                 cnt += __popcll(m);
             }
             wave_lds_sync();
@@ -145,30 +149,32 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
                 for (; g0 + 16 < cnt; g0 += 32) {
                     const int ta = g0 + (lane & 15), tb = ta + 16;
                     const bool okb = tb < cnt;
-                    const float2 ca = cand[ta], cb = cand[okb ? tb : 0];
+                    // lanes past the count take a pair of their own group (slots
+                    // of earlier groups already hold columns)
+                    const f32x4 ca = slot[ta], cb = slot[okb ? tb : ta];
                     f32x4 za, zb;
                     // sample n of a group is candidate g0 + n (g0 + 16 + n); its logits land in lane n
-                    mlp_logits_x2(r, ms.b2 + opaque_zero(), ctab + __float_as_int(ca.y) * kH, ca.x,
-                                  ctab + __float_as_int(cb.y) * kH, cb.x, 0, za, zb);
+                    mlp_logits_x2(r, ms.b2 + opaque_zero(), ctab + __float_as_int(ca.y) * kCtabStride, ca.x,
+                                  ctab + __float_as_int(cb.y) * kCtabStride, cb.x, 0, za, zb);
                     float zm, lse;
                     const f32x4 Qa = softmax4(za, zm, lse);
                     const f32x4 Qb = softmax4(zb, zm, lse);
                     if (lane < 16) {
-                        res[ta] = Qa;
-                        if (okb) res[tb] = Qb;
+                        slot[ta] = Qa;
+                        if (okb) slot[tb] = Qb;
                     }
                 }
                 if (g0 < cnt) {
                     const int t = g0 + (lane & 15);
                     const bool ok = t < cnt;
-                    const float2 cu = cand[ok ? t : 0];
+                    const f32x4 cu = slot[ok ? t : g0];
                     const int k = __float_as_int(cu.y);
                     bf16x8 h1[2], h2[2], h3[2];
-                    const f32x4 z = mlp_logits<false>(r, ms.b2 + opaque_zero(), ctab + k * kH, cu.x, 0.0f, 0, h1,
-                                                      h2, h3);
+                    const f32x4 z = mlp_logits<false>(r, ms.b2 + opaque_zero(), ctab + k * kCtabStride, cu.x, 0.0f,
+                                                      0, h1, h2, h3);
                     float zm, lse;
                     const f32x4 Q = softmax4(z, zm, lse);
-                    if (lane < 16 && ok) res[t] = Q;
+                    if (lane < 16 && ok) slot[t] = Q;
                 }
                 wave_lds_sync();
             }
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(kBlock, 3) void surrogate_kernel(SurArgs a, const f
             for (int j = 0; j < W + kBand; ++j) acc[j] = 0.0f;
 #pragma unroll
             for (int s = 0; s < W; ++s) {
-                const f32x4 Q = need[s] ? res[pos[s]] : (f32x4){1.0f, 0.0f, 0.0f, 0.0f};
+                const f32x4 Q = need[s] ? slot[pos[s]] : (f32x4){1.0f, 0.0f, 0.0f, 0.0f};
                 const float ns = s < top ? out[s] : 0.0f;  // = N[s] on the network's cells
 #pragma unroll
                 for (int d = 0; d < kBand; ++d) acc[s + d] = fmaf(Q[d], ns, acc[s + d]);
@@ -222,14 +228,16 @@ hipError_t launch(const SurArgs &a, const float *E, float *pops, uint8_t *lo, in
     static int per_cu[ADK_MAX_Z + 1] = {};  // occupancy per level count (LDS grows with Z)
     int b = per_cu[a.st.Z];
     if (b <= 0) {
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, surrogate_kernel<W>, kBlock, dyn) != hipSuccess || b <= 0)
-            b = 2;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, surrogate_kernel<W>, kSurBlock, dyn) != hipSuccess ||
+            b <= 0)
+            b = 1;
         per_cu[a.st.Z] = b;
     }
-    const int64_t need = (n + kBlock - 1) / kBlock;
+    const int64_t need = (n + kSurBlock - 1) / kSurBlock;
     const int64_t cap = (int64_t)num_cus() * b;
     const int grid = (int)(need < cap ? need : cap);
-    hipLaunchKernelGGL(surrogate_kernel<W>, dim3(grid), dim3(kBlock), dyn, st, a, E, pops, lo, n, chunk_order(n, 64));
+    hipLaunchKernelGGL(surrogate_kernel<W>, dim3(grid), dim3(kSurBlock), dyn, st, a, E, pops, lo, n,
+                       chunk_order(n, 64));
     return hipGetLastError();
 }
 

@@ -123,12 +123,17 @@ def test_forward_matches_oracle(env, orc):
     Q = net.forward(*_dev(torch, E, dt, k)).cpu().numpy().astype(np.float64)
     assert np.array_equal(Q, Qt)
     assert np.all(Q >= 0) and np.allclose(Q.sum(axis=0), 1.0, atol=1e-6)
-    # the FP64 network's own rounding decisions reach the same columns except
-    # where a pre-activation lies at a rounding boundary: report how often
+    # independent of the device's values: the FP64 network with its own
+    # rounding decisions reaches the same columns except where a
+    # pre-activation lies at a bfloat16 rounding boundary, and there the
+    # columns move by at most what a few roundings of one ulp can cause
     u, v = RNG.features(E, dt)
     Qo, _ = mlp.forward(params.astype(np.float64), Z, u, v, k)
     d = np.abs(Q - Qo.T).max(axis=0)
-    print(f"samples whose columns differ from the FP64 network's own roundings by > 1e-5: {np.mean(d > 1e-5):.4f}")
+    print(f"columns against the FP64 network's own roundings: {np.mean(d > 1e-5):.4f} of samples differ by "
+          f"> 1e-5, {np.mean(d > 1e-4):.4f} by > 1e-4, max {d.max():.2e}")
+    assert np.mean(d <= 1e-5) >= 0.99
+    assert d.max() <= 5e-3
     net.close()
 
 
