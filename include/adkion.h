@@ -541,11 +541,15 @@ int adk_mlp_load(const adk_gas *gas, const char *path, adk_mlp **out);
  * per-level field threshold computed on the host once per dt); every other
  * cell takes the analytic step of ionize_step (ADK_MIXED).  win->prec
  * must be ADK_MIXED, win->layout ADK_LAYOUT_COMPACT, 1 <= win->w <= 3.
+ * A cell whose |E| lies below its window's identity field (every rate of
+ * the window below 1e-16 per step) with no shift due is left unchanged on
+ * either path, as ionize_step leaves it.
  * counters (device, 2 x uint64, may be NULL) are incremented by: [0] cells
- * with a window below the top level that fell back to the analytic step with
- * |E| at or above the gas's field cutoff (below it the step is the identity
- * either way), [1] (cell, source level) pairs evaluated by the network
- * (negligible sources excluded).
+ * with a window below the top level that took the analytic step (out of the
+ * trained range, not left unchanged as above) with |E| at or above the gas's
+ * field cutoff (below it the step is only the window shift), [1] (cell,
+ * source level) pairs evaluated by the network (negligible sources
+ * excluded).
  * Allocates nothing and never synchronises.  Errors: ADK_EINVAL (null
  * arguments with ncells > 0, dt <= 0 or non-finite, eps < 0, prec or layout
  * other than above, network and gas of different Z), ADK_ERANGE (w outside

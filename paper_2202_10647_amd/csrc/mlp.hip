@@ -1072,7 +1072,7 @@ int adk_surrogate_step(const adk_gas *gas, const adk_mlp *m, const void *E, int6
     const bool dt_ok = dt >= m->range.dt_lo && dt <= m->range.dt_hi;
     a.E_lo = dt_ok ? m->range.E_lo : INFINITY;
     a.E_hi = dt_ok ? m->range.E_hi : -INFINITY;
-    a.E_fast = dt_ok ? std::fmin(a.st.E_cut, m->range.E_lo) : a.st.E_cut;
+    a.cut = window_cutoffs(gas, dt, win->w);  // (takes the gas's lock itself)
     a.counters = counters;
     {
         adk_gas *g = const_cast<adk_gas *>(gas);

@@ -368,7 +368,7 @@ struct SurArgs {
     float v;               // step feature (folded into the layer-1 table)
     float au, bu;          // u = au log2|E| + bu
     double E_lo, E_hi;     // trained field range; empty when dt is outside its range
-    double E_fast;         // below this |E| the step is the identity on either path
+    WinCut cut;            // per window bottom: below this |E| the step leaves the cell unchanged
     unsigned long long *counters;
     float thr[ADK_MAX_Z];  // source level k is negligible (identity column) for |E| < thr[k]
 };

@@ -47,6 +47,7 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
     __shared__ double sc[kDevTableLen];
     __shared__ MlpShared ms;
     __shared__ float sthr[ADK_MAX_Z];
+    __shared__ float scut[ADK_MAX_Z + 1];
     extern __shared__ __align__(16) unsigned char dyn[];
     const int Z = a.st.Z;
     const int lane = threadIdx.x & 63;
@@ -55,6 +56,7 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
     // slots, and no other group touches them
     f32x4 *slot = (f32x4 *)(dyn + (size_t)Z * kCtabStride * sizeof(float)) + (threadIdx.x >> 6) * 64 * W;
     for (int t = threadIdx.x; t < Z; t += blockDim.x) sthr[t] = a.thr[t];
+    for (int t = threadIdx.x; t <= ADK_MAX_Z; t += blockDim.x) scut[t] = a.cut.e[t];  // visible after staging
     stage_coefficients(sc, a.st.tab, a.st.ln_dt);
     stage_mlp(ms, ctab, a.prm, a.L, a.v, true);
     const double *slog = sc + kCoefRows * kCoefStride;
@@ -82,7 +84,13 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
         }
         int p = lo0 < Z ? lo0 : Z;
         const double EL = fabs((double)Ef);
-        if (__all(p >= Z || (EL < a.E_fast && (double)Nf[0] >= a.st.eps))) {
+        // a cell under its window's identity field (every rate of the
+        // window below 1e-16 per step) with no shift due is left as it is,
+        // as ionize_step leaves it: the exact step would move less than
+        // 3e-16, and for a field in the trained range every source is then
+        // negligible, so the network's form is the identity too
+        const bool idle = p >= Z || (EL < (double)scut[p] && (double)Nf[0] >= a.st.eps);
+        if (__all(idle)) {
             if (valid && p != lo0) lo[c] = (uint8_t)p;  // windows unchanged in place
             continue;
         }
@@ -96,7 +104,7 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
             N[W] = 0.0;
             ++p;
         }
-        const bool act = p < Z;
+        const bool act = p < Z && !idle;
         const bool in = EL >= a.E_lo && EL <= a.E_hi;
         const bool use_mlp = act && in;
         const bool use_an = act && !in;
