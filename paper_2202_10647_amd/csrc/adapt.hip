@@ -423,8 +423,8 @@ __device__ void adaptive_wide_cell(const StepArgs &a, const AdaptArgs &ad, int64
         if (held && counters && lane == 0) atomicAdd(&counters[1], 1ull);
         wave_sync();
         if (top > 0 && finite) {
-            const double r = chain_sub(top, lane < top ? x : 0.0, lane <= top ? Ns : 0.0, s, e, mm, Nb, cid, pos,
-                                       D, V, wmax);
+            const double r = chain_sub<false>(top, lane < top ? x : 0.0, lane <= top ? Ns : 0.0, s, e, mm, Nb, cid, pos,
+                                              D, V, wmax);
             if (lane <= top) out = r;
         }
     }
@@ -439,7 +439,7 @@ __device__ void adaptive_wide_cell(const StepArgs &a, const AdaptArgs &ad, int64
     }
 }
 
-constexpr size_t adaptive_wave_doubles(int W) { return wide_wave_doubles(W) + 128; }
+constexpr size_t adaptive_wave_doubles(int W) { return wide_wave_doubles(W, false) + 128; }
 
 template <class R>
 __global__ __launch_bounds__(kWideBlock) void adaptive_wide_kernel(StepArgs a, AdaptArgs ad,
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kWideBlock) void adaptive_wide_kernel(StepArgs a, A
     int *pos = cid + 64;
     double *D = wl + 384;
     double *V = D + W * (W + 1) / 2;
-    double *lx = wl + wide_wave_doubles(W);
+    double *lx = wl + wide_wave_doubles(W, false);
     double *lN = lx + 64;
     const uint32_t count = hdr->count;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {

@@ -267,70 +267,126 @@ __device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *sf, c
     return z4;
 }
 
-// Two independent groups A and B through the same weights, interleaved
-// stage by stage so that each stage has twice the independent matrix-core
-// and vector work in flight (inference, v folded into the table).
-__device__ __forceinline__ void mlp_logits_x2(const MlpRegs &r, const float *sf, const float *crowA, float uA,
-                                              const float *crowB, float uB, int qo, f32x4 &zA, f32x4 &zB)
+// Biases and layer-1 field weights of a wavefront's network pass in
+// registers: every group reads the same values, and from LDS they would be
+// most of a group's LDS traffic (the LDS return path, shared by the four
+// SIMDs of a CU, bounds the pass).  Lane (g, n) holds the units its tiles
+// use: b2 and b3 for units 16 t + 4 g + i, the layer-1 weights for units
+// hid(c, g, i).
+// What a pass keeps in registers: 2 all of them, 1 the layer-1 weights and
+// b4 (b2 and b3 from LDS), 0 none.  Measured on the 3D pulse (one group per
+// pass, three wavefronts per SIMD): 1 is 3 % faster than 0; 2 needs two
+// wavefronts per SIMD or spills, and is 5-10 % slower.
+constexpr int kBiasRegs = 1;
+struct MlpBias {
+    f32x4 b2[kBiasRegs >= 2 ? 4 : 1], b3[kBiasRegs >= 2 ? 4 : 1], w[2][2], b4;
+};
+
+__device__ __forceinline__ void load_bias(MlpBias &b, const MlpShared &s, int lane)
+{
+    const int g = lane >> 4;
+    if constexpr (kBiasRegs >= 2) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            b.b2[t] = *(const f32x4 *)(s.b2 + 16 * t + 4 * g);
+            b.b3[t] = *(const f32x4 *)(s.b3 + 16 * t + 4 * g);
+        }
+    }
+    if constexpr (kBiasRegs >= 1) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            b.w[c][0] = *(const f32x4 *)(s.wu + hid(c, g, 0));
+            b.w[c][1] = *(const f32x4 *)(s.wu + hid(c, g, 4));
+        }
+        b.b4 = *(const f32x4 *)s.b4;
+    }
+}
+
+// NG independent groups through the same weights, interleaved stage by
+// stage so that each stage has NG times the independent matrix-core and
+// vector work in flight (inference, v folded into the table).  Group q
+// takes its samples' table rows crow[q] and features u[q]; its logits land
+// in z[q] as in mlp_logits.
+template <int NG>
+__device__ __forceinline__ void mlp_logits_xn(const MlpRegs &r, const MlpBias &bs, const float *sf,
+                                              const float *const (&crow)[NG], const float (&u)[NG], int qo,
+                                              f32x4 (&z)[NG])
 {
     const int g = (threadIdx.x & 63) >> 4;
-    const float *b2 = sf, *b3 = sf + kH, *b4 = sf + 2 * kH, *wu = b4 + 16;
-    bf16x8 hA[2], hB[2];
+    // sf: MlpShared::b2 (followed by b3, b4, wu), for what is not in bs
+    const float *sb2 = sf, *sb3 = sf + kH, *sb4 = sf + 2 * kH, *swu = sb4 + 16;
+    bf16x8 h[NG][2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const f32x4 w0 = lds4(wu + hid(c, g, 0)), w1 = lds4(wu + hid(c, g, 4));
-        const f32x4 a0 = lds4(crowA + hid(c, g, 0)), a1 = lds4(crowA + hid(c, g, 4));
-        const f32x4 c0 = lds4(crowB + hid(c, g, 0)), c1 = lds4(crowB + hid(c, g, 4));
-        const u32x4 wa = {pack2(fmaf(w0[0], uA, a0[0]), fmaf(w0[1], uA, a0[1])),
-                          pack2(fmaf(w0[2], uA, a0[2]), fmaf(w0[3], uA, a0[3])),
-                          pack2(fmaf(w1[0], uA, a1[0]), fmaf(w1[1], uA, a1[1])),
-                          pack2(fmaf(w1[2], uA, a1[2]), fmaf(w1[3], uA, a1[3]))};
-        const u32x4 wb = {pack2(fmaf(w0[0], uB, c0[0]), fmaf(w0[1], uB, c0[1])),
-                          pack2(fmaf(w0[2], uB, c0[2]), fmaf(w0[3], uB, c0[3])),
-                          pack2(fmaf(w1[0], uB, c1[0]), fmaf(w1[1], uB, c1[1])),
-                          pack2(fmaf(w1[2], uB, c1[2]), fmaf(w1[3], uB, c1[3]))};
-        hA[c] = relu_bf16(wa);
-        hB[c] = relu_bf16(wb);
-    }
-    f32x4 accA[4], accB[4];
+        f32x4 w0, w1;
+        if constexpr (kBiasRegs >= 1) {
+            w0 = bs.w[c][0];
+            w1 = bs.w[c][1];
+        } else {
+            w0 = lds4(swu + hid(c, g, 0));
+            w1 = lds4(swu + hid(c, g, 4));
+        }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        accA[t] = accB[t] = lds4(b2 + 16 * t + 4 * g);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            accA[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], hA[c], accA[t], 0, 0, 0);
-            accB[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], hB[c], accB[t], 0, 0, 0);
+        for (int q = 0; q < NG; ++q) {
+            const f32x4 a0 = lds4(crow[q] + hid(c, g, 0)), a1 = lds4(crow[q] + hid(c, g, 4));
+            const u32x4 wq = {pack2(fmaf(w0[0], u[q], a0[0]), fmaf(w0[1], u[q], a0[1])),
+                              pack2(fmaf(w0[2], u[q], a0[2]), fmaf(w0[3], u[q], a0[3])),
+                              pack2(fmaf(w1[0], u[q], a1[0]), fmaf(w1[1], u[q], a1[1])),
+                              pack2(fmaf(w1[2], u[q], a1[2]), fmaf(w1[3], u[q], a1[3]))};
+            h[q][c] = relu_bf16(wq);
         }
     }
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        hA[c] = relu_pack(accA[2 * c], accA[2 * c + 1]);
-        hB[c] = relu_pack(accB[2 * c], accB[2 * c + 1]);
-    }
+    f32x4 acc[NG][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        accA[t] = accB[t] = lds4(b3 + 16 * t + 4 * g);
+        f32x4 bb;
+        if constexpr (kBiasRegs >= 2) bb = bs.b2[t];
+        else bb = lds4(sb2 + 16 * t + 4 * g);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            accA[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], hA[c], accA[t], 0, 0, 0);
-            accB[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], hB[c], accB[t], 0, 0, 0);
-        }
+        for (int q = 0; q < NG; ++q) acc[q][t] = bb;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int q = 0; q < NG; ++q)
+                acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], h[q][c], acc[q][t], 0, 0, 0);
     }
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        hA[c] = relu_pack(accA[2 * c], accA[2 * c + 1]);
-        hB[c] = relu_pack(accB[2 * c], accB[2 * c + 1]);
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < NG; ++q) h[q][c] = relu_pack(acc[q][2 * c], acc[q][2 * c + 1]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        f32x4 bb;
+        if constexpr (kBiasRegs >= 2) bb = bs.b3[t];
+        else bb = lds4(sb3 + 16 * t + 4 * g);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) acc[q][t] = bb;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int q = 0; q < NG; ++q)
+                acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], h[q][c], acc[q][t], 0, 0, 0);
     }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < NG; ++q) h[q][c] = relu_pack(acc[q][2 * c], acc[q][2 * c + 1]);
     const bool rows_q = ((threadIdx.x & 15) >> 2) == qo;
-    const f32x4 b4v = lds4(b4);
-    zA = zB = g == qo ? b4v : (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+        f32x4 b4v;
+        if constexpr (kBiasRegs >= 1) b4v = bs.b4;
+        else b4v = lds4(sb4);
+        z[q] = g == qo ? b4v : (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    }
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const bf16x8 a4 = rows_q ? r.A4[c] : (bf16x8){};
-        zA = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a4, hA[c], zA, 0, 0, 0);
-        zB = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a4, hB[c], zB, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) z[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a4, h[q][c], z[q], 0, 0, 0);
     }
 }
+
 
 // softmax of four logits; also returns log of the normaliser (for the loss).
 __device__ __forceinline__ f32x4 softmax4(const f32x4 &z, float &m, float &lse)

@@ -28,6 +28,9 @@ __device__ __forceinline__ void wave_lds_sync()
 
 constexpr int kSurBlock = kBlock;
 constexpr int kSurWaves = kSurBlock / 64;
+// One 16-sample group per network pass: interleaving 2 groups measured 2 %
+// slower and 3 or 4 (two wavefronts per SIMD) 10 % slower on the 3D pulse.
+constexpr int kSurGroups = 1;
 
 // Dynamic LDS: the layer-1 table ctab[Z][kCtabStride], then per wavefront
 // 64 W slots of 16 bytes: the (cell, source) pairs that need the network
@@ -40,9 +43,8 @@ constexpr size_t sur_dyn_bytes(int Z)
 
 template <int W>
 __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, const float *__restrict__ E,
-                                                                             float *__restrict__ pops,
-                                                                             uint8_t *__restrict__ lo, int64_t n,
-                                                                             ChunkOrder ord)
+                                                                 float *__restrict__ pops, uint8_t *__restrict__ lo,
+                                                                 int64_t n, ChunkOrder ord)
 {
     __shared__ double sc[kDevTableLen];
     __shared__ MlpShared ms;
@@ -151,38 +153,32 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
                 // the analytic branch)
                 MlpRegs r;
                 load_regs(r, *(const MlpShared *)((const char *)&ms + opaque_zero()), lane);
-                // two groups of 16 at a time (independent work interleaved),
-                // then a last single group when the count leaves one
-                int g0 = 0;
-                for (; g0 + 16 < cnt; g0 += 32) {
-                    const int ta = g0 + (lane & 15), tb = ta + 16;
-                    const bool okb = tb < cnt;
-                    // lanes past the count take a pair of their own group (slots
-                    // of earlier groups already hold columns)
-                    const f32x4 ca = slot[ta], cb = slot[okb ? tb : ta];
-                    f32x4 za, zb;
-                    // sample n of a group is candidate g0 + n (g0 + 16 + n); its logits land in lane n
-                    mlp_logits_x2(r, ms.b2 + opaque_zero(), ctab + __float_as_int(ca.y) * kCtabStride, ca.x,
-                                  ctab + __float_as_int(cb.y) * kCtabStride, cb.x, 0, za, zb);
-                    float zm, lse;
-                    const f32x4 Qa = softmax4(za, zm, lse);
-                    const f32x4 Qb = softmax4(zb, zm, lse);
-                    if (lane < 16) {
-                        slot[ta] = Qa;
-                        if (okb) slot[tb] = Qb;
+                MlpBias bs;
+                if constexpr (kBiasRegs > 0) load_bias(bs, *(const MlpShared *)((const char *)&ms + opaque_zero()), lane);
+                // kSurGroups groups of 16 at a time (independent work
+                // interleaved), then one more pass for the groups left; lanes
+                // past the count take a pair of their own pass (slots of
+                // earlier passes already hold columns); sample n of group q
+                // is candidate g0 + 16 q + n, and its logits land in lane n
+                for (int g0 = 0; g0 < cnt; g0 += 16 * kSurGroups) {
+                    const float *crow[kSurGroups];
+                    float uq[kSurGroups];
+#pragma unroll
+                    for (int q = 0; q < kSurGroups; ++q) {
+                        const int t = g0 + 16 * q + (lane & 15);
+                        const f32x4 cq = slot[t < cnt ? t : g0];
+                        crow[q] = ctab + __float_as_int(cq.y) * kCtabStride;
+                        uq[q] = cq.x;
                     }
-                }
-                if (g0 < cnt) {
-                    const int t = g0 + (lane & 15);
-                    const bool ok = t < cnt;
-                    const f32x4 cu = slot[ok ? t : g0];
-                    const int k = __float_as_int(cu.y);
-                    bf16x8 h1[2], h2[2], h3[2];
-                    const f32x4 z = mlp_logits<false>(r, ms.b2 + opaque_zero(), ctab + k * kCtabStride, cu.x, 0.0f,
-                                                      0, h1, h2, h3);
-                    float zm, lse;
-                    const f32x4 Q = softmax4(z, zm, lse);
-                    if (lane < 16 && ok) slot[t] = Q;
+                    f32x4 z[kSurGroups];
+                    mlp_logits_xn<kSurGroups>(r, bs, ms.b2 + opaque_zero(), crow, uq, 0, z);
+#pragma unroll
+                    for (int q = 0; q < kSurGroups; ++q) {
+                        float zm, lse;
+                        const f32x4 Q = softmax4(z[q], zm, lse);
+                        const int t = g0 + 16 * q + (lane & 15);
+                        if (lane < 16 && t < cnt) slot[t] = Q;
+                    }
                 }
                 wave_lds_sync();
             }

@@ -80,8 +80,8 @@ __device__ void wide_cell(const StepArgs &a, int W, bool full, int64_t c,
             if (Wp > 0) {
                 const int src = lane + q_lo < 64 ? lane + q_lo : 63;
                 const double xs = __shfl(x, src), Nsub = __shfl(Ns, src);
-                const double r = chain_sub(Wp, lane < Wp ? xs : 0.0, lane <= Wp ? Nsub : 0.0, s, e, mm, Nb, cid,
-                                           pos, D, V, W);
+                const double r = chain_sub<true>(Wp, lane < Wp ? xs : 0.0, lane <= Wp ? Nsub : 0.0, s, e, mm, Nb,
+                                                 cid, pos, D, V, W);
                 const double back = __shfl(r, lane - q_lo >= 0 ? lane - q_lo : 0);
                 if (lane >= q_lo && lane <= top) out = back;
             }
@@ -102,7 +102,9 @@ __device__ void wide_cell(const StepArgs &a, int W, bool full, int64_t c,
 }
 
 template <class R>
-__global__ __launch_bounds__(kWideBlock) void wide_step_kernel(StepArgs a, int W, int full, const R *__restrict__ E,
+// Four wavefronts per SIMD where LDS allows it (windows up to about 20
+// rates); the register cap spills a few registers.
+__global__ __launch_bounds__(kWideBlock, 4) void wide_step_kernel(StepArgs a, int W, int full, const R *__restrict__ E,
                                                                R *__restrict__ pops, uint8_t *__restrict__ lo,
                                                                int64_t n)
 {
@@ -146,7 +148,7 @@ hipError_t launch_wide(const adk_gas *g, const void *E, int64_t n, double dt, vo
 {
     const StepArgs a = step_args(g, dt, win->eps);
     const int W = win->w;
-    const size_t dyn = sizeof(double) * wide_wave_doubles(W);
+    const size_t dyn = sizeof(double) * wide_wave_doubles(W, true);
     static int per_cu[ADK_MAX_WIDE_W + 1] = {};  // occupancy per width (LDS grows with W)
     int b = per_cu[W];
     if (b <= 0) {
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_advance_kernel(int W, const R
             x = v < (double)kXMax<R> ? v : (v == v ? (double)kXMax<R> : v);
         }
         const double Nk = lane <= W ? (double)pops[(int64_t)lane * n + c] : 0.0;
-        const double r = chain_sub(W, x, Nk, wl, wl + 64, wl + 128, wl + 192, cid, pos, D, V, W);
+        const double r = chain_sub<false>(W, x, Nk, wl, wl + 64, wl + 128, wl + 192, cid, pos, D, V, W);
         if (lane <= W) pops[(int64_t)lane * n + c] = (R)r;
     }
 }
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_advance_kernel(int W, const R
 template <class R>
 hipError_t launch_wide_advance(int W, const void *Wr, int64_t n, double dt, void *pops, hipStream_t st)
 {
-    const size_t dyn = sizeof(double) * wide_wave_doubles(W);
+    const size_t dyn = sizeof(double) * wide_wave_doubles(W, false);
     static int per_cu[ADK_MAX_WIDE_W + 1] = {};
     int b = per_cu[W];
     if (b <= 0) {

@@ -61,6 +61,7 @@ __device__ __forceinline__ double wide_delta(int n)
 }
 
 constexpr int kTaylorMaxTerms = 120;
+constexpr int kTaylorRegRow = 8;  // series rows of up to this many entries are summed in registers
 constexpr double kWideNegligible = 1e-30;  // populations and transfers below this are left out
 constexpr double kWideNegligibleLog = -69.07755278982137;  // log(1e-30)
 
@@ -120,6 +121,44 @@ __device__ void taylor_row(const double *s, const double *e, const double *mm, d
                            double *hv, int lane, int vs)
 {
     const double sa = s[a];
+    if (nmax <= kTaylorRegRow) {
+        // short rows in registers: the same sums, no LDS round trip per term
+        double y[kTaylorRegRow], h[kTaylorRegRow], acc[kTaylorRegRow];
+#pragma unroll
+        for (int k = 0; k < kTaylorRegRow; ++k) {
+            y[k] = k < nmax ? s[a + k + 1] - sa : 0.0;
+            h[k] = 1.0;
+            acc[k] = kInvFactL.v[k + 1];
+        }
+        double sgn = 1.0;
+        for (int m = 1; m < kTaylorMaxTerms; ++m) {
+            sgn = -sgn;
+            double prev = 0.0;
+            bool conv = true;
+#pragma unroll
+            for (int k = 0; k < kTaylorRegRow; ++k) {
+                if (k < nmax) {
+                    const double hk = fma(y[k], h[k], prev);
+                    h[k] = hk;
+                    prev = hk;
+                    const double term = sgn * hk * kInvFactL.v[k + 1 + m];
+                    acc[k] += term;
+                    conv = conv && !(fabs(term) > 1e-17 * acc[k]);
+                }
+            }
+            if (conv) break;
+        }
+        const double ea = e[a];
+        double scale = 1.0;
+#pragma unroll
+        for (int k = 0; k < kTaylorRegRow; ++k) {
+            if (k < nmax) {
+                scale *= mm[a + k + 1];
+                D[tri(a, a + k + 1)] = ea == 0.0 ? 0.0 : ea * acc[k] * scale;
+            }
+        }
+        return;
+    }
     for (int k = 1; k <= nmax; ++k) {
         hv[(k - 1) * vs + lane] = 1.0;
         D[tri(a, a + k)] = kInvFactL.v[k];
@@ -220,10 +259,79 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Row j = lane of the update, N'_j = sum_{i <= j} T[j][i] N_i (lanes below
+// Wp), and in err a bound on its absolute rounding error from the table
+// entries' relative bounds Et: the hole recurrence combines non-negative
+// terms, so a term's relative error is at most the largest of its entries'
+// plus the recurrence's own rounding.
+template <bool ERR>
+__device__ __forceinline__ double chain_rows(int Wp, double x, const double *s, const double *mm, const double *Nb,
+                                             const int *cid, const int *pos, const double *ls, const double *lNb,
+                                             const double *D, const float *Et, double *V, int vs, double &err)
+{
+    const int lane = wide_lane();
+    double acc = 0.0;
+    err = 0.0;
+    if (lane < Wp) {
+        const int j = lane;
+        const double mj = fmax(1.0, x);
+        double Rp = 1.0;  // prod_{k=i}^{j-1} min(x_k, 1)
+        double lb = 0.0;  // log of prod_{k=i}^{j-1} x_k / (j-i)!, which bounds T[j][i] (g <= 1/n!)
+        int A = pos[j], B = A;
+        for (int i = j; i >= 0; --i) {
+            const int pi = pos[i];
+            if (i < j) {
+                const double xi = s[pi];
+                Rp *= fmin(xi, 1.0);
+                if (Rp == 0.0) break;  // every lower source reaches row j through a zero rate
+                lb += ls[pi] - kLogFact.v[j - i] + kLogFact.v[j - i - 1];  // log x_i - log (j-i)
+            }
+            A = min(A, pi);
+            B = max(B, pi);
+            const double Ni = Nb[i];
+            // a source whose contribution is below 1e-30 is skipped (every
+            // skipped term is bounded by N_i prod x / (j-i)!)
+            if (Ni == 0.0 || fmin(lb, 0.0) + lNb[i] < kWideNegligibleLog) continue;
+            const int holes = (B - A + 1) - (j - i + 1);
+            double G, eG = 0.0;
+            if (holes == 0) {
+                G = D[tri(A, B)];
+                if constexpr (ERR) eG = (double)Et[tri(A, B)];
+            } else {
+                for (int t = 0; t <= holes; ++t) {
+                    V[t * vs + lane] = D[tri(A + t, B)];
+                    if constexpr (ERR) eG = fmax(eG, (double)Et[tri(A + t, B)]);
+                }
+                if constexpr (ERR) eG += (double)((holes + 1) * (holes + 2)) * kWideUlp;
+                int cnt = holes;
+                for (int q = B; q > A && cnt > 0; --q) {
+                    const int ci = cid[q];
+                    if (ci >= i && ci <= j) continue;
+                    --cnt;
+                    const double rh = 1.0 / mm[q];
+                    const double sq = s[q];
+                    double cur = V[lane];
+                    for (int t = 0; t <= cnt; ++t) {
+                        const double nxt = V[(t + 1) * vs + lane];
+                        V[t * vs + lane] = fma(nxt, mm[A + t + 1], (sq - s[A + t]) * cur) * rh;
+                        cur = nxt;
+                    }
+                }
+                G = V[lane];
+            }
+            const double term = Rp * (mm[A] / mj) * G * Ni;
+            acc += term;
+            if constexpr (ERR) err = fma(fabs(term), eG + 8.0 * kWideUlp, err);
+        }
+    }
+    return acc;
+}
+
 // The exact update of a window of Wp rates held one per lane (x_k in lane k
 // for k < Wp, N_k in lane k for k <= Wp; zero elsewhere): returns N'_k in
 // lane k.  All 64 lanes call it together.  V: per-lane columns of the hole
 // recurrence, entry t of lane k at V[t vs + k] (vs >= Wp, t <= Wp - 2).
+template <bool POSTERIOR>
 __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, double *mm, double *Nb, int *cid,
                             int *pos, double *D, double *V, int vs)
 {
@@ -248,8 +356,10 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
     // scaled Newton table of the sorted rates: the series for every entry
     // within kWideClusterSpread (one pass per row), then one order per step,
     // Newton where the spread reaches the order's threshold
+    float *Et = (float *)(V + (size_t)(vs - 1) * vs + 192);  // relative error bounds of the entries
     if (lane < Wp) {
         D[tri(lane, lane)] = e[lane];
+        if constexpr (POSTERIOR) Et[tri(lane, lane)] = (float)(4.0 * kWideUlp);
         int nmax = 0;
         while (lane + nmax + 1 < Wp && s[lane + nmax + 1] - s[lane] < kWideClusterSpread) ++nmax;
         if (nmax > 0) taylor_row(s, e, mm, D, lane, nmax, V, lane, vs);
@@ -261,6 +371,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
     // Lane a carries the bound of its entry [a][a+ord-1]; entry
     // [a+1][a+ord] is lane a+1's.
     double eprev = 4.0 * kWideUlp, emax = 0.0;
+    bool cancelled = false;  // an entry whose two terms cancelled exactly (its relative bound is void)
     for (int ord = 1; ord < Wp; ++ord) {
         const double enb = __shfl_down(eprev, 1);
         double ecur = eprev;
@@ -271,10 +382,14 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
                 const double A = D[tri(lo_, hi - 1)] * mm[hi], B = D[tri(lo_ + 1, hi)] * mm[lo_ + 1];
                 D[tri(lo_, hi)] = PolicyF64::quot(A - B, spread);
                 ecur = (fabs(A) * eprev + fabs(B) * enb) / fabs(A - B) + 4.0 * kWideUlp;
+                cancelled = cancelled || (A == B && A != 0.0);
             } else {
                 ecur = kWideSeriesErr;
             }
-            emax = fmax(emax, ecur);  // (0/0 of two vanishing entries is ignored)
+            // (0/0 of two vanishing entries gives NaN: the entry is 0 and so
+            // is its error; an exact cancellation of nonzero terms is flagged)
+            if constexpr (POSTERIOR) Et[tri(lo_, hi)] = ecur == ecur ? (float)fmin(ecur, 1e30) : 0.0f;
+            emax = fmax(emax, ecur);  // (NaN ignored, as above)
         }
         eprev = ecur;
         wave_sync();
@@ -289,52 +404,32 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
     // for every entry, the scaled table (entries of exp(-J/2^j), a factor
     // 2^-j per order, times the same max(1, s) scale) is squared j times, and
     // the entries that involve larger points are redone on top of it.
-    if (__any(emax > kWideTableTol)) square_block(Wp, s, mm, D, V, vs);
-    // row j = lane: N'_j = sum_{i <= j} T[j][i] N_i
-    double acc = 0.0;
-    if (lane < Wp) {
-        const int j = lane;
-        const double mj = fmax(1.0, x);
-        double Rp = 1.0;  // prod_{k=i}^{j-1} min(x_k, 1)
-        double lb = 0.0;  // log of prod_{k=i}^{j-1} x_k / (j-i)!, which bounds T[j][i] (g <= 1/n!)
-        int A = pos[j], B = A;
-        for (int i = j; i >= 0; --i) {
-            const int pi = pos[i];
-            if (i < j) {
-                const double xi = s[pi];
-                Rp *= fmin(xi, 1.0);
-                if (Rp == 0.0) break;  // every lower source reaches row j through a zero rate
-                lb += ls[pi] - kLogFact.v[j - i] + kLogFact.v[j - i - 1];  // log x_i - log (j-i)
-            }
-            A = min(A, pi);
-            B = max(B, pi);
-            const double Ni = Nb[i];
-            // a source whose contribution is below 1e-30 is skipped (every
-            // skipped term is bounded by N_i prod x / (j-i)!)
-            if (Ni == 0.0 || fmin(lb, 0.0) + log(fabs(Ni)) < kWideNegligibleLog) continue;
-            const int holes = (B - A + 1) - (j - i + 1);
-            double G;
-            if (holes == 0) {
-                G = D[tri(A, B)];
-            } else {
-                for (int t = 0; t <= holes; ++t) V[t * vs + lane] = D[tri(A + t, B)];
-                int cnt = holes;
-                for (int q = B; q > A && cnt > 0; --q) {
-                    const int ci = cid[q];
-                    if (ci >= i && ci <= j) continue;
-                    --cnt;
-                    const double rh = 1.0 / mm[q];
-                    const double sq = s[q];
-                    double cur = V[lane];
-                    for (int t = 0; t <= cnt; ++t) {
-                        const double nxt = V[(t + 1) * vs + lane];
-                        V[t * vs + lane] = fma(nxt, mm[A + t + 1], (sq - s[A + t]) * cur) * rh;
-                        cur = nxt;
-                    }
-                }
-                G = V[lane];
-            }
-            acc = fma(Rp * (mm[A] / mj) * G, Ni, acc);
+    // When an entry's bound exceeds kWideTableTol: without POSTERIOR the
+    // table is squared before the rows are taken; with it the rows are taken
+    // first, with a bound on their rounding from the entries' bounds weighted
+    // by what each term contributes (all rows together, which also bounds the
+    // top slot), and the table is squared and the rows taken again only when
+    // that bound exceeds kWideTableTol.  POSTERIOR pays off where the entries
+    // with large bounds carry negligible terms (a full chain, most of whose
+    // levels hold almost nothing); where they matter (a window just wide
+    // enough for its populations) it costs one more pass over the rows.
+    const bool suspect = __any(emax > kWideTableTol) || __any(cancelled);
+    if (suspect && !POSTERIOR) square_block(Wp, s, mm, D, V, vs);
+    // log |N_i| once per source, in the squaring's scratch after the columns
+    // (rewritten after a squaring, which uses that scratch)
+    double *lNb = V + (size_t)(vs - 1) * vs;
+    if (lane <= Wp) lNb[lane] = Nk != 0.0 ? log(fabs(Nk)) : -INFINITY;
+    wave_sync();
+    double err;
+    double acc = chain_rows<POSTERIOR>(Wp, x, s, mm, Nb, cid, pos, ls, lNb, D, Et, V, vs, err);
+    if (suspect && POSTERIOR) {
+        const double errsum = wave_sum(lane < Wp ? err : 0.0);
+        if (!(errsum <= kWideTableTol) || __any(cancelled)) {
+            wave_sync();
+            square_block(Wp, s, mm, D, V, vs);
+            if (lane <= Wp) lNb[lane] = Nk != 0.0 ? log(fabs(Nk)) : -INFINITY;
+            wave_sync();
+            acc = chain_rows<false>(Wp, x, s, mm, Nb, cid, pos, ls, lNb, D, Et, V, vs, err);
         }
     }
     // the top slot keeps what the rows leave (columns of T sum to one)
@@ -348,10 +443,11 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
 // Doubles of one wavefront's LDS region for width W: s, e, mm, Nb, cid and
 // pos, log rates (384), the triangular table, the per-lane columns
 // ((W - 1) W >= 2 (W + 1), which also holds the scratch of the reach test
-// and of the squaring), and the scaled points of the squaring (192).
-constexpr size_t wide_wave_doubles(int W)
+// and of the squaring), the scaled points of the squaring (192), and, for
+// chain_sub<true>, the entries' error bounds (float, triangular).
+constexpr size_t wide_wave_doubles(int W, bool bounds)
 {
-    return 384 + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * W + 192;
+    return 384 + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * W + 192 + (bounds ? ((size_t)W * (W + 1) / 2 + 1) / 2 : 0);
 }
 
 }  // namespace
