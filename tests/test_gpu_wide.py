@@ -256,3 +256,45 @@ def test_clustered_tables_match_oracle(env, orc, prec, w, hi):
     err = check(out, ref, prec, f"clustered w={w} hi={hi} {prec}")
     print(f"max |dN| {err:.2e}")
     assert np.allclose(out.sum(axis=0), pops.astype(np.float64).sum(axis=0), atol=TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("state", ["neutral", "spread"])
+def test_full_chain_of_a_gas_with_clustered_rates(env, orc, prec, state):
+    """ionize_step's full chain (w = Z = 36, no shift) on a gas whose
+    potentials rise by only 10 % per level (30 eV x 1.1^k, s electrons), at
+    fields of 8,000 to 30,000 GV/m: a dozen of its rates fall within a few
+    per step of each other, the sorted divided-difference table's error
+    bound exceeds 1e-13, and the full-chain path decides by the rows'
+    weighted bound whether to recompute the table by scaling and squaring.
+    Against the oracle's binary128 exponential, from neutral cells and from
+    populations spread over every level."""
+    torch, ak, _ = env
+    Z = 36
+    U = 30.0 * 1.1 ** np.arange(Z)
+    l = np.zeros(Z, np.int8)
+    m = np.zeros(Z, np.int8)
+    gas = ak.Gas(U, l, m)
+    spec = orc.GasSpec(U, l, m)
+    n = 640 + 17
+    rng = np.random.default_rng(4242 if state == "neutral" else 4343)
+    E = np.exp(rng.uniform(np.log(8000.0), np.log(30000.0), n))
+    E[::7] *= -1.0
+    pops = np.zeros((Z + 1, n))
+    if state == "neutral":
+        pops[0] = 1.0
+    else:
+        pops = rng.random((Z + 1, n))
+        pops[rng.random((Z + 1, n)) < 0.3] = 0.0
+        pops[0] += 1e-3
+        pops /= pops.sum(axis=0)
+    pops = pops.astype(npdt(prec))
+    lo = np.zeros(n, np.uint8)
+    out, l2 = run(torch, ak, gas, E.astype(npdt(prec)), pops, lo, Z, 0.0, "full")
+    ref, rlo = orc.ionize_step(spec, E.astype(npdt(prec)).astype(np.float64), DT, pops.astype(np.float64), lo, Z,
+                               0.0, layout=1)
+    assert np.array_equal(l2, rlo)
+    err = check(out, ref, prec, f"clustered gas full chain {state} {prec}")
+    print(f"max |dN| {err:.2e}")
+    assert np.allclose(out.sum(axis=0), pops.astype(np.float64).sum(axis=0), atol=TOL[prec])
+    gas.close()
