@@ -302,20 +302,20 @@ __device__ __forceinline__ void load_bias(MlpBias &b, const MlpShared &s, int la
     }
 }
 
-// NG independent groups through the same weights, interleaved stage by
-// stage so that each stage has NG times the independent matrix-core and
-// vector work in flight (inference, v folded into the table).  Group q
-// takes its samples' table rows crow[q] and features u[q]; its logits land
-// in z[q] as in mlp_logits.
-template <int NG>
-__device__ __forceinline__ void mlp_logits_xn(const MlpRegs &r, const MlpBias &bs, const float *sf,
-                                              const float *const (&crow)[NG], const float (&u)[NG], int qo,
-                                              f32x4 (&z)[NG])
+// One group of 16 samples through the network (inference, v folded into the
+// table): lane (g, n) supplies sample n's layer-1 table row crow and feature
+// u.  The output weights fill every row block of their operand (row m holds
+// logit m & 3), so every lane group receives the group's logits; lanes
+// (qo, n) keep them in z, the other lanes keep what z held.  After four
+// groups with qo = 0..3, lane (g, n) holds the logits of sample n of group g
+// and one softmax serves 64 samples.
+__device__ __forceinline__ void mlp_logits_into(const MlpRegs &r, const MlpBias &bs, const float *sf,
+                                                const float *crow, float u, int qo, f32x4 &z)
 {
     const int g = (threadIdx.x & 63) >> 4;
     // sf: MlpShared::b2 (followed by b3, b4, wu), for what is not in bs
     const float *sb2 = sf, *sb3 = sf + kH, *sb4 = sf + 2 * kH, *swu = sb4 + 16;
-    bf16x8 h[NG][2];
+    bf16x8 h[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         f32x4 w0, w1;
@@ -326,65 +326,36 @@ __device__ __forceinline__ void mlp_logits_xn(const MlpRegs &r, const MlpBias &b
             w0 = lds4(swu + hid(c, g, 0));
             w1 = lds4(swu + hid(c, g, 4));
         }
-#pragma unroll
-        for (int q = 0; q < NG; ++q) {
-            const f32x4 a0 = lds4(crow[q] + hid(c, g, 0)), a1 = lds4(crow[q] + hid(c, g, 4));
-            const u32x4 wq = {pack2(fmaf(w0[0], u[q], a0[0]), fmaf(w0[1], u[q], a0[1])),
-                              pack2(fmaf(w0[2], u[q], a0[2]), fmaf(w0[3], u[q], a0[3])),
-                              pack2(fmaf(w1[0], u[q], a1[0]), fmaf(w1[1], u[q], a1[1])),
-                              pack2(fmaf(w1[2], u[q], a1[2]), fmaf(w1[3], u[q], a1[3]))};
-            h[q][c] = relu_bf16(wq);
-        }
+        const f32x4 a0 = lds4(crow + hid(c, g, 0)), a1 = lds4(crow + hid(c, g, 4));
+        const u32x4 wq = {pack2(fmaf(w0[0], u, a0[0]), fmaf(w0[1], u, a0[1])),
+                          pack2(fmaf(w0[2], u, a0[2]), fmaf(w0[3], u, a0[3])),
+                          pack2(fmaf(w1[0], u, a1[0]), fmaf(w1[1], u, a1[1])),
+                          pack2(fmaf(w1[2], u, a1[2]), fmaf(w1[3], u, a1[3]))};
+        h[c] = relu_bf16(wq);
     }
-    f32x4 acc[NG][4];
+    f32x4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f32x4 bb;
-        if constexpr (kBiasRegs >= 2) bb = bs.b2[t];
-        else bb = lds4(sb2 + 16 * t + 4 * g);
+        if constexpr (kBiasRegs >= 2) acc[t] = bs.b2[t];
+        else acc[t] = lds4(sb2 + 16 * t + 4 * g);
 #pragma unroll
-        for (int q = 0; q < NG; ++q) acc[q][t] = bb;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int q = 0; q < NG; ++q)
-                acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], h[q][c], acc[q][t], 0, 0, 0);
+        for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], h[c], acc[t], 0, 0, 0);
     }
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int q = 0; q < NG; ++q) h[q][c] = relu_pack(acc[q][2 * c], acc[q][2 * c + 1]);
+    for (int c = 0; c < 2; ++c) h[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f32x4 bb;
-        if constexpr (kBiasRegs >= 2) bb = bs.b3[t];
-        else bb = lds4(sb3 + 16 * t + 4 * g);
+        if constexpr (kBiasRegs >= 2) acc[t] = bs.b3[t];
+        else acc[t] = lds4(sb3 + 16 * t + 4 * g);
 #pragma unroll
-        for (int q = 0; q < NG; ++q) acc[q][t] = bb;
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int q = 0; q < NG; ++q)
-                acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], h[q][c], acc[q][t], 0, 0, 0);
+        for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], h[c], acc[t], 0, 0, 0);
     }
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 2; ++c) h[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);
+    f32x4 zq = lds4(sb4);
 #pragma unroll
-        for (int q = 0; q < NG; ++q) h[q][c] = relu_pack(acc[q][2 * c], acc[q][2 * c + 1]);
-    const bool rows_q = ((threadIdx.x & 15) >> 2) == qo;
-#pragma unroll
-    for (int q = 0; q < NG; ++q) {
-        f32x4 b4v;
-        if constexpr (kBiasRegs >= 1) b4v = bs.b4;
-        else b4v = lds4(sb4);
-        z[q] = g == qo ? b4v : (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-    }
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const bf16x8 a4 = rows_q ? r.A4[c] : (bf16x8){};
-#pragma unroll
-        for (int q = 0; q < NG; ++q) z[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a4, h[q][c], z[q], 0, 0, 0);
-    }
+    for (int c = 0; c < 2; ++c) zq = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A4[c], h[c], zq, 0, 0, 0);
+    if (g == qo) z = zq;
 }
 
 

@@ -26,11 +26,11 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kSurBlock = kBlock;
-constexpr int kSurWaves = kSurBlock / 64;
-// One 16-sample group per network pass: interleaving 2 groups measured 2 %
-// slower and 3 or 4 (two wavefronts per SIMD) 10 % slower on the 3D pulse.
-constexpr int kSurGroups = 1;
+// One workgroup per CU: 12 wavefronts (three per SIMD, what the register
+// file holds at this kernel's register count) share one chunk counter.
+// Against workgroups of 4 wavefronts, the 3D pulse step measured 711 -> 671 us.
+constexpr int kSurWaves = 12;
+constexpr int kSurBlock = 64 * kSurWaves;
 
 // Dynamic LDS: the layer-1 table ctab[Z][kCtabStride], then per wavefront
 // 64 W slots of 16 bytes: the (cell, source) pairs that need the network
@@ -50,6 +50,7 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
     __shared__ MlpShared ms;
     __shared__ float sthr[ADK_MAX_Z];
     __shared__ float scut[ADK_MAX_Z + 1];
+    __shared__ unsigned next_chunk;
     extern __shared__ __align__(16) unsigned char dyn[];
     const int Z = a.st.Z;
     const int lane = threadIdx.x & 63;
@@ -57,33 +58,80 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
     // a group reads its pairs before it writes their columns into the same
     // slots, and no other group touches them
     f32x4 *slot = (f32x4 *)(dyn + (size_t)Z * kCtabStride * sizeof(float)) + (threadIdx.x >> 6) * 64 * W;
+    if (threadIdx.x == 0) next_chunk = 0u;  // visible after staging
     for (int t = threadIdx.x; t < Z; t += blockDim.x) sthr[t] = a.thr[t];
     for (int t = threadIdx.x; t <= ADK_MAX_Z; t += blockDim.x) scut[t] = a.cut.e[t];  // visible after staging
     stage_coefficients(sc, a.st.tab, a.st.ln_dt);
     stage_mlp(ms, ctab, a.prm, a.L, a.v, true);
     const double *slog = sc + kCoefRows * kCoefStride;
     const bool has_poly = a.st.has_poly != 0;
-    const int64_t wave = ((int64_t)blockIdx.x * kSurBlock + threadIdx.x) >> 6;
-    const int64_t nwaves = (int64_t)gridDim.x * kSurWaves;
     const unsigned long long below = (1ull << lane) - 1ull;  // lanes under this one
     unsigned long long n_fb = 0, n_eval = 0;
 
-    // wavefront-uniform loop: every lane stays active for the matrix ops
+    // Workgroup b owns the chunk indices [b per, (b + 1) per) (scattered over
+    // the mesh by ChunkOrder), and its wavefronts take them one at a time
+    // from a counter in LDS: a chunk's cost depends on how many of its cells
+    // the pulse has reached, and a fixed share per wavefront would leave the
+    // launch waiting for the wavefronts that drew the most of them.  A cell's
+    // result does not depend on which wavefront takes it.
+    //
+    // Wavefront-uniform loop: every lane stays active for the matrix ops.
+    // The next chunk's cells are loaded while this one is worked on (the
+    // network and the column sums hide their HBM latency), and handed over
+    // to the loop's working registers before this chunk's stores: the
+    // vector-memory counter retires loads and stores in the order they were
+    // issued, so a wait for the loads after the stores (at the top of the
+    // next iteration) would also wait for the stores.
     const int64_t nchunks = (n + 63) / 64;
-    for (int64_t v = wave; v < nchunks; v += nwaves) {
-        const int64_t c = chunk_place(v, ord) * 64 + lane;
+    const int64_t per = (nchunks + gridDim.x - 1) / gridDim.x;
+    const int64_t vb = (int64_t)blockIdx.x * per;
+    const int64_t ve = vb + per < nchunks ? vb + per : nchunks;
+    auto take = [&]() -> int64_t {
+        unsigned t = 0u;
+        if (lane == 0) t = atomicAdd(&next_chunk, 1u);
+        return vb + (int64_t)__builtin_amdgcn_readfirstlane(t);
+    };
+    // the network's weight operands stay in registers for the whole loop
+    // (loading them per chunk measured 17 % of the wavefronts' time)
+    MlpRegs r;
+    load_regs(r, ms, lane);
+    MlpBias bs;
+    if constexpr (kBiasRegs > 0) load_bias(bs, ms, lane);
+    int64_t vt = take();
+    int64_t cn = vt < ve ? chunk_place(vt, ord) * 64 + lane : n;
+    // lanes past the end load the last cell (any in-bounds address) and
+    // drop it at the hand-over; n > 0 whenever the loop runs
+    CellLoad<float, W> nxt;
+    if (n > 0) load_cell(nxt, E, pops, lo, n, cn < n ? cn : n - 1);
+    int64_t ch;  // the handed-over chunk: its cells, field and window bottom
+    float Eh, Nh[W + 1];
+    int loh;
+    auto handover = [&]() __attribute__((always_inline)) {
+        const bool ok = cn < n;
+        ch = cn;
+        Eh = ok ? nxt.E : 0.0f;
+#pragma unroll
+        for (int s = 0; s <= W; ++s) Nh[s] = ok ? nxt.N[s] : 0.0f;
+        loh = ok ? (int)nxt.lo : Z;
+        // the values pass through an empty asm statement, so that they count
+        // as computed here (after the wait for the loads) and the stores that
+        // follow stay after it
+        asm volatile("" : "+v"(Eh), "+v"(loh)::"memory");
+#pragma unroll
+        for (int s = 0; s <= W; ++s) asm volatile("" : "+v"(Nh[s])::"memory");
+    };
+    handover();
+    while (vt < ve) {
+        const int64_t c = ch;
         const bool valid = c < n;
-        float Ef = 0.0f;
+        const float Ef = Eh;
         float Nf[W + 1];
-        int lo0 = Z;
 #pragma unroll
-        for (int s = 0; s <= W; ++s) Nf[s] = 0.0f;
-        if (valid) {
-            Ef = E[c];
-#pragma unroll
-            for (int s = 0; s <= W; ++s) Nf[s] = pops[(int64_t)s * n + c];
-            lo0 = lo[c];
-        }
+        for (int s = 0; s <= W; ++s) Nf[s] = Nh[s];
+        const int lo0 = loh;
+        vt = take();
+        cn = vt < ve ? chunk_place(vt, ord) * 64 + lane : n;
+        load_cell(nxt, E, pops, lo, n, cn < n ? cn : n - 1);
         int p = lo0 < Z ? lo0 : Z;
         const double EL = fabs((double)Ef);
         // a cell under its window's identity field (every rate of the
@@ -93,6 +141,7 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
         // negligible, so the network's form is the identity too
         const bool idle = p >= Z || (EL < (double)scut[p] && (double)Nf[0] >= a.st.eps);
         if (__all(idle)) {
+            handover();
             if (valid && p != lo0) lo[c] = (uint8_t)p;  // windows unchanged in place
             continue;
         }
@@ -149,35 +198,23 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
             }
             wave_lds_sync();
             if (cnt > 0) {
-                // weight operands loaded per wavefront pass (not held across
-                // the analytic branch)
-                MlpRegs r;
-                load_regs(r, *(const MlpShared *)((const char *)&ms + opaque_zero()), lane);
-                MlpBias bs;
-                if constexpr (kBiasRegs > 0) load_bias(bs, *(const MlpShared *)((const char *)&ms + opaque_zero()), lane);
-                // kSurGroups groups of 16 at a time (independent work
-                // interleaved), then one more pass for the groups left; lanes
-                // past the count take a pair of their own pass (slots of
-                // earlier passes already hold columns); sample n of group q
-                // is candidate g0 + 16 q + n, and its logits land in lane n
-                for (int g0 = 0; g0 < cnt; g0 += 16 * kSurGroups) {
-                    const float *crow[kSurGroups];
-                    float uq[kSurGroups];
-#pragma unroll
-                    for (int q = 0; q < kSurGroups; ++q) {
-                        const int t = g0 + 16 * q + (lane & 15);
-                        const f32x4 cq = slot[t < cnt ? t : g0];
-                        crow[q] = ctab + __float_as_int(cq.y) * kCtabStride;
-                        uq[q] = cq.x;
-                    }
-                    f32x4 z[kSurGroups];
-                    mlp_logits_xn<kSurGroups>(r, bs, ms.b2 + opaque_zero(), crow, uq, 0, z);
-#pragma unroll
-                    for (int q = 0; q < kSurGroups; ++q) {
+                // 16 pairs per pass; four passes in a row add their logits
+                // into one tile (pass j's samples land in lane group j & 3),
+                // which then takes one softmax for 64 pairs.  Lanes past the
+                // count repeat the pass's first pair; slots of a block are
+                // read by its passes before the block's columns overwrite them
+                f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                for (int g0 = 0; g0 < cnt; g0 += 16) {
+                    const float *sf = ms.b2 + opaque_zero();  // biases read per pass, not held
+                    const int qo = (g0 >> 4) & 3;
+                    const int t = g0 + (lane & 15);
+                    const f32x4 cq = slot[t < cnt ? t : g0];
+                    mlp_logits_into(r, bs, sf, ctab + __float_as_int(cq.y) * kCtabStride, cq.x, qo, z);
+                    if (qo == 3 || g0 + 16 >= cnt) {
                         float zm, lse;
-                        const f32x4 Q = softmax4(z[q], zm, lse);
-                        const int t = g0 + 16 * q + (lane & 15);
-                        if (lane < 16 && t < cnt) slot[t] = Q;
+                        const f32x4 Q = softmax4(z, zm, lse);
+                        const int tb = (g0 & ~63) + lane;
+                        if (tb < cnt) slot[tb] = Q;
                     }
                 }
                 wave_lds_sync();
@@ -209,6 +246,7 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
 
         n_fb += (unsigned long long)__popcll(__ballot(use_an && EL >= a.st.E_cut));
 
+        handover();
         if (valid) {
             const bool finite = EL <= 1.7976931348623157e308 || p >= Z;
 #pragma unroll
