@@ -84,8 +84,15 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
     // next iteration) would also wait for the stores.
     const int64_t nchunks = (n + 63) / 64;
     const int64_t per = (nchunks + gridDim.x - 1) / gridDim.x;
-    const int64_t vb = (int64_t)blockIdx.x * per;
-    const int64_t ve = vb + per < nchunks ? vb + per : nchunks;
+    // uniform values, held in scalar registers (so is what is derived from
+    // them: the chunk's place under ChunkOrder is a scalar loop)
+    auto uniform = [](int64_t x) -> int64_t {
+        const uint32_t lo32 = __builtin_amdgcn_readfirstlane((uint32_t)x);
+        const uint32_t hi32 = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+        return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+    };
+    const int64_t vb = uniform((int64_t)blockIdx.x * per);
+    const int64_t ve = uniform(vb + per < nchunks ? vb + per : nchunks);
     auto take = [&]() -> int64_t {
         unsigned t = 0u;
         if (lane == 0) t = atomicAdd(&next_chunk, 1u);
