@@ -463,8 +463,9 @@ def adaptive_measure(ak, gas36, mesh, steps, eps, wmax=24, tol=1e-9, t0=200):
     3D mesh: widths 1..wmax per cell and step (leak tolerance tol per step),
     the pulse run in from neutral cells over steps 0..t0-1, then `steps`
     steps timed as one graph replay (HIP events); an untimed eager pass
-    counts window populations (wc + 1 per live cell) and the cells the
-    wavefront-per-cell tier solved."""
+    counts window populations (wc + 1 per live cell) and the cells the wide
+    tiers solved (16 lanes per cell, or a wavefront when its slots do not
+    fit)."""
     import torch
     n = mesh.ncells
     Z = 36
@@ -530,10 +531,10 @@ def adaptive_measure(ak, gas36, mesh, steps, eps, wmax=24, tol=1e-9, t0=200):
            "mean_width_live_cells": wsum / max(wlive, 1.0), "max_width": int(Wc.max()),
            "wide_tier_cells_per_step": wide_cells / steps, "held_by_wmax_timed_steps": held,
            "held_by_wmax_run_in": held_run_in,
-           "launches_per_step": 4}
+           "launches_per_step": 5}
     log(f"[adaptive] mixed, widths 1..{wmax}, tol {tol:g}: {ms * 1e3:.1f} us/step, {res['value']:.3e} cell-level/s, "
         f"mean width {res['mean_width_live_cells']:.2f} (max {res['max_width']}), {wide_cells / steps:.0f} "
-        f"cells/step on the wavefront tier, held by wmax: {held} (timed) {held_run_in} (run-in); widths "
+        f"cells/step on the wide tiers, held by wmax: {held} (timed) {held_run_in} (run-in); widths "
         f"{res['width_histogram_last_step']}")
     del fields, P, L, Wc, P0, L0, W0, work
     torch.cuda.empty_cache()

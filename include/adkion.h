@@ -194,7 +194,8 @@ int ionize_step_yield(const adk_gas *gas, const void *E, int64_t ncells, double 
  * With tol = 0 and wmax >= Z - lo the result is the full chain; with
  * wmin = wmax = w it is ionize_step with window w.  Cells whose window fits
  * three rates run one per lane in a sweep of the mesh, those that fit eight
- * one per lane over a list of them, wider ones one per wavefront (double
+ * one per lane over a list of them, wider ones on 16 lanes each (four cells
+ * per wavefront) while their slots fit, else one per wavefront (double
  * arithmetic), up to ADK_MAX_WIDE_W rates.
  */
 typedef struct {
@@ -207,8 +208,9 @@ typedef struct {
 
 /* Bytes of the device workspace ionize_step_adaptive needs for ncells cells
  * (a bit mask of the cells handed from the first to the second tier, a list
- * of those handed to the third, and its length):
- * 256 + 32 ceil(ncells / 256) + 4 ncells. */
+ * of those handed to the third, a list of those the third passes on to the
+ * fourth, and their lengths):
+ * 256 + 32 ceil(ncells / 256) + 8 ncells. */
 size_t adk_adaptive_work_bytes(int64_t ncells);
 
 /* One step with adaptive windows for ncells cells (compact layout):
@@ -220,13 +222,14 @@ size_t adk_adaptive_work_bytes(int64_t ncells);
  * is a device buffer of at least adk_adaptive_work_bytes(ncells) bytes that
  * the call uses as scratch (contents need no initialisation; calls sharing
  * one workspace must be ordered).  counters (device, 2 x uint64, may be
- * NULL) are incremented by: [0] cells solved one per wavefront (window wider
- * than eight rates), [1] cells whose top the storage limit wmax held back
- * with leak above tol.  A cell below the gas's field cutoff (every rate
+ * NULL) are incremented by: [0] cells listed for the wide tiers (window
+ * wider than eight rates), [1] cells whose top the storage limit wmax held
+ * back with leak above tol.  A cell below the gas's field cutoff (every rate
  * below 1e-30 per step) with no shift due keeps its populations when
- * tol >= 1e-30.  Four launches on stream (clear the list, lane-per-cell
- * sweep, lane-per-cell tier over the cells it marked, wavefront-per-cell
- * tier); allocates nothing and never synchronises.  Results do not depend
+ * tol >= 1e-30.  Five launches on stream (clear the lists, lane-per-cell
+ * sweep, lane-per-cell tier over the cells it marked, 16-lane tier over the
+ * cells that one listed, wavefront-per-cell tier over the cells the 16-lane
+ * tier passed on); allocates nothing and never synchronises.  Results do not depend
  * on timing: repeated calls on the same inputs agree bit for bit.
  * Errors: ADK_EINVAL (null gas/win, null arrays or work with ncells > 0,
  * ncells < 0, work_bytes too small, dt <= 0 or non-finite, eps < 0 or

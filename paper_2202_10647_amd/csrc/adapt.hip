@@ -29,12 +29,16 @@
 //     solution takes wavefront-wide shortcuts (weak rates, negligible
 //     entries, monotone rates), and a fixed grouping keeps every step
 //     reproducible bit for bit.  Cells wider still are listed (atomics) for
-//   * wide, one wavefront per listed cell: the wide path's sorted-table
-//     solution (chain_sub), up to ADK_MAX_WIDE_W rates; a cell's result does
-//     not depend on its place in the list.
-// A step is four launches on the stream: clear the list header, narrow,
-// middle, wide.  No allocation and no host synchronisation, so a step can
-// be captured in a HIP graph.
+//   * wide: the wide path's sorted-table solution (chain_sub), up to
+//     ADK_MAX_WIDE_W rates, first on 16 lanes per listed cell, four cells
+//     per wavefront (every vote, exchange and sum confined to the cell's
+//     lanes, a quarter of the LDS per cell, so more cells are in flight per
+//     CU); a cell whose slots do not fit 16 lanes is left untouched and
+//     listed again, for one wavefront each.  A cell's result does not depend
+//     on its place in either list, nor on the cells beside it.
+// A step is five launches on the stream: clear the list headers, narrow,
+// middle, groups of 16 lanes, wavefronts.  No allocation and no host
+// synchronisation, so a step can be captured in a HIP graph.
 #include "wide.hpp"
 
 namespace adk {
@@ -49,17 +53,20 @@ struct AdaptArgs {
 };
 
 struct AdaptHeader {
-    uint32_t count;  // cells listed for the wide tier
-    uint32_t pad[63];
+    uint32_t count;       // cells listed for the wide tier (groups of 16 lanes)
+    uint32_t count_wave;  // cells of that list passed on to one wavefront each
+    uint32_t pad[62];
 };
 
 // Workspace: the wide tier's list header, the narrow tier's mask (one word
 // per wavefront of the sweep: 4 per 256-cell chunk of the scattered order),
-// then the wide tier's list (ncells entries).
+// then the wide tier's list and the list of its cells passed on to one
+// wavefront each (ncells entries each).
 struct AdaptWork {
     AdaptHeader *hdr;
     unsigned long long *mask;
     int32_t *list;
+    int32_t *list_wave;
     int64_t nwords;
 };
 
@@ -72,12 +79,16 @@ __host__ __device__ inline AdaptWork adapt_work(void *work, int64_t n)
     w.mask = (unsigned long long *)(w.hdr + 1);
     w.nwords = adapt_mask_words(n);
     w.list = (int32_t *)(w.mask + w.nwords);
+    w.list_wave = w.list + n;
     return w;
 }
 
 __global__ void adaptive_clear_kernel(AdaptHeader *h)
 {
-    if (threadIdx.x == 0) h->count = 0u;
+    if (threadIdx.x == 0) {
+        h->count = 0u;
+        h->count_wave = 0u;
+    }
 }
 
 // Appends the lanes with go set to a list: one atomic per wavefront.  All
@@ -361,27 +372,39 @@ __global__ __launch_bounds__(kBlock) void adaptive_mid_kernel(StepArgs a, AdaptA
 
 // Wide tier: one wavefront per listed cell (double arithmetic).  LDS as the
 // wide ionize_step path (wide_wave_doubles) plus the leak scratch.
-template <class R>
-__device__ void adaptive_wide_cell(const StepArgs &a, const AdaptArgs &ad, int64_t c, const R *__restrict__ E,
-                                   R *__restrict__ pops, uint8_t *__restrict__ lo, uint8_t *__restrict__ wc,
-                                   int64_t n, double *s, double *e, double *mm, double *Nb, int *cid, int *pos,
-                                   double *D, double *V, double *lx, double *lN,
-                                   unsigned long long *__restrict__ counters)
+// One listed cell on G lanes (a wavefront, or a group of 16 of it): shift,
+// leak test, exact solve by chain_sub.  With G < 64 a cell whose slots do
+// not fit the group (its window already 16 rates or more, or its top above
+// slot 15) is left untouched and listed in list_wave (returns false).
+template <class R, int G>
+__device__ void adaptive_cell(const StepArgs &a, const AdaptArgs &ad, int64_t c, const R *__restrict__ E,
+                              R *__restrict__ pops, uint8_t *__restrict__ lo, uint8_t *__restrict__ wc, int64_t n,
+                              double *s, double *e, double *mm, double *Nb, int *cid, int *pos, double *D, double *V,
+                              int vs, double *lx, double *lN, AdaptHeader *__restrict__ hdr,
+                              int32_t *__restrict__ list_wave, unsigned long long *__restrict__ counters)
 {
-    const int lane = wide_lane();
+    using L = Lanes<G>;
+    const int lane = L::lane();
     const int Z = a.Z;
     const int wmax = ad.wmax;
+    auto pass_on = [&]() {
+        if (lane == 0) list_wave[atomicAdd(&hdr->count_wave, 1u)] = (int32_t)c;
+    };
     wave_sync();  // the previous cell's reads of LDS are done
     const double EL = fabs((double)E[c]);
     const int l0 = lo[c];
     int p = l0 < Z ? l0 : Z;
     const int w0 = wc[c];
     const int w_in = w0 < wmax ? w0 : wmax;
+    if (G < 64 && w_in >= G) {
+        pass_on();
+        return;
+    }
     double Ns = lane <= w_in ? (double)pops[(int64_t)lane * n + c] : 0.0;
     int w = w_in;
-    while (p < Z && __shfl(Ns, 0) < a.eps) {
-        const double up = __shfl_down(Ns, 1);
-        Ns = lane == 0 ? Ns + up : (lane < wmax ? up : 0.0);
+    while (p < Z && L::shfl(Ns, 0) < a.eps) {
+        const double up = L::down1(Ns);
+        Ns = lane == 0 ? Ns + up : (lane < wmax && lane < G - 1 ? up : 0.0);
         ++p;
         w = w > 0 ? w - 1 : 0;
     }
@@ -416,15 +439,21 @@ __device__ void adaptive_wide_cell(const StepArgs &a, const AdaptArgs &ad, int64
         }
         // top: the lowest slot t in [t0, room) with leak(t) <= tol (a NaN
         // leak widens), else room
-        const unsigned long long okm = __ballot(lane >= t0 && lane < room && leak <= ad.tol);
+        const unsigned long long okm = L::ballot(lane >= t0 && lane < room && leak <= ad.tol);
+        if (G < 64 && !okm && room >= G) {
+            // the top lies above the group's slots
+            wave_sync();
+            pass_on();
+            return;
+        }
         top = okm ? __ffsll((long long)okm) - 1 : room;
         // the storage limit held the top back
-        const bool held = !okm && room < Z - p && !(__shfl(leak, room) <= ad.tol);
+        const bool held = !okm && room < Z - p && !(L::shfl(leak, room) <= ad.tol);
         if (held && counters && lane == 0) atomicAdd(&counters[1], 1ull);
         wave_sync();
         if (top > 0 && finite) {
-            const double r = chain_sub<false>(top, lane < top ? x : 0.0, lane <= top ? Ns : 0.0, s, e, mm, Nb, cid, pos,
-                                              D, V, wmax);
+            const double r = chain_sub<false, G>(top, lane < top ? x : 0.0, lane <= top ? Ns : 0.0, s, e, mm, Nb,
+                                                 cid, pos, D, V, vs);
             if (lane <= top) out = r;
         }
     }
@@ -439,15 +468,55 @@ __device__ void adaptive_wide_cell(const StepArgs &a, const AdaptArgs &ad, int64
     }
 }
 
-constexpr size_t adaptive_wave_doubles(int W) { return wide_wave_doubles(W, false) + 128; }
+// LDS doubles of one cell of G lanes, windows up to W rates: chain_sub's
+// region and the leak test's logs (2 G).
+template <int G>
+constexpr size_t adaptive_cell_doubles(int W)
+{
+    return wide_cell_doubles<G>(W, false) + 2 * (size_t)G;
+}
 
+// Cells of the list, four per wavefront (16 lanes each); windows that need
+// 16 or more slots go on to list_wave.
+constexpr int kGroupLanes = 16;
+constexpr int kGroupsPerWave = 64 / kGroupLanes;
+
+template <class R>
+__global__ __launch_bounds__(kWideBlock) void adaptive_group_kernel(StepArgs a, AdaptArgs ad,
+                                                                    const R *__restrict__ E, R *__restrict__ pops,
+                                                                    uint8_t *__restrict__ lo,
+                                                                    uint8_t *__restrict__ wc, int64_t n,
+                                                                    AdaptHeader *__restrict__ hdr,
+                                                                    const int32_t *__restrict__ list,
+                                                                    int32_t *__restrict__ list_wave,
+                                                                    unsigned long long *__restrict__ counters)
+{
+    constexpr int G = kGroupLanes;
+    extern __shared__ __align__(16) double wl[];
+    const int grp = threadIdx.x / G;
+    double *base = wl + (size_t)grp * adaptive_cell_doubles<G>(G);
+    int *cid = (int *)(base + 4 * G);
+    int *pos = cid + G;
+    double *D = base + 6 * G;
+    double *V = D + G * (G + 1) / 2;
+    double *lx = base + wide_cell_doubles<G>(G, false);
+    double *lN = lx + G;
+    const uint32_t count = hdr->count;
+    for (uint32_t i = blockIdx.x * kGroupsPerWave + grp; i < count; i += gridDim.x * kGroupsPerWave) {
+        const int64_t c = list[i];
+        adaptive_cell<R, G>(a, ad, c, E, pops, lo, wc, n, base, base + G, base + 2 * G, base + 3 * G, cid, pos, D,
+                            V, G, lx, lN, hdr, list_wave, counters);
+    }
+}
+
+// Cells passed on by the groups, one per wavefront.
 template <class R>
 __global__ __launch_bounds__(kWideBlock) void adaptive_wide_kernel(StepArgs a, AdaptArgs ad,
                                                                    const R *__restrict__ E, R *__restrict__ pops,
                                                                    uint8_t *__restrict__ lo,
                                                                    uint8_t *__restrict__ wc, int64_t n,
-                                                                   const AdaptHeader *__restrict__ hdr,
-                                                                   const int32_t *__restrict__ list,
+                                                                   AdaptHeader *__restrict__ hdr,
+                                                                   const int32_t *__restrict__ list_wave,
                                                                    unsigned long long *__restrict__ counters)
 {
     extern __shared__ __align__(16) double wl[];
@@ -458,11 +527,11 @@ __global__ __launch_bounds__(kWideBlock) void adaptive_wide_kernel(StepArgs a, A
     double *V = D + W * (W + 1) / 2;
     double *lx = wl + wide_wave_doubles(W, false);
     double *lN = lx + 64;
-    const uint32_t count = hdr->count;
+    const uint32_t count = hdr->count_wave;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-        const int64_t c = list[i];
-        adaptive_wide_cell<R>(a, ad, c, E, pops, lo, wc, n, wl, wl + 64, wl + 128, wl + 192, cid, pos, D, V, lx,
-                              lN, counters);
+        const int64_t c = list_wave[i];
+        adaptive_cell<R, 64>(a, ad, c, E, pops, lo, wc, n, wl, wl + 64, wl + 128, wl + 192, cid, pos, D, V, W, lx,
+                             lN, hdr, nullptr, counters);
     }
 }
 
@@ -495,7 +564,28 @@ hipError_t launch_adaptive(const adk_gas *g, const void *E, int64_t n, double dt
                        counters);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t dyn = sizeof(double) * adaptive_wave_doubles(ad.wmax);
+    // groups of 16 lanes over the list: the resident workgroups (one
+    // wavefront each, LDS bound)
+    {
+        const size_t gdyn = sizeof(double) * kGroupsPerWave * adaptive_cell_doubles<kGroupLanes>(kGroupLanes);
+        static int gper_cu = 0;
+        if (gper_cu <= 0) {
+            int b = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, adaptive_group_kernel<R>, kWideBlock, gdyn) !=
+                    hipSuccess ||
+                b <= 0)
+                b = 1;
+            gper_cu = b;
+        }
+        const int64_t need = (n + kWideBlock - 1) / kWideBlock;
+        const int64_t cap = (int64_t)num_cus() * gper_cu;
+        const int ggrid = (int)(need < cap ? need : cap);
+        hipLaunchKernelGGL(adaptive_group_kernel<R>, dim3(ggrid), dim3(kWideBlock), gdyn, st, a, ad, (const R *)E,
+                           (R *)pops, lo, wc, n, wk.hdr, (const int32_t *)wk.list, wk.list_wave, counters);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const size_t dyn = sizeof(double) * adaptive_cell_doubles<64>(ad.wmax);
     static int per_cu[ADK_MAX_WIDE_W + 1] = {};  // occupancy per widest window (LDS grows with it)
     int b = per_cu[ad.wmax];
     if (b <= 0) {
@@ -509,7 +599,7 @@ hipError_t launch_adaptive(const adk_gas *g, const void *E, int64_t n, double dt
     const int64_t cap = (int64_t)num_cus() * b;
     const int wgrid = (int)(need < cap ? need : cap);
     hipLaunchKernelGGL(adaptive_wide_kernel<R>, dim3(wgrid), dim3(kWideBlock), dyn, st, a, ad, (const R *)E,
-                       (R *)pops, lo, wc, n, (const AdaptHeader *)wk.hdr, (const int32_t *)wk.list, counters);
+                       (R *)pops, lo, wc, n, wk.hdr, (const int32_t *)wk.list_wave, counters);
     return hipGetLastError();
 }
 
@@ -520,7 +610,7 @@ size_t adk_adaptive_work_bytes_impl(int64_t ncells)
 {
     const int64_t n = ncells > 0 ? ncells : 0;
     return sizeof(adk::AdaptHeader) + sizeof(unsigned long long) * (size_t)adk::adapt_mask_words(n) +
-           sizeof(int32_t) * (size_t)n;
+           2 * sizeof(int32_t) * (size_t)n;
 }
 
 hipError_t adk_step_adaptive(const adk_gas *g, const void *E, int64_t n, double dt, void *pops, uint8_t *lo,

@@ -44,6 +44,41 @@ constexpr int kWideBlock = 64;  // one wavefront per workgroup
 
 __device__ __forceinline__ int wide_lane() { return threadIdx.x; }
 
+// A cell's lanes: the whole wavefront (G = 64) or an aligned group of G
+// lanes of it (the adaptive window's groups of 16, four cells per
+// wavefront).  Votes, sums and exchanges stay within the group, so a cell's
+// result does not depend on the cells beside it.
+template <int G>
+struct Lanes {
+    static_assert(G == 16 || G == 32 || G == 64, "a cell's lanes are 16, 32 or 64");
+    // (a whole-wavefront cell runs in a one-wavefront workgroup)
+    static __device__ __forceinline__ int lane() { return G == 64 ? (int)threadIdx.x : (int)(threadIdx.x & (G - 1)); }
+    static __device__ __forceinline__ unsigned long long ballot(bool p)
+    {
+        const unsigned long long b = __ballot(p);
+        if constexpr (G == 64) return b;
+        else return (b >> (threadIdx.x & 63 & ~(G - 1))) & ((1ull << G) - 1ull);
+    }
+    static __device__ __forceinline__ bool any(bool p) { return ballot(p) != 0ull; }
+    template <class T>
+    static __device__ __forceinline__ T shfl(T v, int k)  // lane k of the group, 0 <= k < G
+    {
+        if constexpr (G == 64) return __shfl(v, k);
+        else return __shfl(v, k, G);
+    }
+    template <class T>
+    static __device__ __forceinline__ T down1(T v)  // the next lane's value (own value in the last lane)
+    {
+        if constexpr (G == 64) return __shfl_down(v, 1);
+        else return __shfl_down(v, 1, G);
+    }
+    static __device__ __forceinline__ double sum(double v)
+    {
+        static_for<0, (G == 64 ? 6 : (G == 32 ? 5 : 4))>([&](auto kk) { v += __shfl_xor(v, 1 << decltype(kk)::value); });
+        return v;
+    }
+};
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -197,16 +232,17 @@ constexpr double kSquareMax = 1024.0;                 // points squared: s <= kS
 // scaling and squaring (see chain_sub), then the entries with larger points
 // again by the Newton / series rule on top of them.  LDS: D (table), V
 // (scratch of (vs - 1) vs doubles), and 192 doubles after V for the scaled
-// points.  All 64 lanes call it.
+// points.  All G lanes of the cell call it.
+template <int G>
 __device__ void square_block(int Wp, const double *s, const double *mm, double *D, double *V, int vs)
 {
-    const int lane = wide_lane();
-    const int r = __popcll(__ballot(lane < Wp && s[lane] <= kSquareMax));  // sorted ascending
+    const int lane = Lanes<G>::lane();
+    const int r = __popcll(Lanes<G>::ballot(lane < Wp && s[lane] <= kSquareMax));  // sorted ascending
     if (r < 2) return;
     const double smax = s[r - 1];
     int j = 0;
     while (j < 10 && ldexp(1.0, j) < smax) ++j;
-    double *ss = V + (size_t)(vs - 1) * vs, *ee = ss + 64, *ms = ee + 64;
+    double *ss = V + (size_t)(vs - 1) * vs, *ee = ss + G, *ms = ee + G;
     if (lane < r) {
         ss[lane] = ldexp(s[lane], -j);
         ee[lane] = exp(-ss[lane]);
@@ -221,7 +257,7 @@ __device__ void square_block(int Wp, const double *s, const double *mm, double *
     const int nent = r * (r + 1) / 2;  // entries [a][b], b < r: the first nent of the table
     double *src = D, *dst = V;
     for (int it = 0; it < j; ++it) {
-        for (int t = lane; t < nent; t += 64) {
+        for (int t = lane; t < nent; t += G) {
             int b = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
             while (b * (b + 1) / 2 > t) --b;
             while ((b + 1) * (b + 2) / 2 <= t) ++b;
@@ -236,7 +272,7 @@ __device__ void square_block(int Wp, const double *s, const double *mm, double *
         dst = tmp;
     }
     if (src != D) {
-        for (int t = lane; t < nent; t += 64) D[t] = src[t];
+        for (int t = lane; t < nent; t += G) D[t] = src[t];
         wave_sync();
     }
     if (r < Wp) {
@@ -253,23 +289,17 @@ __device__ void square_block(int Wp, const double *s, const double *mm, double *
     }
 }
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-    static_for<0, 6>([&](auto kk) { v += __shfl_xor(v, 1 << decltype(kk)::value); });
-    return v;
-}
-
 // Row j = lane of the update, N'_j = sum_{i <= j} T[j][i] N_i (lanes below
 // Wp), and in err a bound on its absolute rounding error from the table
 // entries' relative bounds Et: the hole recurrence combines non-negative
 // terms, so a term's relative error is at most the largest of its entries'
 // plus the recurrence's own rounding.
-template <bool ERR>
+template <bool ERR, int G>
 __device__ __forceinline__ double chain_rows(int Wp, double x, const double *s, const double *mm, const double *Nb,
                                              const int *cid, const int *pos, const double *ls, const double *lNb,
                                              const double *D, const float *Et, double *V, int vs, double &err)
 {
-    const int lane = wide_lane();
+    const int lane = Lanes<G>::lane();
     double acc = 0.0;
     err = 0.0;
     if (lane < Wp) {
@@ -293,9 +323,9 @@ __device__ __forceinline__ double chain_rows(int Wp, double x, const double *s, 
             // skipped term is bounded by N_i prod x / (j-i)!)
             if (Ni == 0.0 || fmin(lb, 0.0) + lNb[i] < kWideNegligibleLog) continue;
             const int holes = (B - A + 1) - (j - i + 1);
-            double G, eG = 0.0;
+            double gS, eG = 0.0;
             if (holes == 0) {
-                G = D[tri(A, B)];
+                gS = D[tri(A, B)];
                 if constexpr (ERR) eG = (double)Et[tri(A, B)];
             } else {
                 for (int t = 0; t <= holes; ++t) {
@@ -317,9 +347,9 @@ __device__ __forceinline__ double chain_rows(int Wp, double x, const double *s, 
                         cur = nxt;
                     }
                 }
-                G = V[lane];
+                gS = V[lane];
             }
-            const double term = Rp * (mm[A] / mj) * G * Ni;
+            const double term = Rp * (mm[A] / mj) * gS * Ni;
             acc += term;
             if constexpr (ERR) err = fma(fabs(term), eG + 8.0 * kWideUlp, err);
         }
@@ -328,19 +358,20 @@ __device__ __forceinline__ double chain_rows(int Wp, double x, const double *s, 
 }
 
 // The exact update of a window of Wp rates held one per lane (x_k in lane k
-// for k < Wp, N_k in lane k for k <= Wp; zero elsewhere): returns N'_k in
-// lane k.  All 64 lanes call it together.  V: per-lane columns of the hole
+// for k < Wp, N_k in lane k for k <= Wp; zero elsewhere; lanes counted
+// within the cell's G lanes, Wp < G): returns N'_k in lane k.  All G lanes
+// of the cell call it together.  V: per-lane columns of the hole
 // recurrence, entry t of lane k at V[t vs + k] (vs >= Wp, t <= Wp - 2).
-template <bool POSTERIOR>
+template <bool POSTERIOR, int G = 64>
 __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, double *mm, double *Nb, int *cid,
                             int *pos, double *D, double *V, int vs)
 {
-    double *ls = (double *)(pos + 64);  // log of the sorted rates
-    const int lane = wide_lane();
+    double *ls = (double *)(pos + G);  // log of the sorted rates
+    const int lane = Lanes<G>::lane();
     // rank of x_k among the window's rates (ties by chain index)
     int rank = 0;
     for (int k = 0; k < Wp; ++k) {
-        const double xk = __shfl(x, k);
+        const double xk = Lanes<G>::shfl(x, k);
         rank += (xk < x || (xk == x && k < lane)) ? 1 : 0;
     }
     if (lane < Wp) {
@@ -356,7 +387,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
     // scaled Newton table of the sorted rates: the series for every entry
     // within kWideClusterSpread (one pass per row), then one order per step,
     // Newton where the spread reaches the order's threshold
-    float *Et = (float *)(V + (size_t)(vs - 1) * vs + 192);  // relative error bounds of the entries
+    float *Et = (float *)(V + (size_t)(vs - 1) * vs + 3 * G);  // relative error bounds of the entries
     if (lane < Wp) {
         D[tri(lane, lane)] = e[lane];
         if constexpr (POSTERIOR) Et[tri(lane, lane)] = (float)(4.0 * kWideUlp);
@@ -373,7 +404,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
     double eprev = 4.0 * kWideUlp, emax = 0.0;
     bool cancelled = false;  // an entry whose two terms cancelled exactly (its relative bound is void)
     for (int ord = 1; ord < Wp; ++ord) {
-        const double enb = __shfl_down(eprev, 1);
+        const double enb = Lanes<G>::down1(eprev);
         double ecur = eprev;
         if (lane < Wp - ord) {
             const int lo_ = lane, hi = lane + ord;
@@ -413,42 +444,45 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
     // with large bounds carry negligible terms (a full chain, most of whose
     // levels hold almost nothing); where they matter (a window just wide
     // enough for its populations) it costs one more pass over the rows.
-    const bool suspect = __any(emax > kWideTableTol) || __any(cancelled);
-    if (suspect && !POSTERIOR) square_block(Wp, s, mm, D, V, vs);
+    const bool suspect = Lanes<G>::any(emax > kWideTableTol) || Lanes<G>::any(cancelled);
+    if (suspect && !POSTERIOR) square_block<G>(Wp, s, mm, D, V, vs);
     // log |N_i| once per source, in the squaring's scratch after the columns
     // (rewritten after a squaring, which uses that scratch)
     double *lNb = V + (size_t)(vs - 1) * vs;
     if (lane <= Wp) lNb[lane] = Nk != 0.0 ? log(fabs(Nk)) : -INFINITY;
     wave_sync();
     double err;
-    double acc = chain_rows<POSTERIOR>(Wp, x, s, mm, Nb, cid, pos, ls, lNb, D, Et, V, vs, err);
+    double acc = chain_rows<POSTERIOR, G>(Wp, x, s, mm, Nb, cid, pos, ls, lNb, D, Et, V, vs, err);
     if (suspect && POSTERIOR) {
-        const double errsum = wave_sum(lane < Wp ? err : 0.0);
-        if (!(errsum <= kWideTableTol) || __any(cancelled)) {
+        const double errsum = Lanes<G>::sum(lane < Wp ? err : 0.0);
+        if (!(errsum <= kWideTableTol) || Lanes<G>::any(cancelled)) {
             wave_sync();
-            square_block(Wp, s, mm, D, V, vs);
+            square_block<G>(Wp, s, mm, D, V, vs);
             if (lane <= Wp) lNb[lane] = Nk != 0.0 ? log(fabs(Nk)) : -INFINITY;
             wave_sync();
-            acc = chain_rows<false>(Wp, x, s, mm, Nb, cid, pos, ls, lNb, D, Et, V, vs, err);
+            acc = chain_rows<false, G>(Wp, x, s, mm, Nb, cid, pos, ls, lNb, D, Et, V, vs, err);
         }
     }
     // the top slot keeps what the rows leave (columns of T sum to one)
-    const double total = wave_sum(lane <= Wp ? Nk : 0.0);
-    const double rows = wave_sum(lane < Wp ? acc : 0.0);
+    const double total = Lanes<G>::sum(lane <= Wp ? Nk : 0.0);
+    const double rows = Lanes<G>::sum(lane < Wp ? acc : 0.0);
     const double top = fmax(total - rows, 0.0);
     wave_sync();  // LDS reads done before the next use
     return lane < Wp ? acc : (lane == Wp ? top : 0.0);
 }
 
-// Doubles of one wavefront's LDS region for width W: s, e, mm, Nb, cid and
-// pos, log rates (384), the triangular table, the per-lane columns
+// Doubles of one cell's LDS region for width W and G lanes: s, e, mm, Nb,
+// cid and pos, log rates (6 G), the triangular table, the per-lane columns
 // ((W - 1) W >= 2 (W + 1), which also holds the scratch of the reach test
-// and of the squaring), the scaled points of the squaring (192), and, for
+// and of the squaring), the scaled points of the squaring (3 G), and, for
 // chain_sub<true>, the entries' error bounds (float, triangular).
-constexpr size_t wide_wave_doubles(int W, bool bounds)
+template <int G = 64>
+constexpr size_t wide_cell_doubles(int W, bool bounds)
 {
-    return 384 + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * W + 192 + (bounds ? ((size_t)W * (W + 1) / 2 + 1) / 2 : 0);
+    return 9 * (size_t)G + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * W +
+           (bounds ? ((size_t)W * (W + 1) / 2 + 1) / 2 : 0);
 }
+constexpr size_t wide_wave_doubles(int W, bool bounds) { return wide_cell_doubles<64>(W, bounds); }
 
 }  // namespace
 }  // namespace adk

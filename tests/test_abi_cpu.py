@@ -247,8 +247,8 @@ def test_adaptive_host_validation(L):
     """Workspace size and the host-side rejections of ionize_step_adaptive
     that need no gas on a device."""
     assert L.adk_adaptive_work_bytes(0) == 256
-    assert L.adk_adaptive_work_bytes(1000) == 256 + 32 * 4 + 4000
-    assert L.adk_adaptive_work_bytes(1024) == 256 + 32 * 4 + 4096
+    assert L.adk_adaptive_work_bytes(1000) == 256 + 32 * 4 + 8000
+    assert L.adk_adaptive_work_bytes(1024) == 256 + 32 * 4 + 8192
     win = adkion._Adaptive(1, 8, 1e-8, 1e-9, adkion.ADK_MIXED)
     E = adkion.ADK_EINVAL
     assert L.ionize_step_adaptive(None, None, 4, 1e-16, None, None, None, ctypes.byref(win), None, 0, None,
