@@ -422,19 +422,36 @@ __device__ void adaptive_cell(const StepArgs &a, const AdaptArgs &ad, int64_t c,
             row[0] += a.ln_dt * kLog2e;
             x = RateEval<PolicyF64>::x_of(row, f, a.has_poly != 0);
         }
-        // leak(t) of lane t, in the log domain (products of many capped
-        // rates leave the double range)
-        if (lane <= room) {
-            lx[lane] = log(x);
-            lN[lane] = Ns != 0.0 ? log(fabs(Ns)) : -INFINITY;
-        }
-        wave_sync();
+        // leak(t) of lane t: on a wavefront in the log domain (products of
+        // many capped rates leave the double range); within 16 slots the
+        // products of at most 16 rates (each at most kXMax) stay in range,
+        // and a running product takes the place of an exponential per term
         double leak = 0.0;
-        if (lane >= t0 && lane <= room) {
-            double path = 0.0;
-            for (int q = lane; q >= 0; --q) {
-                path += lx[q];
-                if (lN[q] > -INFINITY) leak += exp(lN[q] + path - kLogFact.v[lane - q + 1]);
+        if constexpr (G < 64) {
+            if (lane <= room) {
+                lx[lane] = x;
+                lN[lane] = fabs(Ns);
+            }
+            wave_sync();
+            if (lane >= t0 && lane <= room) {
+                double prod = 1.0;
+                for (int q = lane; q >= 0; --q) {
+                    prod *= lx[q];
+                    if (lN[q] != 0.0) leak = fma(lN[q] * prod, kInvFactL.v[lane - q + 1], leak);
+                }
+            }
+        } else {
+            if (lane <= room) {
+                lx[lane] = log(x);
+                lN[lane] = Ns != 0.0 ? log(fabs(Ns)) : -INFINITY;
+            }
+            wave_sync();
+            if (lane >= t0 && lane <= room) {
+                double path = 0.0;
+                for (int q = lane; q >= 0; --q) {
+                    path += lx[q];
+                    if (lN[q] > -INFINITY) leak += exp(lN[q] + path - kLogFact.v[lane - q + 1]);
+                }
             }
         }
         // top: the lowest slot t in [t0, room) with leak(t) <= tol (a NaN
