@@ -435,9 +435,10 @@ __device__ void adaptive_cell(const StepArgs &a, const AdaptArgs &ad, int64_t c,
             wave_sync();
             if (lane >= t0 && lane <= room) {
                 double prod = 1.0;
-                for (int q = lane; q >= 0; --q) {
+                for (int d = 0; d <= lane; ++d) {  // d = lane - q: uniform over the lanes in the loop
+                    const int q = lane - d;
                     prod *= lx[q];
-                    if (lN[q] != 0.0) leak = fma(lN[q] * prod, kInvFactL.v[lane - q + 1], leak);
+                    if (lN[q] != 0.0) leak = fma(lN[q] * prod, kInvFactL.v[d + 1], leak);
                 }
             }
         } else {
@@ -469,8 +470,9 @@ __device__ void adaptive_cell(const StepArgs &a, const AdaptArgs &ad, int64_t c,
         if (held && counters && lane == 0) atomicAdd(&counters[1], 1ull);
         wave_sync();
         if (top > 0 && finite) {
-            const double r = chain_sub<false, G>(top, lane < top ? x : 0.0, lane <= top ? Ns : 0.0, s, e, mm, Nb,
-                                                 cid, pos, D, V, vs);
+            const double r =
+                chain_sub<false, G>(top, lane < top ? x : 0.0, lane <= top ? Ns : 0.0, to_lds(s), to_lds(e), to_lds(mm),
+                                    to_lds(Nb), to_lds(cid), to_lds(pos), to_lds(D), to_lds(V), vs);
             if (lane <= top) out = r;
         }
     }

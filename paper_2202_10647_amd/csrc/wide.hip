@@ -80,8 +80,9 @@ __device__ void wide_cell(const StepArgs &a, int W, bool full, int64_t c,
             if (Wp > 0) {
                 const int src = lane + q_lo < 64 ? lane + q_lo : 63;
                 const double xs = __shfl(x, src), Nsub = __shfl(Ns, src);
-                const double r = chain_sub<true>(Wp, lane < Wp ? xs : 0.0, lane <= Wp ? Nsub : 0.0, s, e, mm, Nb,
-                                                 cid, pos, D, V, W);
+                const double r =
+                    chain_sub<true>(Wp, lane < Wp ? xs : 0.0, lane <= Wp ? Nsub : 0.0, to_lds(s), to_lds(e), to_lds(mm),
+                                    to_lds(Nb), to_lds(cid), to_lds(pos), to_lds(D), to_lds(V), W);
                 const double back = __shfl(r, lane - q_lo >= 0 ? lane - q_lo : 0);
                 if (lane >= q_lo && lane <= top) out = back;
             }
@@ -186,7 +187,8 @@ __global__ __launch_bounds__(kWideBlock) void wide_advance_kernel(int W, const R
             x = v < (double)kXMax<R> ? v : (v == v ? (double)kXMax<R> : v);
         }
         const double Nk = lane <= W ? (double)pops[(int64_t)lane * n + c] : 0.0;
-        const double r = chain_sub<false>(W, x, Nk, wl, wl + 64, wl + 128, wl + 192, cid, pos, D, V, W);
+        const double r = chain_sub<false>(W, x, Nk, to_lds(wl), to_lds(wl + 64), to_lds(wl + 128), to_lds(wl + 192),
+                                          to_lds(cid), to_lds(pos), to_lds(D), to_lds(V), W);
         if (lane <= W) pops[(int64_t)lane * n + c] = (R)r;
     }
 }

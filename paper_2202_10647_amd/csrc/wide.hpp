@@ -88,6 +88,21 @@ __device__ __forceinline__ void wave_sync()
 
 __device__ __forceinline__ int tri(int a, int b) { return b * (b + 1) / 2 + a; }
 
+// The solver's tables live in LDS.  Its functions are not inlined (they
+// would hold the caller's registers), so their pointers carry the LDS
+// address space: through plain (generic) pointers every table access would
+// be a flat memory instruction, on the vector memory path, instead of an
+// LDS one.
+#define ADK_LDS __attribute__((address_space(3)))
+using ldsd = ADK_LDS double;
+using ldsi = ADK_LDS int;
+using ldsf = ADK_LDS float;
+template <class T>
+__device__ __forceinline__ ADK_LDS T *to_lds(T *p)
+{
+    return (ADK_LDS T *)p;
+}
+
 // Newton below this spread for an entry of n + 1 points (FP64 accuracy; the
 // rounding of the recurrence grows ~ n / spread per order).
 __device__ __forceinline__ double wide_delta(int n)
@@ -152,8 +167,8 @@ constexpr double kWideClusterSpread = 2.0;  // largest spread any order's thresh
 // h_m(y_1..y_{k-1}) builds every k from the one below in the same sweep.
 // The partial sums accumulate in D[a][a+k] (written by this lane only), the
 // h values in this lane's column of hv; on return D holds ghat.
-__device__ void taylor_row(const double *s, const double *e, const double *mm, double *D, int a, int nmax,
-                           double *hv, int lane, int vs)
+__device__ void taylor_row(const ldsd *s, const ldsd *e, const ldsd *mm, ldsd *D, int a, int nmax, ldsd *hv,
+                           int lane, int vs)
 {
     const double sa = s[a];
     if (nmax <= kTaylorRegRow) {
@@ -234,7 +249,7 @@ constexpr double kSquareMax = 1024.0;                 // points squared: s <= kS
 // (scratch of (vs - 1) vs doubles), and 192 doubles after V for the scaled
 // points.  All G lanes of the cell call it.
 template <int G>
-__device__ void square_block(int Wp, const double *s, const double *mm, double *D, double *V, int vs)
+__device__ void square_block(int Wp, const ldsd *s, const ldsd *mm, ldsd *D, ldsd *V, int vs)
 {
     const int lane = Lanes<G>::lane();
     const int r = __popcll(Lanes<G>::ballot(lane < Wp && s[lane] <= kSquareMax));  // sorted ascending
@@ -242,7 +257,7 @@ __device__ void square_block(int Wp, const double *s, const double *mm, double *
     const double smax = s[r - 1];
     int j = 0;
     while (j < 10 && ldexp(1.0, j) < smax) ++j;
-    double *ss = V + (size_t)(vs - 1) * vs, *ee = ss + G, *ms = ee + G;
+    ldsd *ss = V + (size_t)(vs - 1) * vs, *ee = ss + G, *ms = ee + G;
     if (lane < r) {
         ss[lane] = ldexp(s[lane], -j);
         ee[lane] = exp(-ss[lane]);
@@ -255,7 +270,7 @@ __device__ void square_block(int Wp, const double *s, const double *mm, double *
     }
     wave_sync();
     const int nent = r * (r + 1) / 2;  // entries [a][b], b < r: the first nent of the table
-    double *src = D, *dst = V;
+    ldsd *src = D, *dst = V;
     for (int it = 0; it < j; ++it) {
         for (int t = lane; t < nent; t += G) {
             int b = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -267,7 +282,7 @@ __device__ void square_block(int Wp, const double *s, const double *mm, double *
             dst[t] = acc;
         }
         wave_sync();
-        double *tmp = src;
+        ldsd *tmp = src;
         src = dst;
         dst = tmp;
     }
@@ -295,9 +310,9 @@ __device__ void square_block(int Wp, const double *s, const double *mm, double *
 // terms, so a term's relative error is at most the largest of its entries'
 // plus the recurrence's own rounding.
 template <bool ERR, int G>
-__device__ __forceinline__ double chain_rows(int Wp, double x, const double *s, const double *mm, const double *Nb,
-                                             const int *cid, const int *pos, const double *ls, const double *lNb,
-                                             const double *D, const float *Et, double *V, int vs, double &err)
+__device__ __forceinline__ double chain_rows(int Wp, double x, const ldsd *s, const ldsd *mm, const ldsd *Nb,
+                                             const ldsi *cid, const ldsi *pos, const ldsd *ls, const ldsd *lNb,
+                                             const ldsd *D, const ldsf *Et, ldsd *V, int vs, double &err)
 {
     const int lane = Lanes<G>::lane();
     double acc = 0.0;
@@ -308,13 +323,17 @@ __device__ __forceinline__ double chain_rows(int Wp, double x, const double *s, 
         double Rp = 1.0;  // prod_{k=i}^{j-1} min(x_k, 1)
         double lb = 0.0;  // log of prod_{k=i}^{j-1} x_k / (j-i)!, which bounds T[j][i] (g <= 1/n!)
         int A = pos[j], B = A;
-        for (int i = j; i >= 0; --i) {
+        // d = j - i counts the steps down from the row: the same on every
+        // lane still in the loop, so the factorial table is read with a
+        // uniform index
+        for (int d = 0; d <= j; ++d) {
+            const int i = j - d;
             const int pi = pos[i];
-            if (i < j) {
+            if (d > 0) {
                 const double xi = s[pi];
                 Rp *= fmin(xi, 1.0);
                 if (Rp == 0.0) break;  // every lower source reaches row j through a zero rate
-                lb += ls[pi] - kLogFact.v[j - i] + kLogFact.v[j - i - 1];  // log x_i - log (j-i)
+                lb += ls[pi] - kLogFact.v[d] + kLogFact.v[d - 1];  // log x_i - log (j-i)
             }
             A = min(A, pi);
             B = max(B, pi);
@@ -363,10 +382,10 @@ __device__ __forceinline__ double chain_rows(int Wp, double x, const double *s, 
 // of the cell call it together.  V: per-lane columns of the hole
 // recurrence, entry t of lane k at V[t vs + k] (vs >= Wp, t <= Wp - 2).
 template <bool POSTERIOR, int G = 64>
-__device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, double *mm, double *Nb, int *cid,
-                            int *pos, double *D, double *V, int vs)
+__device__ double chain_sub(int Wp, double x, double Nk, ldsd *s, ldsd *e, ldsd *mm, ldsd *Nb, ldsi *cid, ldsi *pos,
+                            ldsd *D, ldsd *V, int vs)
 {
-    double *ls = (double *)(pos + G);  // log of the sorted rates
+    ldsd *ls = (ldsd *)(pos + G);  // log of the sorted rates
     const int lane = Lanes<G>::lane();
     // rank of x_k among the window's rates (ties by chain index)
     int rank = 0;
@@ -387,7 +406,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
     // scaled Newton table of the sorted rates: the series for every entry
     // within kWideClusterSpread (one pass per row), then one order per step,
     // Newton where the spread reaches the order's threshold
-    float *Et = (float *)(V + (size_t)(vs - 1) * vs + 3 * G);  // relative error bounds of the entries
+    ldsf *Et = (ldsf *)(V + (size_t)(vs - 1) * vs + 3 * G);  // relative error bounds of the entries
     if (lane < Wp) {
         D[tri(lane, lane)] = e[lane];
         if constexpr (POSTERIOR) Et[tri(lane, lane)] = (float)(4.0 * kWideUlp);
@@ -448,7 +467,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, double *s, double *e, d
     if (suspect && !POSTERIOR) square_block<G>(Wp, s, mm, D, V, vs);
     // log |N_i| once per source, in the squaring's scratch after the columns
     // (rewritten after a squaring, which uses that scratch)
-    double *lNb = V + (size_t)(vs - 1) * vs;
+    ldsd *lNb = V + (size_t)(vs - 1) * vs;
     if (lane <= Wp) lNb[lane] = Nk != 0.0 ? log(fabs(Nk)) : -INFINITY;
     wave_sync();
     double err;
