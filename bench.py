@@ -895,7 +895,7 @@ def window_study_3d(ak, mesh, eps, steps, widths=(2, 3, 4), every=10, half_width
             f"n_e error {ga['max_rel_err_ne']:.2e}; strong-start cells max |dN| "
             f"{sa['max_abs_dN'] if sa else float('nan'):.2e}; mean width {r['mean_width']:.2f} (max {a['wmax']}); "
             f"{r['us_per_step']:.0f} us/step against {res['full_chain_us_per_step']:.0f} for the full chain; "
-            f"{r['wide_tier_cells_per_step']:.0f} cells/step on the wavefront tier")
+            f"{r['wide_tier_cells_per_step']:.0f} cells/step on the wide tiers")
     jg = res["largest_charge_gain_in_one_step"]["gradual"]
     log(f"[study3d] largest charge gain of the full chain in one step (gradual-onset cells): median "
         f"{jg['median']:.2f}, max {jg['max']:.2f} levels")
