@@ -487,18 +487,19 @@ __device__ void adaptive_cell(const StepArgs &a, const AdaptArgs &ad, int64_t c,
     }
 }
 
-// LDS doubles of one cell of G lanes, windows up to W rates: chain_sub's
-// region and the leak test's logs (2 G).
-template <int G>
-constexpr size_t adaptive_cell_doubles(int W)
-{
-    return wide_cell_doubles<G>(W, false) + 2 * (size_t)G;
-}
+// LDS doubles of one cell on a wavefront, windows up to W rates: chain_sub's
+// region and the leak test's logs (2 x 64).
+constexpr size_t adaptive_wave_doubles(int W) { return wide_cell_doubles<64>(W, false) + 128; }
 
-// Cells of the list, four per wavefront (16 lanes each); windows that need
-// 16 or more slots go on to list_wave.
+// Cells of the list, four per wavefront (16 lanes each): windows of up to
+// kGroupW rates (slots 0..15); the others go on to list_wave.
 constexpr int kGroupLanes = 16;
 constexpr int kGroupsPerWave = 64 / kGroupLanes;
+constexpr int kGroupW = kGroupLanes - 1;  // widest window of a group, also its column stride
+// LDS doubles of one group's cell: chain_sub's region for kGroupW rates; the
+// leak test's scratch lies in its columns, which are used only after it
+// (LDS bounds how many of these wavefronts a CU holds)
+constexpr size_t kGroupCellDoubles = wide_cell_doubles<kGroupLanes>(kGroupW, false);
 
 template <class R>
 __global__ __launch_bounds__(kWideBlock) void adaptive_group_kernel(StepArgs a, AdaptArgs ad,
@@ -513,18 +514,18 @@ __global__ __launch_bounds__(kWideBlock) void adaptive_group_kernel(StepArgs a, 
     constexpr int G = kGroupLanes;
     extern __shared__ __align__(16) double wl[];
     const int grp = threadIdx.x / G;
-    double *base = wl + (size_t)grp * adaptive_cell_doubles<G>(G);
+    double *base = wl + (size_t)grp * kGroupCellDoubles;
     int *cid = (int *)(base + 4 * G);
     int *pos = cid + G;
     double *D = base + 6 * G;
-    double *V = D + G * (G + 1) / 2;
-    double *lx = base + wide_cell_doubles<G>(G, false);
-    double *lN = lx + G;
+    double *V = D + kGroupW * (kGroupW + 1) / 2;
+    double *lx = V;  // the leak test's rates and populations, before the solve uses V
+    double *lN = V + G;
     const uint32_t count = hdr->count;
     for (uint32_t i = blockIdx.x * kGroupsPerWave + grp; i < count; i += gridDim.x * kGroupsPerWave) {
         const int64_t c = list[i];
         adaptive_cell<R, G>(a, ad, c, E, pops, lo, wc, n, base, base + G, base + 2 * G, base + 3 * G, cid, pos, D,
-                            V, G, lx, lN, hdr, list_wave, counters);
+                            V, kGroupW, lx, lN, hdr, list_wave, counters);
     }
 }
 
@@ -586,7 +587,7 @@ hipError_t launch_adaptive(const adk_gas *g, const void *E, int64_t n, double dt
     // groups of 16 lanes over the list: the resident workgroups (one
     // wavefront each, LDS bound)
     {
-        const size_t gdyn = sizeof(double) * kGroupsPerWave * adaptive_cell_doubles<kGroupLanes>(kGroupLanes);
+        const size_t gdyn = sizeof(double) * kGroupsPerWave * kGroupCellDoubles;
         static int gper_cu = 0;
         if (gper_cu <= 0) {
             int b = 0;
@@ -604,7 +605,7 @@ hipError_t launch_adaptive(const adk_gas *g, const void *E, int64_t n, double dt
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const size_t dyn = sizeof(double) * adaptive_cell_doubles<64>(ad.wmax);
+    const size_t dyn = sizeof(double) * adaptive_wave_doubles(ad.wmax);
     static int per_cu[ADK_MAX_WIDE_W + 1] = {};  // occupancy per widest window (LDS grows with it)
     int b = per_cu[ad.wmax];
     if (b <= 0) {
