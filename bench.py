@@ -1211,7 +1211,8 @@ def measure_ceilings(ak):
         t = best_ms(lambda: ak.ceiling_valu(kind, iters, out))
         assert bool(torch.all(out == 8)), key
         res[key] = per * iters * lanes / (t * 1e-3) / 1e12
-    res["method"] = ("HBM: best of the library's 16-byte streaming copy and the runtime's device-to-device copy "
+    res["method"] = ("HBM: best of the library's 16-byte copy (one 4 KiB block per workgroup, in address order) "
+                     "and the runtime's device-to-device copy "
                      "over 1, 2 and 4 GiB; cache: the library's copy of 32 MiB x 50 passes; VALU: "
                      "8 dependent chains per lane of fma(x, 1, 0) or exp2(fma(x, 0, 0)) on every wavefront slot; "
                      "best of 3 launches")

@@ -374,9 +374,10 @@ int adk_field_hash(void *E, int64_t n, uint64_t seed, int64_t step, double E_lo,
 /* Hardware ceilings for the measurement harness (not part of the method).
  * adk_ceiling_copy: reps passes of a 16-byte-per-lane streaming copy of
  * `bytes` bytes from src to dst (device buffers, not overlapping; bytes a
- * multiple of 16).  One pass over a large buffer measures the HBM bandwidth,
- * several passes over a buffer that fits the 256 MB Infinity Cache its
- * bandwidth; bytes moved = 2 x bytes x reps.
+ * multiple of 16).  One pass (one 4 KiB block per workgroup, in address
+ * order) over a large buffer measures the HBM bandwidth, several passes (a
+ * grid-stride loop of resident workgroups) over a buffer that fits the
+ * 256 MB Infinity Cache its bandwidth; bytes moved = 2 x bytes x reps.
  * adk_ceiling_valu: nlanes lanes (a multiple of 256) each run 8 independent
  * chains of `iters` steps: kind 0 x <- fma(x, 1, 0) in float, kind 1 the
  * same in double, kind 2 x <- exp2(fma(x, 0, 0)) in float; out[nlanes] (float

@@ -35,6 +35,19 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const uint4 *__restrict__ 
     }
 }
 
+// One pass of dst[i] = src[i], one 16-byte access per lane: workgroup b
+// copies the 4 KiB block b, so the workgroups in flight stream through one
+// region of memory in address order.  On the MI355X this measured 6.2 TB/s
+// (read + write, 1 GiB) where the grid-stride loop above measured 4.0-4.5
+// at 4-32 workgroups per CU (5.4-5.6 with a contiguous 16 KiB block per
+// workgroup and pass): the HBM ceiling takes this form.
+__global__ __launch_bounds__(kBlock) void copy_block_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                            int64_t n16, int64_t first)
+{
+    const int64_t i = first + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n16) dst[i] = src[i];
+}
+
 constexpr int kChains = 8;  // independent dependency chains per lane
 
 // Every lane runs kChains chains of `iters` steps x <- fma(x, a, b) (T float
@@ -72,6 +85,17 @@ int adk_ceiling_copy(void *dst, const void *src, int64_t bytes, int64_t reps, hi
     const int64_t n16 = bytes / 16;
     if (n16 == 0) return ADK_OK;
     const int64_t need = (n16 + adk::kBlock - 1) / adk::kBlock;
+    if (reps == 1) {
+        // one block per workgroup, launches of at most 2^30 workgroups
+        const int64_t maxg = (int64_t)1 << 30;
+        for (int64_t g0 = 0; g0 < need; g0 += maxg) {
+            const int64_t g = need - g0 < maxg ? need - g0 : maxg;
+            hipLaunchKernelGGL(adk::copy_block_kernel, dim3((unsigned)g), dim3(adk::kBlock), 0, stream,
+                               (const uint4 *)src, (uint4 *)dst, n16, g0 * adk::kBlock);
+            if (hipGetLastError() != hipSuccess) return ADK_EDEVICE;
+        }
+        return ADK_OK;
+    }
     const int64_t cap = (int64_t)adk::num_cus() * 8;
     const int grid = (int)(need < cap ? need : cap);
     hipLaunchKernelGGL(adk::copy_kernel, dim3(grid), dim3(adk::kBlock), 0, stream, (const uint4 *)src, (uint4 *)dst,
