@@ -1,8 +1,10 @@
-// Wide windows: one wavefront per cell (shared by the wide ionize_step path
-// and the adaptive window's wide tier).
+// Wide windows: one cell per wavefront, or per aligned group of 16 lanes
+// (shared by the wide ionize_step path, adk_chain_advance and the adaptive
+// window's wide tiers).
 //
 // A window this wide does not fit the per-lane register tables of the
-// narrow path, so the 64 lanes of a wavefront share one cell.  The step is
+// narrow path, so the lanes of a wavefront (or of a 16-lane group, for
+// windows of up to 15 rates) share one cell.  The step is
 // the same (shift at the start, rates of Eq. (1) frozen over dt, exact
 // solution of the chain, Sec. 3); the transition entries
 //     T[j][i] = (x_i ... x_{j-1}) g(x_i, ..., x_j)
@@ -28,12 +30,12 @@
 //     what the rows leave (conservation).
 // All arithmetic is double; populations are stored in the precision's type.
 //
-// LDS bounds how many of these latency-bound wavefronts a CU holds, so it
-// goes to the cells only: each wavefront (one per workgroup) has its region
-// (sorted rates, the triangular table, and the per-lane columns of the hole
-// recurrence, W - 1 entries for each of the W lanes that use them), and the
-// rate coefficients and the log2 table, read once per cell, come from the
-// gas's device table through the caches instead of being staged.
+// LDS bounds how many of these latency-bound cells a CU holds, so it goes to
+// the cells only: each cell has its region (sorted rates, the triangular
+// table, and the per-lane columns of the hole recurrence, W - 1 entries for
+// each of the W lanes that use them), and the rate coefficients and the log2
+// table, read once per cell, come from the gas's device table through the
+// caches instead of being staged.
 #pragma once
 #include "kernels.hpp"
 
