@@ -273,13 +273,13 @@ __device__ __forceinline__ f32x4 mlp_logits(const MlpRegs &r, const float *sf, c
 // SIMDs of a CU, bounds the pass).  Lane (g, n) holds the units its tiles
 // use: b2 and b3 for units 16 t + 4 g + i, the layer-1 weights for units
 // hid(c, g, i).
-// What a pass keeps in registers: 2 all of them, 1 the layer-1 weights and
-// b4 (b2 and b3 from LDS), 0 none.  Measured on the 3D pulse (one group per
+// What a pass keeps in registers: 2 all of them, 1 the layer-1 weights (the
+// biases from LDS), 0 none.  Measured on the 3D pulse (one group per
 // pass, three wavefronts per SIMD): 1 is 3 % faster than 0; 2 needs two
 // wavefronts per SIMD or spills, and is 5-10 % slower.
 constexpr int kBiasRegs = 1;
 struct MlpBias {
-    f32x4 b2[kBiasRegs >= 2 ? 4 : 1], b3[kBiasRegs >= 2 ? 4 : 1], w[2][2], b4;
+    f32x4 b2[kBiasRegs >= 2 ? 4 : 1], b3[kBiasRegs >= 2 ? 4 : 1], w[2][2];
 };
 
 __device__ __forceinline__ void load_bias(MlpBias &b, const MlpShared &s, int lane)
@@ -298,7 +298,6 @@ __device__ __forceinline__ void load_bias(MlpBias &b, const MlpShared &s, int la
             b.w[c][0] = *(const f32x4 *)(s.wu + hid(c, g, 0));
             b.w[c][1] = *(const f32x4 *)(s.wu + hid(c, g, 4));
         }
-        b.b4 = *(const f32x4 *)s.b4;
     }
 }
 
@@ -309,12 +308,16 @@ __device__ __forceinline__ void load_bias(MlpBias &b, const MlpShared &s, int la
 // (qo, n) keep them in z, the other lanes keep what z held.  After four
 // groups with qo = 0..3, lane (g, n) holds the logits of sample n of group g
 // and one softmax serves 64 samples.
-__device__ __forceinline__ void mlp_logits_into(const MlpRegs &r, const MlpBias &bs, const float *sf,
-                                                const float *crow, float u, int qo, f32x4 &z)
+//
+// b23 points at MlpShared::b2 + 4 g (this lane's units of b2; b3 follows kH
+// floats later) and b4 at MlpShared::b4: callers derive both from offsets
+// they pass through an empty asm statement on every pass, so that these
+// reads stay inside their loop, cost no address arithmetic, and do not hold
+// registers for the whole kernel.
+__device__ __forceinline__ void mlp_logits_into(const MlpRegs &r, const MlpBias &bs, const float *b23,
+                                                const float *b4, const float *crow, float u, int qo, f32x4 &z)
 {
     const int g = (threadIdx.x & 63) >> 4;
-    // sf: MlpShared::b2 (followed by b3, b4, wu), for what is not in bs
-    const float *sb2 = sf, *sb3 = sf + kH, *sb4 = sf + 2 * kH, *swu = sb4 + 16;
     bf16x8 h[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -323,6 +326,8 @@ __device__ __forceinline__ void mlp_logits_into(const MlpRegs &r, const MlpBias 
             w0 = bs.w[c][0];
             w1 = bs.w[c][1];
         } else {
+            // MlpShared::wu follows b4 (16 floats after b3)
+            const float *swu = b23 - 4 * g + 2 * kH + 16;
             w0 = lds4(swu + hid(c, g, 0));
             w1 = lds4(swu + hid(c, g, 4));
         }
@@ -337,7 +342,7 @@ __device__ __forceinline__ void mlp_logits_into(const MlpRegs &r, const MlpBias 
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         if constexpr (kBiasRegs >= 2) acc[t] = bs.b2[t];
-        else acc[t] = lds4(sb2 + 16 * t + 4 * g);
+        else acc[t] = lds4(b23 + 16 * t);
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A2[t][c], h[c], acc[t], 0, 0, 0);
     }
@@ -346,13 +351,13 @@ __device__ __forceinline__ void mlp_logits_into(const MlpRegs &r, const MlpBias 
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         if constexpr (kBiasRegs >= 2) acc[t] = bs.b3[t];
-        else acc[t] = lds4(sb3 + 16 * t + 4 * g);
+        else acc[t] = lds4(b23 + kH + 16 * t);
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A3[t][c], h[c], acc[t], 0, 0, 0);
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) h[c] = relu_pack(acc[2 * c], acc[2 * c + 1]);
-    f32x4 zq = lds4(sb4);
+    f32x4 zq = lds4(b4);
 #pragma unroll
     for (int c = 0; c < 2; ++c) zq = __builtin_amdgcn_mfma_f32_16x16x32_bf16(r.A4[c], h[c], zq, 0, 0, 0);
     if (g == qo) z = zq;

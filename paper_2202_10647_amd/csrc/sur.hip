@@ -48,7 +48,10 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
 {
     __shared__ double sc[kDevTableLen];
     __shared__ MlpShared ms;
-    __shared__ float sthr[ADK_MAX_Z];
+    // thresholds of levels 0..Z-1, then infinite ones up to level Z + W - 1
+    // (a window's slots past the last level need no clamp)
+    static_assert(W <= 4, "threshold padding");
+    __shared__ float sthr[ADK_MAX_Z + 4];
     __shared__ float scut[ADK_MAX_Z + 1];
     __shared__ unsigned next_chunk;
     extern __shared__ __align__(16) unsigned char dyn[];
@@ -59,13 +62,12 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
     // slots, and no other group touches them
     f32x4 *slot = (f32x4 *)(dyn + (size_t)Z * kCtabStride * sizeof(float)) + (threadIdx.x >> 6) * 64 * W;
     if (threadIdx.x == 0) next_chunk = 0u;  // visible after staging
-    for (int t = threadIdx.x; t < Z; t += blockDim.x) sthr[t] = a.thr[t];
+    for (int t = threadIdx.x; t < Z + W; t += blockDim.x) sthr[t] = t < Z ? a.thr[t] : INFINITY;
     for (int t = threadIdx.x; t <= ADK_MAX_Z; t += blockDim.x) scut[t] = a.cut.e[t];  // visible after staging
     stage_coefficients(sc, a.st.tab, a.st.ln_dt);
     stage_mlp(ms, ctab, a.prm, a.L, a.v, true);
     const double *slog = sc + kCoefRows * kCoefStride;
     const bool has_poly = a.st.has_poly != 0;
-    const unsigned long long below = (1ull << lane) - 1ull;  // lanes under this one
     unsigned long long n_fb = 0, n_eval = 0;
 
     // Workgroup b owns the chunk indices [b per, (b + 1) per) (scattered over
@@ -191,32 +193,54 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
             // 1e-9, |E| below its threshold) keeps its population (identity
             // column) without an evaluation
             const float u = fmaf(__log2f(fabsf(Ef)), a.au, a.bu);
+            const float Eabs = fabsf(Ef);
+            const float *lthr = sthr + p;  // p <= Z
+            const int rowb = __mul24(p, (int)(kCtabStride * sizeof(float)));  // byte offset of level p's layer-1 row
             int cnt = 0;
             int pos[W];
             bool need[W];
 #pragma unroll
             for (int s = 0; s < W; ++s) {
-                const int k = p + s;
-                need[s] = use_mlp && s < top && !(EL < (double)sthr[k < Z ? k : Z - 1]);
+                // every lane reads its threshold (thresholds are 0, positive
+                // or infinite) and a lane with no pair in slot s tests -1
+                // against it, so that one compare gives the mask and the
+                // ballot takes it as it is
+                const float thr = lthr[s];
+                const float x = (use_mlp & (s < top)) ? Eabs : -1.0f;
+                need[s] = !(x < thr);
                 const unsigned long long m = __ballot(need[s]);
-                pos[s] = cnt + __popcll(m & below);
-                if (need[s]) slot[pos[s]] = (f32x4){u, __int_as_float(k), 0.0f, 0.0f};
+                pos[s] = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                // the pair: u and the byte offset of level k's layer-1 row
+                if (need[s])
+                    slot[pos[s]] = (f32x4){u, __int_as_float(rowb + s * (int)(kCtabStride * sizeof(float))), 0.0f, 0.0f};
                 cnt += __popcll(m);
             }
+            // the list is padded to whole passes with a pair that evaluates
+            // harmlessly (u = 0, level 0), so that every lane of a pass reads
+            // its own slot; the padding's columns are not stored
+            // (a pass reads u and the row offset, the slot's first two words)
+            const int cpad = (cnt + 15) & ~15;
+            if (lane < cpad - cnt) *(uint2 *)(slot + cnt + lane) = make_uint2(0u, 0u);
             wave_lds_sync();
             if (cnt > 0) {
                 // 16 pairs per pass; four passes in a row add their logits
                 // into one tile (pass j's samples land in lane group j & 3),
-                // which then takes one softmax for 64 pairs.  Lanes past the
-                // count repeat the pass's first pair; slots of a block are
-                // read by its passes before the block's columns overwrite them
+                // which then takes one softmax for 64 pairs.  Slots of a
+                // block are read by its passes before the block's columns
+                // overwrite them
                 f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                const f32x4 *mine = slot + (lane & 15);
+                // byte offsets of this lane's b2 units and of b4, renewed
+                // (as far as the compiler knows) on every pass
+                int ob = (int)(4 * sizeof(float)) * (lane >> 4), oz = 0;
                 for (int g0 = 0; g0 < cnt; g0 += 16) {
-                    const float *sf = ms.b2 + opaque_zero();  // biases read per pass, not held
+                    asm volatile("" : "+v"(ob), "+v"(oz));
                     const int qo = (g0 >> 4) & 3;
-                    const int t = g0 + (lane & 15);
-                    const f32x4 cq = slot[t < cnt ? t : g0];
-                    mlp_logits_into(r, bs, sf, ctab + __float_as_int(cq.y) * kCtabStride, cq.x, qo, z);
+                    const f32x4 cq = mine[g0];
+                    mlp_logits_into(r, bs, (const float *)((const char *)ms.b2 + ob),
+                                    (const float *)((const char *)ms.b4 + oz),
+                                    (const float *)((const char *)ctab + __float_as_int(cq.y)), cq.x, qo, z);
                     if (qo == 3 || g0 + 16 >= cnt) {
                         float zm, lse;
                         const f32x4 Q = softmax4(z, zm, lse);
