@@ -102,7 +102,9 @@ __device__ inline void stage_mlp(MlpShared &s, float *ctab, const float *__restr
         s.wu[t] = prm[L.W1u + t];
         s.wv[t] = prm[L.W1v + t];
     }
-    for (int t = threadIdx.x; t < 16; t += blockDim.x) s.b4[t] = t < kBand ? prm[L.b4 + t] : 0.0f;
+    // b4 once per group of four floats: lane group g of a pass reads b4 + 4 g
+    static_assert(16 % kBand == 0, "b4 copies");
+    for (int t = threadIdx.x; t < 16; t += blockDim.x) s.b4[t] = prm[L.b4 + t % kBand];
     for (int t = threadIdx.x; t < L.Z * kH; t += blockDim.x) {
         const int k = t / kH, h = t % kH;
         float acc = prm[L.b1 + h];
@@ -310,10 +312,10 @@ __device__ __forceinline__ void load_bias(MlpBias &b, const MlpShared &s, int la
 // and one softmax serves 64 samples.
 //
 // b23 points at MlpShared::b2 + 4 g (this lane's units of b2; b3 follows kH
-// floats later) and b4 at MlpShared::b4: callers derive both from offsets
-// they pass through an empty asm statement on every pass, so that these
-// reads stay inside their loop, cost no address arithmetic, and do not hold
-// registers for the whole kernel.
+// floats later) and b4 at MlpShared::b4 + 4 g (this lane group's copy):
+// callers derive both from one offset that they pass through an empty asm
+// statement on every pass, so that these reads stay inside their loop, cost
+// no address arithmetic, and do not hold registers for the whole kernel.
 __device__ __forceinline__ void mlp_logits_into(const MlpRegs &r, const MlpBias &bs, const float *b23,
                                                 const float *b4, const float *crow, float u, int qo, f32x4 &z)
 {

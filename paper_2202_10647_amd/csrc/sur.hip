@@ -231,15 +231,18 @@ __global__ __launch_bounds__(kSurBlock, 3) void surrogate_kernel(SurArgs a, cons
                 // overwrite them
                 f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
                 const f32x4 *mine = slot + (lane & 15);
-                // byte offsets of this lane's b2 units and of b4, renewed
-                // (as far as the compiler knows) on every pass
-                int ob = (int)(4 * sizeof(float)) * (lane >> 4), oz = 0;
+                // byte offset of this lane group's b2 units and b4 copy,
+                // renewed (as far as the compiler knows) on every pass
+                int ob = (int)(4 * sizeof(float)) * (lane >> 4);
+                f32x2 cqn = *(const f32x2 *)mine;
                 for (int g0 = 0; g0 < cnt; g0 += 16) {
-                    asm volatile("" : "+v"(ob), "+v"(oz));
+                    asm volatile("" : "+v"(ob));
                     const int qo = (g0 >> 4) & 3;
-                    const f32x4 cq = mine[g0];
+                    const f32x2 cq = cqn;
+                    // the next pass's pair, read during this pass
+                    cqn = *(const f32x2 *)(mine + (g0 + 16 < cnt ? g0 + 16 : g0));
                     mlp_logits_into(r, bs, (const float *)((const char *)ms.b2 + ob),
-                                    (const float *)((const char *)ms.b4 + oz),
+                                    (const float *)((const char *)ms.b4 + ob),
                                     (const float *)((const char *)ctab + __float_as_int(cq.y)), cq.x, qo, z);
                     if (qo == 3 || g0 + 16 >= cnt) {
                         float zm, lse;
