@@ -462,9 +462,10 @@ __device__ double chain_sub(int Wp, double x, double Nk, ldsd *s, ldsd *e, ldsd 
     // by what each term contributes (all rows together, which also bounds the
     // top slot), and the table is squared and the rows taken again only when
     // that bound exceeds kWideTableTol.  POSTERIOR pays off where the entries
-    // with large bounds carry negligible terms (a full chain, most of whose
-    // levels hold almost nothing); where they matter (a window just wide
-    // enough for its populations) it costs one more pass over the rows.
+    // with large bounds carry negligible terms: a full chain, most of whose
+    // levels hold almost nothing, and, as measured, the adaptive window's
+    // cells on the 3D pulse; where such entries matter it costs one more pass
+    // over the rows.
     const bool suspect = Lanes<G>::any(emax > kWideTableTol) || Lanes<G>::any(cancelled);
     if (suspect && !POSTERIOR) square_block<G>(Wp, s, mm, D, V, vs);
     // log |N_i| once per source, in the squaring's scratch after the columns
