@@ -306,6 +306,30 @@ __device__ void square_block(int Wp, const ldsd *s, const ldsd *mm, ldsd *D, lds
     }
 }
 
+// The table entries' relative error bounds as kept in LDS: a float per entry
+// on a wavefront; on a group of fewer lanes the float's upper 16 bits (the
+// bfloat16 grid), rounded up so that a stored bound still bounds, which
+// halves the table and lets a CU hold one more wavefront of such groups.
+template <int G, bool HALF = (G < 64)>
+struct EtStore {
+    using type = ADK_LDS float;
+    static constexpr size_t kBytes = sizeof(float);
+    __device__ static void put(type *p, int i, float v) { p[i] = v; }
+    __device__ static float get(const type *p, int i) { return p[i]; }
+};
+template <int G>
+struct EtStore<G, true> {
+    using type = ADK_LDS unsigned short;
+    static constexpr size_t kBytes = sizeof(unsigned short);
+    // v >= 0 and finite (bounds are clamped to 1e30): adding 0xffff before
+    // the shift moves every value off the grid up to the next grid point
+    __device__ static void put(type *p, int i, float v)
+    {
+        p[i] = (unsigned short)((__float_as_uint(v) + 0xffffu) >> 16);
+    }
+    __device__ static float get(const type *p, int i) { return __uint_as_float((unsigned)p[i] << 16); }
+};
+
 // Row j = lane of the update, N'_j = sum_{i <= j} T[j][i] N_i (lanes below
 // Wp), and in err a bound on its absolute rounding error from the table
 // entries' relative bounds Et: the hole recurrence combines non-negative
@@ -314,7 +338,8 @@ __device__ void square_block(int Wp, const ldsd *s, const ldsd *mm, ldsd *D, lds
 template <bool ERR, int G>
 __device__ __forceinline__ double chain_rows(int Wp, double x, const ldsd *s, const ldsd *mm, const ldsd *Nb,
                                              const ldsi *cid, const ldsi *pos, const ldsd *ls, const ldsd *lNb,
-                                             const ldsd *D, const ldsf *Et, ldsd *V, int vs, double &err)
+                                             const ldsd *D, const typename EtStore<G>::type *Et, ldsd *V,
+                                             int vs, double &err)
 {
     const int lane = Lanes<G>::lane();
     double acc = 0.0;
@@ -347,11 +372,11 @@ __device__ __forceinline__ double chain_rows(int Wp, double x, const ldsd *s, co
             double gS, eG = 0.0;
             if (holes == 0) {
                 gS = D[tri(A, B)];
-                if constexpr (ERR) eG = (double)Et[tri(A, B)];
+                if constexpr (ERR) eG = (double)EtStore<G>::get(Et, tri(A, B));
             } else {
                 for (int t = 0; t <= holes; ++t) {
                     V[t * vs + lane] = D[tri(A + t, B)];
-                    if constexpr (ERR) eG = fmax(eG, (double)Et[tri(A + t, B)]);
+                    if constexpr (ERR) eG = fmax(eG, (double)EtStore<G>::get(Et, tri(A + t, B)));
                 }
                 if constexpr (ERR) eG += (double)((holes + 1) * (holes + 2)) * kWideUlp;
                 int cnt = holes;
@@ -408,10 +433,14 @@ __device__ double chain_sub(int Wp, double x, double Nk, ldsd *s, ldsd *e, ldsd 
     // scaled Newton table of the sorted rates: the series for every entry
     // within kWideClusterSpread (one pass per row), then one order per step,
     // Newton where the spread reaches the order's threshold
-    ldsf *Et = (ldsf *)(V + (size_t)(vs - 1) * vs + 3 * G);  // relative error bounds of the entries
+    // relative error bounds of the entries: over the squaring's scaled points
+    // after their first G doubles (log |N_i| while the rows are taken); they
+    // are read only by the rows taken before any squaring
+    using Ets = EtStore<G>;
+    typename Ets::type *Et = (typename Ets::type *)(V + (size_t)(vs - 1) * vs + G);
     if (lane < Wp) {
         D[tri(lane, lane)] = e[lane];
-        if constexpr (POSTERIOR) Et[tri(lane, lane)] = (float)(4.0 * kWideUlp);
+        if constexpr (POSTERIOR) Ets::put(Et, tri(lane, lane), (float)(4.0 * kWideUlp));
         int nmax = 0;
         while (lane + nmax + 1 < Wp && s[lane + nmax + 1] - s[lane] < kWideClusterSpread) ++nmax;
         if (nmax > 0) taylor_row(s, e, mm, D, lane, nmax, V, lane, vs);
@@ -440,7 +469,7 @@ __device__ double chain_sub(int Wp, double x, double Nk, ldsd *s, ldsd *e, ldsd 
             }
             // (0/0 of two vanishing entries gives NaN: the entry is 0 and so
             // is its error; an exact cancellation of nonzero terms is flagged)
-            if constexpr (POSTERIOR) Et[tri(lo_, hi)] = ecur == ecur ? (float)fmin(ecur, 1e30) : 0.0f;
+            if constexpr (POSTERIOR) Ets::put(Et, tri(lo_, hi), ecur == ecur ? (float)fmin(ecur, 1e30) : 0.0f);
             emax = fmax(emax, ecur);  // (NaN ignored, as above)
         }
         eprev = ecur;
@@ -496,13 +525,16 @@ __device__ double chain_sub(int Wp, double x, double Nk, ldsd *s, ldsd *e, ldsd 
 // Doubles of one cell's LDS region for width W and G lanes: s, e, mm, Nb,
 // cid and pos, log rates (6 G), the triangular table, the per-lane columns
 // ((W - 1) W >= 2 (W + 1), which also holds the scratch of the reach test
-// and of the squaring), the scaled points of the squaring (3 G), and, for
-// chain_sub<true>, the entries' error bounds (float, triangular).
+// and of the squaring), then the squaring's scaled points (3 G; the first G
+// hold log |N_i| while the rows are taken), and, for chain_sub<true>, the
+// entries' error bounds (EtStore, triangular) over the last 2 G of those
+// points and past them as far as they need.
 template <int G = 64>
 constexpr size_t wide_cell_doubles(int W, bool bounds)
 {
-    return 9 * (size_t)G + (size_t)W * (W + 1) / 2 + (size_t)(W - 1) * W +
-           (bounds ? ((size_t)W * (W + 1) / 2 + 1) / 2 : 0);
+    const size_t tri = (size_t)W * (W + 1) / 2, cols = (size_t)(W - 1) * W;
+    const size_t et = (tri * EtStore<G>::kBytes + sizeof(double) - 1) / sizeof(double);
+    return 7 * (size_t)G + tri + cols + (bounds && et > 2 * (size_t)G ? et : 2 * (size_t)G);
 }
 constexpr size_t wide_wave_doubles(int W, bool bounds) { return wide_cell_doubles<64>(W, bounds); }
 
